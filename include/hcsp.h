@@ -1,0 +1,249 @@
+/*
+ * hcsp — clustered Gustavson SpGEMM on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libhcsp.so.  Plain pointers and sizes only; no C++ exceptions
+ * cross this boundary.  Every entry point returns an int status: HCSP_OK (0)
+ * or a negative HCSP_E_* code; hcsp_last_error() then holds a one-line
+ * description (thread-local).
+ *
+ * Problem (paper, Background "SpGEMM Kernel" and Fig. 1): C = A x B with all
+ * three matrices sparse.  A may be given as plain CSR or in the paper's
+ * row-clustered CSR_Cluster format (Sec. "Access Pattern and Matrix
+ * Format"); B is CSR; C is always CSR in A's original row order.  The
+ * product runs in the two phases the paper describes: a symbolic phase that
+ * counts the non-zeros of every output row so C can be allocated, then a
+ * numeric phase that fills C.
+ *
+ * Conventions
+ *  - Matrices: int64 row offsets, int32 column indices strictly increasing
+ *    within a row, float64 values.  nrows/ncols/nnz < 2^31 for column and
+ *    row ids; offsets are 64-bit.
+ *  - Suffix _d: device pointer (memory the caller allocated on the GPU, e.g.
+ *    a torch tensor).  Suffix _h: host pointer.  Pointers inside hcsp_csr /
+ *    hcsp_csr_cluster are device pointers unless an entry point says "host".
+ *  - The library never allocates device memory.  Callers query workspace
+ *    sizes, allocate, and pass buffers in.  Host-side plans allocate only
+ *    host memory.
+ *  - Everything runs on the given stream (hipStream_t passed as void*, NULL
+ *    = the default stream).  Only calls documented as synchronizing wait
+ *    for the stream.
+ *  - Kernels never write outside the caller's buffers: output writes are
+ *    bounds-checked against the capacities passed in; a violation is
+ *    reported as HCSP_E_CAPACITY where the call synchronizes.
+ *  - Arithmetic contract: each output value c_ij starts at +0.0 and takes
+ *    its contributions a_ik * b_kj in ascending k, each with one fused
+ *    multiply-add (the accumulation order the CPU reference uses); entries
+ *    whose value cancels to 0.0 are kept, so the structure of C is the
+ *    boolean product.  Output columns are sorted ascending.
+ */
+#ifndef HCSP_H
+#define HCSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+enum {
+    HCSP_OK = 0,
+    HCSP_E_INVALID = -1,     /* bad argument: null pointer, negative size, mismatched shapes */
+    HCSP_E_PTR = -2,         /* row offsets not starting at 0, not monotone or not ending at nnz */
+    HCSP_E_RANGE = -3,       /* a column index outside [0, ncols) */
+    HCSP_E_UNSORTED = -4,    /* column indices not strictly increasing within a row */
+    HCSP_E_CAPACITY = -5,    /* a workspace or output buffer is too small */
+    HCSP_E_HIP = -6,         /* the HIP runtime reported an error */
+    HCSP_E_NOMEM = -7,       /* host memory allocation failed */
+    HCSP_E_UNSUPPORTED = -8, /* shape or option outside what the library implements */
+    HCSP_E_OVERFLOW = -9     /* a count does not fit its index type */
+};
+
+/* ------------------------------------------------------------------ types */
+
+/* CSR matrix (paper, Background "Sparse Matrix Storage Formats": row-id,
+ * col-id and value arrays).  row_ptr[nrows+1], col[nnz], val[nnz]. */
+typedef struct hcsp_csr {
+    int64_t nrows, ncols, nnz;
+    int64_t *row_ptr;
+    int32_t *col;
+    double *val;
+} hcsp_csr;
+
+/*
+ * CSR_Cluster (paper, "Access Pattern and Matrix Format" and its figure):
+ * rows grouped into clusters whose non-zeros are stored together column by
+ * column.  Variable-length form: cluster sizes are kept as offsets, so row
+ * ids are implicit, plus an array of pointers into the value array.
+ *   cl_row_ptr[nclusters+1]  cluster c holds positions cl_row_ptr[c] .. cl_row_ptr[c+1)-1
+ *   perm[nrows]              position -> original row id of A
+ *   cl_col_ptr[nclusters+1]  cluster c's union columns are cl_col[cl_col_ptr[c] ..)
+ *   cl_col[ncc]              sorted union of the member rows' columns
+ *   cl_mask[ncc]             bit l set iff member l stores that column (the
+ *                            placeholder positions of the paper have bit 0)
+ *   cl_val_ptr[nclusters+1]  cluster c's values start at cl_val[cl_val_ptr[c]]
+ *   cl_val[nslots]           column-major per cluster: value of member l at union
+ *                            column t is cl_val[cl_val_ptr[c] + t*s + l], +0.0 for
+ *                            placeholders (s = cluster size)
+ * Clusters hold 1..16 rows (the mask is 16 bits).  max_cluster is the
+ * largest cluster size present.
+ */
+typedef struct hcsp_csr_cluster {
+    int64_t nrows, ncols, nclusters, ncc, nslots;
+    int32_t max_cluster;
+    int32_t reserved;
+    int64_t *cl_row_ptr;
+    int32_t *perm;
+    int64_t *cl_col_ptr;
+    int32_t *cl_col;
+    uint16_t *cl_mask;
+    int64_t *cl_val_ptr;
+    double *cl_val;
+} hcsp_csr_cluster;
+
+enum { HCSP_OP_CSR = 0, HCSP_OP_CLUSTER = 1 };
+
+/* The left operand A: plain CSR (kind HCSP_OP_CSR, field csr) or CSR_Cluster
+ * (kind HCSP_OP_CLUSTER, field cl). */
+typedef struct hcsp_operand {
+    int32_t kind;
+    int32_t reserved;
+    hcsp_csr csr;
+    hcsp_csr_cluster cl;
+} hcsp_operand;
+
+/* Exact rational threshold num/den (den > 0), so similarity comparisons are
+ * done in integers. */
+typedef struct hcsp_ratio {
+    int32_t num, den;
+} hcsp_ratio;
+
+/* Product options.  Zero-initialised means: defaults, whole matrix. */
+enum {
+    HCSP_F_SYNC_CHECK = 1   /* numeric: synchronize and report out-of-range writes as HCSP_E_CAPACITY */
+};
+typedef struct hcsp_opts {
+    int32_t lanes;          /* lanes per row/cluster group: 0 = automatic, else 8, 16, 32 or 64 */
+    int32_t flags;          /* HCSP_F_* */
+    int64_t unit_lo;        /* numeric: first unit (row of a CSR A, cluster of a CSR_Cluster A) */
+    int64_t unit_hi;        /* numeric: one past the last unit; <= 0 means all units */
+    int64_t out_base;       /* numeric: C_col_d/C_val_d point at global entry out_base of C */
+    int32_t dense_slots;    /* concurrent dense accumulators for very long rows: 0 = default (64) */
+    int32_t load_pct;       /* numeric hash-table fill target in percent: 0 = default (60) */
+    int32_t sym_tmax_log2;  /* largest shared-memory symbolic table, log2 slots: 0 = default */
+    int32_t num_tmax;       /* largest shared-memory numeric table, slots: 0 = default */
+} hcsp_opts;
+
+#define HCSP_MAX_BINS 96
+
+/* What the symbolic phase learned, handed to the numeric phase. */
+typedef struct hcsp_sym_info {
+    int64_t nnz;                       /* nnz(C) */
+    int64_t units;                     /* rows (CSR A) or clusters (CSR_Cluster A) */
+    int64_t sym_bin_count[HCSP_MAX_BINS];
+    int64_t num_bin_count[HCSP_MAX_BINS];
+    int32_t lanes;                     /* lanes per group actually used */
+    int32_t valid;                     /* set to 1 by hcsp_spgemm_symbolic */
+} hcsp_sym_info;
+
+/* -------------------------------------------------------------- library */
+
+const char *hcsp_version(void);
+const char *hcsp_strerror(int status);
+/* Detail of the last error on this host thread ("" if none). */
+const char *hcsp_last_error(void);
+
+/*
+ * Validate a device CSR matrix: row_ptr[0] == 0, non-decreasing,
+ * row_ptr[nrows] == nnz (else HCSP_E_PTR); every column in [0, ncols)
+ * (else HCSP_E_RANGE); strictly increasing within each row (else
+ * HCSP_E_UNSORTED).  ws_d: >= 64 bytes of device scratch.  Synchronizes.
+ */
+int hcsp_csr_check(const hcsp_csr *A, void *ws_d, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------- cluster plans
+ * Plans run on HOST copies of A (every pointer in A_h is a host pointer; val
+ * may be NULL).  They work on A's rows in the order perm_in_h gives
+ * (position p holds original row perm_in_h[p]; NULL = identity) and report
+ * clusters as consecutive position ranges: cluster c holds original rows
+ * perm_out_h[cl_row_ptr_h[c] .. cl_row_ptr_h[c+1]).  perm_out_h has nrows
+ * entries and cl_row_ptr_h nrows+1; *ncl receives the cluster count.
+ * max_cluster is 1..16.
+ */
+
+/* Fixed-length clusters (paper, "Fixed-length Clusters"): consecutive blocks
+ * of K rows; the last block holds the remainder. */
+int hcsp_plan_fixed(int64_t nrows, int32_t K, const int32_t *perm_in_h,
+                    int32_t *perm_out_h, int64_t *cl_row_ptr_h, int64_t *ncl);
+
+/* Variable-length clusters (paper, Alg. 2): a row joins the open cluster
+ * while its Jaccard similarity to the cluster's first row is >= jacc_th and
+ * the cluster has fewer than max_cluster rows. */
+int hcsp_plan_variable(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_cluster,
+                       const int32_t *perm_in_h, int32_t *perm_out_h, int64_t *cl_row_ptr_h,
+                       int64_t *ncl);
+
+enum { HCSP_SIM_ROOT = 0, HCSP_SIM_UNION = 1 };
+/*
+ * Hierarchical clusters (paper, Alg. 3): candidate pairs from
+ * SpGEMM_TopK(A, A^T) with topk = max_cluster-1 and similarity strictly above
+ * jacc_th; a max-heap of candidates and a union-find forest; two roots merge
+ * while the merged size stays within max_cluster; a popped non-root pair is
+ * lifted to its roots and re-scored (HCSP_SIM_ROOT: the root rows' patterns;
+ * HCSP_SIM_UNION: the union of each cluster's rows).  Clusters are ordered by
+ * smallest member position, members ascending.  nthreads host threads
+ * compute the candidate pairs (<= 0: all available).
+ */
+int hcsp_plan_hierarchical(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_cluster,
+                           uint32_t sim_flags, int32_t nthreads, const int32_t *perm_in_h,
+                           int32_t *perm_out_h, int64_t *cl_row_ptr_h, int64_t *ncl);
+
+/* ------------------------------------------------------ CSR_Cluster build
+ * Device construction of the CSR_Cluster form of A (paper, the
+ * A_CSR_CLUSTER(A_CSR, clusters) step of Alg. 2 and Alg. 3).
+ * Step 1, hcsp_cluster_count: given perm_d[nrows] and cl_row_ptr_d[ncl+1]
+ * (a plan copied to the device), writes cl_col_ptr_d[ncl+1] and
+ * cl_val_ptr_d[ncl+1] and returns the sizes ncc, nslots and the largest
+ * cluster size on the host.  Synchronizes.  ws_d needs
+ * hcsp_cluster_workspace() bytes.
+ * Step 2, hcsp_cluster_fill: with out->cl_col/cl_mask/cl_val allocated to
+ * those sizes and the other out fields set (the pointer arrays from step 1),
+ * fills the union columns, masks and values.  Asynchronous.
+ */
+int hcsp_cluster_workspace(int64_t nrows, int64_t ncl, size_t *bytes);
+int hcsp_cluster_count(const hcsp_csr *A, const int32_t *perm_d, const int64_t *cl_row_ptr_d,
+                       int64_t ncl, int64_t *cl_col_ptr_d, int64_t *cl_val_ptr_d,
+                       int64_t *ncc_h, int64_t *nslots_h, int32_t *max_cluster_h,
+                       void *ws_d, size_t ws_bytes, void *stream);
+int hcsp_cluster_fill(const hcsp_csr *A, const hcsp_csr_cluster *out, void *stream);
+
+/* ---------------------------------------------------------------- SpGEMM
+ * hcsp_spgemm_workspace: device workspace bytes for C = A x B.  Host only.
+ *
+ * hcsp_spgemm_symbolic: the symbolic phase (paper, "SpGEMM Kernel").
+ * Writes C_row_ptr_d[A.nrows+1] (offsets of C in A's original row order) and
+ * fills *info (host).  Synchronizes twice (after binning and to read nnz).
+ *
+ * hcsp_spgemm_numeric: the numeric phase.  C_col_d/C_val_d hold `capacity`
+ * entries starting at global entry opts->out_base, so a caller can compute
+ * C in panels of units (opts->unit_lo/unit_hi).  `info` must come from the
+ * hcsp_spgemm_symbolic call on the same A, B, opts and workspace, and the
+ * workspace must not have been touched since.  Asynchronous unless
+ * HCSP_F_SYNC_CHECK is set.
+ */
+int hcsp_spgemm_workspace(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
+                          size_t *bytes);
+int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
+                         int64_t *C_row_ptr_d, hcsp_sym_info *info, void *ws_d, size_t ws_bytes,
+                         void *stream);
+int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
+                        const hcsp_sym_info *info, const int64_t *C_row_ptr_d, int32_t *C_col_d,
+                        double *C_val_d, int64_t capacity, void *ws_d, size_t ws_bytes,
+                        void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HCSP_H */

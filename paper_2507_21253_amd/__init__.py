@@ -1,0 +1,400 @@
+"""hcsp — clustered Gustavson SpGEMM for AMD Instinct MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``libhcsp.so`` (declared in
+``include/hcsp.h``).  The functions below carry the C names without the
+``hcsp_`` prefix and only marshal arguments: torch tensors supply device
+memory and the current HIP stream, numpy arrays supply host memory for the
+cluster plans.  Every step of the product runs in the library's own kernels;
+there is no Python or CPU fallback, and a missing library raises.
+
+Paper: "Improving SpGEMM Performance Through Matrix Reordering and
+Cluster-wise Computation" (arXiv 2507.21253): row-wise Gustavson SpGEMM over
+CSR and over the row-clustered CSR_Cluster format (Alg. 1), with clusters
+from fixed-length, variable-length (Alg. 2) or hierarchical (Alg. 3)
+clustering.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhcsp.so")
+
+HCSP_OK = 0
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_PTR", -3: "E_RANGE", -4: "E_UNSORTED", -5: "E_CAPACITY",
+          -6: "E_HIP", -7: "E_NOMEM", -8: "E_UNSUPPORTED", -9: "E_OVERFLOW"}
+OP_CSR, OP_CLUSTER = 0, 1
+SIM_ROOT, SIM_UNION = 0, 1
+F_SYNC_CHECK = 1
+MAX_BINS = 96
+
+i64, i32, u32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p
+
+
+class c_csr(ctypes.Structure):
+    _fields_ = [("nrows", i64), ("ncols", i64), ("nnz", i64), ("row_ptr", vp), ("col", vp), ("val", vp)]
+
+
+class c_csr_cluster(ctypes.Structure):
+    _fields_ = [("nrows", i64), ("ncols", i64), ("nclusters", i64), ("ncc", i64), ("nslots", i64),
+                ("max_cluster", i32), ("reserved", i32), ("cl_row_ptr", vp), ("perm", vp), ("cl_col_ptr", vp),
+                ("cl_col", vp), ("cl_mask", vp), ("cl_val_ptr", vp), ("cl_val", vp)]
+
+
+class c_operand(ctypes.Structure):
+    _fields_ = [("kind", i32), ("reserved", i32), ("csr", c_csr), ("cl", c_csr_cluster)]
+
+
+class c_ratio(ctypes.Structure):
+    _fields_ = [("num", i32), ("den", i32)]
+
+
+class c_opts(ctypes.Structure):
+    _fields_ = [("lanes", i32), ("flags", i32), ("unit_lo", i64), ("unit_hi", i64), ("out_base", i64),
+                ("dense_slots", i32), ("load_pct", i32), ("sym_tmax_log2", i32), ("num_tmax", i32)]
+
+
+class c_sym_info(ctypes.Structure):
+    _fields_ = [("nnz", i64), ("units", i64), ("sym_bin_count", i64 * MAX_BINS),
+                ("num_bin_count", i64 * MAX_BINS), ("lanes", i32), ("valid", i32)]
+
+
+# every symbol include/hcsp.h declares, with its ctypes signature
+_SIGS = {
+    "hcsp_version": ([], ctypes.c_char_p),
+    "hcsp_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "hcsp_last_error": ([], ctypes.c_char_p),
+    "hcsp_csr_check": ([ctypes.POINTER(c_csr), vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_plan_fixed": ([i64, i32, vp, vp, vp, ctypes.POINTER(i64)], ctypes.c_int),
+    "hcsp_plan_variable": ([ctypes.POINTER(c_csr), c_ratio, i32, vp, vp, vp, ctypes.POINTER(i64)], ctypes.c_int),
+    "hcsp_plan_hierarchical": ([ctypes.POINTER(c_csr), c_ratio, i32, u32, i32, vp, vp, vp, ctypes.POINTER(i64)],
+                               ctypes.c_int),
+    "hcsp_cluster_workspace": ([i64, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hcsp_cluster_count": ([ctypes.POINTER(c_csr), vp, vp, i64, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                            ctypes.POINTER(i32), vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_cluster_fill": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr_cluster), vp], ctypes.c_int),
+    "hcsp_spgemm_workspace": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
+                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hcsp_spgemm_symbolic": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts), vp,
+                              ctypes.POINTER(c_sym_info), vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_spgemm_numeric": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
+                             ctypes.POINTER(c_sym_info), vp, vp, vp, i64, vp, ctypes.c_size_t, vp], ctypes.c_int),
+}
+
+_lib = None
+
+
+class HcspError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__("%s: %s (%s)" % (where, STATUS.get(status, status), detail))
+        self.status = status
+
+
+def lib():
+    """The loaded ``libhcsp.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhcsp.so is not built (run __graft_entry__.build() or "
+                               "python paper_2507_21253_amd/build.py); there is no fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != HCSP_OK:
+        raise HcspError(rc, where, lib().hcsp_last_error().decode())
+
+
+def _np(a):
+    return None if a is None else a.ctypes.data_as(vp)
+
+
+def _ratio(t) -> c_ratio:
+    if isinstance(t, tuple):
+        return c_ratio(int(t[0]), int(t[1]))      # passed as given; the library validates it
+    f = Fraction(t).limit_denominator(1 << 20)
+    return c_ratio(f.numerator, f.denominator)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return vp(s.cuda_stream)
+
+
+def _tp(t):
+    return None if t is None else vp(t.data_ptr())
+
+
+# ------------------------------------------------------------------ matrices
+
+@dataclass
+class DeviceCSR:
+    """CSR matrix in device memory (torch tensors): row_ptr int64, col int32, val float64."""
+
+    row_ptr: "object"
+    col: "object"
+    val: "object"
+    nrows: int
+    ncols: int
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_host(H, device="cuda"):
+        import torch
+        return DeviceCSR(torch.from_numpy(np.ascontiguousarray(H.rp)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(H.col)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(H.val)).to(device), H.nrows, H.ncols)
+
+    def to_host(self):
+        from types import SimpleNamespace
+        return SimpleNamespace(rp=self.row_ptr.cpu().numpy(), col=self.col.cpu().numpy(),
+                               val=self.val.cpu().numpy(), nrows=self.nrows, ncols=self.ncols)
+
+    def c(self) -> c_csr:
+        return c_csr(self.nrows, self.ncols, self.nnz, _tp(self.row_ptr), _tp(self.col), _tp(self.val))
+
+
+@dataclass
+class DeviceCluster:
+    """CSR_Cluster in device memory (see include/hcsp.h for the layout)."""
+
+    nrows: int
+    ncols: int
+    nclusters: int
+    ncc: int
+    nslots: int
+    max_cluster: int
+    cl_row_ptr: "object"
+    perm: "object"
+    cl_col_ptr: "object"
+    cl_col: "object"
+    cl_mask: "object"
+    cl_val_ptr: "object"
+    cl_val: "object"
+
+    def c(self) -> c_csr_cluster:
+        return c_csr_cluster(self.nrows, self.ncols, self.nclusters, self.ncc, self.nslots, self.max_cluster, 0,
+                             _tp(self.cl_row_ptr), _tp(self.perm), _tp(self.cl_col_ptr), _tp(self.cl_col),
+                             _tp(self.cl_mask), _tp(self.cl_val_ptr), _tp(self.cl_val))
+
+    def bytes(self) -> int:
+        return 8 * 3 * (self.nclusters + 1) + 4 * self.nrows + 6 * self.ncc + 8 * self.nslots
+
+
+def operand(A) -> c_operand:
+    op = c_operand()
+    if isinstance(A, DeviceCluster):
+        op.kind = OP_CLUSTER
+        op.cl = A.c()
+    else:
+        op.kind = OP_CSR
+        op.csr = A.c()
+    return op
+
+
+def opts(**kw) -> c_opts:
+    o = c_opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+# ------------------------------------------------------------------ C-ABI mirrors
+
+def version() -> str:
+    return lib().hcsp_version().decode()
+
+
+def strerror(status: int) -> str:
+    return lib().hcsp_strerror(status).decode()
+
+
+def last_error() -> str:
+    return lib().hcsp_last_error().decode()
+
+
+def csr_check(A: DeviceCSR, ws=None, stream=None) -> int:
+    """Validate a device CSR matrix; returns the status code (0 = valid)."""
+    import torch
+    if ws is None:
+        ws = torch.empty(64, dtype=torch.uint8, device=A.row_ptr.device)
+    m = A.c()
+    return lib().hcsp_csr_check(ctypes.byref(m), _tp(ws), ws.numel(), _stream(stream))
+
+
+def _host_csr(H) -> c_csr:
+    rp = np.ascontiguousarray(H.rp, np.int64)
+    col = np.ascontiguousarray(H.col, np.int32)
+    H._keep = (rp, col)
+    return c_csr(H.nrows, H.ncols, int(rp[-1]) if len(rp) else 0, _np(rp), _np(col), None)
+
+
+@dataclass
+class Plan:
+    """Cluster plan: cluster c holds original rows perm[cl_row_ptr[c]:cl_row_ptr[c+1]]."""
+
+    perm: np.ndarray
+    cl_row_ptr: np.ndarray
+
+    @property
+    def nclusters(self) -> int:
+        return len(self.cl_row_ptr) - 1
+
+
+def plan_fixed(nrows: int, K: int, perm_in=None) -> Plan:
+    pi = None if perm_in is None else np.ascontiguousarray(perm_in, np.int32)
+    perm = np.empty(max(nrows, 1), np.int32)
+    crp = np.empty(nrows + 1, np.int64)
+    ncl = i64()
+    _check(lib().hcsp_plan_fixed(nrows, K, _np(pi), _np(perm), _np(crp), ctypes.byref(ncl)), "plan_fixed")
+    return Plan(perm[:nrows], crp[:ncl.value + 1].copy())
+
+
+def plan_variable(A_host, jacc_th=(3, 10), max_cluster: int = 8, perm_in=None) -> Plan:
+    m = _host_csr(A_host)
+    pi = None if perm_in is None else np.ascontiguousarray(perm_in, np.int32)
+    perm = np.empty(max(A_host.nrows, 1), np.int32)
+    crp = np.empty(A_host.nrows + 1, np.int64)
+    ncl = i64()
+    _check(lib().hcsp_plan_variable(ctypes.byref(m), _ratio(jacc_th), max_cluster, _np(pi), _np(perm), _np(crp),
+                                    ctypes.byref(ncl)), "plan_variable")
+    return Plan(perm[:A_host.nrows], crp[:ncl.value + 1].copy())
+
+
+def plan_hierarchical(A_host, jacc_th=(3, 10), max_cluster: int = 8, sim=SIM_ROOT, nthreads: int = 0,
+                      perm_in=None) -> Plan:
+    m = _host_csr(A_host)
+    pi = None if perm_in is None else np.ascontiguousarray(perm_in, np.int32)
+    perm = np.empty(max(A_host.nrows, 1), np.int32)
+    crp = np.empty(A_host.nrows + 1, np.int64)
+    ncl = i64()
+    _check(lib().hcsp_plan_hierarchical(ctypes.byref(m), _ratio(jacc_th), max_cluster, sim, nthreads, _np(pi),
+                                        _np(perm), _np(crp), ctypes.byref(ncl)), "plan_hierarchical")
+    return Plan(perm[:A_host.nrows], crp[:ncl.value + 1].copy())
+
+
+def cluster_workspace(nrows: int, ncl: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().hcsp_cluster_workspace(nrows, ncl, ctypes.byref(b)), "cluster_workspace")
+    return b.value
+
+
+def cluster_count(A: DeviceCSR, perm_d, cl_row_ptr_d, ws, stream=None):
+    """Returns (cl_col_ptr, cl_val_ptr, ncc, nslots, max_cluster)."""
+    import torch
+    ncl = cl_row_ptr_d.numel() - 1
+    ccp = torch.empty(ncl + 1, dtype=torch.int64, device=cl_row_ptr_d.device)
+    cvp = torch.empty(ncl + 1, dtype=torch.int64, device=cl_row_ptr_d.device)
+    ncc, nslots, mx = i64(), i64(), i32()
+    m = A.c()
+    _check(lib().hcsp_cluster_count(ctypes.byref(m), _tp(perm_d), _tp(cl_row_ptr_d), ncl, _tp(ccp), _tp(cvp),
+                                    ctypes.byref(ncc), ctypes.byref(nslots), ctypes.byref(mx), _tp(ws), ws.numel(),
+                                    _stream(stream)), "cluster_count")
+    return ccp, cvp, ncc.value, nslots.value, mx.value
+
+
+def cluster_fill(A: DeviceCSR, out: DeviceCluster, stream=None):
+    m = A.c()
+    o = out.c()
+    _check(lib().hcsp_cluster_fill(ctypes.byref(m), ctypes.byref(o), _stream(stream)), "cluster_fill")
+
+
+def cluster_build(A: DeviceCSR, plan: Plan, stream=None) -> DeviceCluster:
+    """CSR_Cluster of A on the device for a host plan (count, allocate, fill)."""
+    import torch
+    dev = A.row_ptr.device
+    perm_d = torch.from_numpy(np.ascontiguousarray(plan.perm, np.int32)).to(dev)
+    crp_d = torch.from_numpy(np.ascontiguousarray(plan.cl_row_ptr, np.int64)).to(dev)
+    ws = torch.empty(cluster_workspace(A.nrows, plan.nclusters), dtype=torch.uint8, device=dev)
+    ccp, cvp, ncc, nslots, mx = cluster_count(A, perm_d, crp_d, ws, stream)
+    out = DeviceCluster(A.nrows, A.ncols, plan.nclusters, ncc, nslots, mx, crp_d, perm_d, ccp,
+                        torch.empty(ncc, dtype=torch.int32, device=dev),
+                        torch.empty(ncc, dtype=torch.int16, device=dev),
+                        cvp, torch.empty(nslots, dtype=torch.float64, device=dev))
+    cluster_fill(A, out, stream)
+    return out
+
+
+def spgemm_workspace(A, B: DeviceCSR, o: c_opts | None = None) -> int:
+    op = operand(A)
+    b = B.c()
+    o = o or c_opts()
+    n = ctypes.c_size_t()
+    _check(lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b), ctypes.byref(o), ctypes.byref(n)),
+           "spgemm_workspace")
+    return n.value
+
+
+def spgemm_symbolic(A, B: DeviceCSR, C_row_ptr, ws, o: c_opts | None = None, stream=None) -> c_sym_info:
+    op = operand(A)
+    b = B.c()
+    o = o or c_opts()
+    info = c_sym_info()
+    _check(lib().hcsp_spgemm_symbolic(ctypes.byref(op), ctypes.byref(b), ctypes.byref(o), _tp(C_row_ptr),
+                                      ctypes.byref(info), _tp(ws), ws.numel(), _stream(stream)), "spgemm_symbolic")
+    return info
+
+
+def spgemm_numeric(A, B: DeviceCSR, info: c_sym_info, C_row_ptr, C_col, C_val, ws, o: c_opts | None = None,
+                   capacity: int | None = None, stream=None):
+    op = operand(A)
+    b = B.c()
+    o = o or c_opts()
+    cap = C_col.numel() if capacity is None else capacity
+    _check(lib().hcsp_spgemm_numeric(ctypes.byref(op), ctypes.byref(b), ctypes.byref(o), ctypes.byref(info),
+                                     _tp(C_row_ptr), _tp(C_col), _tp(C_val), cap, _tp(ws), ws.numel(),
+                                     _stream(stream)), "spgemm_numeric")
+
+
+class Product:
+    """Workspace and output buffers for repeated C = A x B with one structure (the paper's use case of
+    many SpGEMMs on the same operands).  ``run()`` does symbolic, the nnz read-back, and numeric."""
+
+    def __init__(self, A, B: DeviceCSR, o: c_opts | None = None):
+        import torch
+        self.A, self.B = A, B
+        self.o = o or c_opts()
+        dev = B.row_ptr.device
+        self.ws = torch.empty(spgemm_workspace(A, B, self.o), dtype=torch.uint8, device=dev)
+        self.C_row_ptr = torch.empty(A.nrows + 1, dtype=torch.int64, device=dev)
+        self.C_col = torch.empty(0, dtype=torch.int32, device=dev)
+        self.C_val = torch.empty(0, dtype=torch.float64, device=dev)
+        self.info = None
+
+    def symbolic(self, stream=None):
+        import torch
+        self.info = spgemm_symbolic(self.A, self.B, self.C_row_ptr, self.ws, self.o, stream)
+        nnz = self.info.nnz
+        if self.C_col.numel() < nnz:
+            self.C_col = torch.empty(nnz, dtype=torch.int32, device=self.ws.device)
+            self.C_val = torch.empty(nnz, dtype=torch.float64, device=self.ws.device)
+        return nnz
+
+    def numeric(self, stream=None):
+        spgemm_numeric(self.A, self.B, self.info, self.C_row_ptr, self.C_col, self.C_val, self.ws, self.o,
+                       capacity=self.info.nnz, stream=stream)
+
+    def run(self, stream=None) -> DeviceCSR:
+        nnz = self.symbolic(stream)
+        self.numeric(stream)
+        return DeviceCSR(self.C_row_ptr, self.C_col[:nnz], self.C_val[:nnz], self.A.nrows, self.B.ncols)
+
+
+def spgemm(A, B: DeviceCSR, o: c_opts | None = None, stream=None) -> DeviceCSR:
+    """C = A x B (A: DeviceCSR or DeviceCluster) with C in A's original row order."""
+    return Product(A, B, o).run(stream)

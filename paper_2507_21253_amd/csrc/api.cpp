@@ -1,0 +1,516 @@
+// C ABI of libhcsp: argument checks, workspace layout, bin dispatch and the
+// two-phase SpGEMM orchestration (symbolic, then numeric) on one HIP stream.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace hcsp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, char *base, Workspace *ws)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        off = align_up(off, 256);
+        void *p = base ? (void *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t nu = (size_t)std::max<int64_t>(nunits, 1);
+    ws->probes = (int64_t *)take(8 * nu);
+    ws->keylo = (int32_t *)take(4 * nu);
+    ws->keyhi = (int32_t *)take(4 * nu);
+    ws->ucount = (int32_t *)take(4 * nu);
+    ws->bin = (uint8_t *)take(nu);
+    ws->order_sym = (int32_t *)take(4 * nu);
+    ws->order_num = (int32_t *)take(4 * nu);
+    ws->sym_count = (int64_t *)take(8 * HCSP_MAX_BINS);
+    ws->num_count = (int64_t *)take(8 * HCSP_MAX_BINS);
+    ws->cursor = (int64_t *)take(8 * HCSP_MAX_BINS);
+    ws->err = (uint32_t *)take(256);
+    ws->scan_tmp = (int64_t *)take(8 * scan_tmp_elems(std::max(nrows, nunits) + 1));
+    ws->dense_words = (std::max<int64_t>(ncols, 1) + 31) / 32;
+    ws->dense_slots = dense_slots;
+    ws->dense_bits = (uint32_t *)take(4 * (size_t)ws->dense_words * dense_slots);
+    ws->dense_vals = (double *)take(8 * (size_t)std::max<int64_t>(ncols, 1) * dense_slots);
+    ws->bytes = align_up(off, 256);
+    return ws->bytes;
+}
+
+// Shared memory per workgroup the bins may plan for (queried once per device).
+static int64_t lds_limit()
+{
+    static std::mutex mu;
+    static int64_t cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        cache[dev] = std::min<int64_t>(v, 160 * 1024);
+    }
+    return cache[dev];
+}
+
+static int floor_log2(int64_t x)
+{
+    int l = 0;
+    while (((int64_t)2 << l) <= x) ++l;
+    return l;
+}
+
+static int pow2_at_least(int64_t x)
+{
+    int v = 1;
+    while (v < x && v < 64) v <<= 1;
+    return v;
+}
+
+static int make_tune(const hcsp_opts *o, const hcsp_csr *B, bool need_device, Tune *t)
+{
+    hcsp_opts z;
+    std::memset(&z, 0, sizeof z);
+    if (!o) o = &z;
+    if (o->lanes) {
+        if (o->lanes != 8 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64)
+            return fail(HCSP_E_INVALID, "opts.lanes must be 0, 8, 16, 32 or 64");
+        t->G = o->lanes;
+    } else {
+        const int64_t avg = B->nrows > 0 ? (B->nnz + B->nrows - 1) / B->nrows : 1;
+        t->G = std::min(64, std::max(16, pow2_at_least(avg)));
+    }
+    t->load_pct = o->load_pct ? o->load_pct : 60;
+    if (t->load_pct < 10 || t->load_pct > 95) return fail(HCSP_E_INVALID, "opts.load_pct must be in 10..95");
+    t->lds_budget = need_device ? lds_limit() : 64 * 1024;
+    int sym = std::min(kSymLog2Max, floor_log2(t->lds_budget / 4));
+    if (o->sym_tmax_log2) sym = std::max(kSymLog2Min + 1, std::min(sym, (int)o->sym_tmax_log2));
+    t->sym_tmax_log2 = sym;
+    t->num_tmax = o->num_tmax ? o->num_tmax : (1 << 30);
+    t->dense_slots = o->dense_slots ? o->dense_slots : 32;
+    if (t->dense_slots < 4) t->dense_slots = 4;
+    t->dense_slots &= ~3;
+    // keep the dense accumulators within 16 GiB
+    const int64_t per_slot = 8 * std::max<int64_t>(B->ncols, 1) + 4 * ((B->ncols + 31) / 32);
+    while (t->dense_slots > 4 && (int64_t)t->dense_slots * per_slot > (16ll << 30)) t->dense_slots -= 4;
+    return HCSP_OK;
+}
+
+static void num_tmax_classes(const Tune &tu, bool cl, int out[kSClasses])
+{
+    for (int sc = 0; sc < kSClasses; ++sc) {
+        int best = 0;
+        for (int t = 0; t < kNumT; ++t) {
+            const int T = num_table(t);
+            if (T <= tu.num_tmax && num_group_bytes(cl, sc, T, tu.G) <= tu.lds_budget) best = T;
+        }
+        out[sc] = best;
+    }
+}
+
+static int check_csr_shape(const hcsp_csr *M, const char *name, bool need_val)
+{
+    if (!M) return fail(HCSP_E_INVALID, std::string(name) + " is null");
+    if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0)
+        return fail(HCSP_E_INVALID, std::string(name) + ": negative size");
+    if (M->nrows >= INT32_MAX || M->ncols >= INT32_MAX)
+        return fail(HCSP_E_OVERFLOW, std::string(name) + ": row/column ids must fit int32");
+    if (!M->row_ptr || (M->nnz > 0 && (!M->col || (need_val && !M->val))))
+        return fail(HCSP_E_INVALID, std::string(name) + ": null array");
+    return HCSP_OK;
+}
+
+struct OpView {
+    bool cluster;
+    int64_t nrows, ncols, nunits;
+};
+
+static int check_operands(const hcsp_operand *A, const hcsp_csr *B, OpView *v)
+{
+    if (!A || !B) return fail(HCSP_E_INVALID, "null operand");
+    int rc = check_csr_shape(B, "B", true);
+    if (rc) return rc;
+    if (A->kind == HCSP_OP_CSR) {
+        rc = check_csr_shape(&A->csr, "A", true);
+        if (rc) return rc;
+        v->cluster = false;
+        v->nrows = A->csr.nrows;
+        v->ncols = A->csr.ncols;
+        v->nunits = A->csr.nrows;
+    } else if (A->kind == HCSP_OP_CLUSTER) {
+        const hcsp_csr_cluster &c = A->cl;
+        if (c.nrows < 0 || c.nclusters < 0 || c.ncc < 0 || c.nslots < 0)
+            return fail(HCSP_E_INVALID, "A (cluster): negative size");
+        if (c.nrows >= INT32_MAX || c.ncols >= INT32_MAX || c.nclusters >= INT32_MAX)
+            return fail(HCSP_E_OVERFLOW, "A (cluster): ids must fit int32");
+        if (c.max_cluster < 0 || c.max_cluster > 16) return fail(HCSP_E_UNSUPPORTED, "clusters hold at most 16 rows");
+        if (!c.cl_row_ptr || !c.perm && c.nrows > 0 || !c.cl_col_ptr || !c.cl_val_ptr ||
+            (c.ncc > 0 && (!c.cl_col || !c.cl_mask)) || (c.nslots > 0 && !c.cl_val))
+            return fail(HCSP_E_INVALID, "A (cluster): null array");
+        v->cluster = true;
+        v->nrows = c.nrows;
+        v->ncols = c.ncols;
+        v->nunits = c.nclusters;
+    } else {
+        return fail(HCSP_E_INVALID, "unknown operand kind");
+    }
+    if (v->ncols != B->nrows) return fail(HCSP_E_INVALID, "A.ncols != B.nrows");
+    return HCSP_OK;
+}
+
+static SpArgs base_args(const hcsp_operand *A, const hcsp_csr *B, const Workspace &ws, const Tune &tu)
+{
+    SpArgs a;
+    std::memset(&a, 0, sizeof a);
+    if (A->kind == HCSP_OP_CSR) {
+        a.a_rp = A->csr.row_ptr;
+        a.a_col = A->csr.col;
+        a.a_val = A->csr.val;
+    } else {
+        a.cl_row_ptr = A->cl.cl_row_ptr;
+        a.perm = A->cl.perm;
+        a.cl_col_ptr = A->cl.cl_col_ptr;
+        a.cl_col = A->cl.cl_col;
+        a.cl_mask = A->cl.cl_mask;
+        a.cl_val_ptr = A->cl.cl_val_ptr;
+        a.cl_val = A->cl.cl_val;
+    }
+    a.b_rp = B->row_ptr;
+    a.b_col = B->col;
+    a.b_val = B->val;
+    a.keylo = ws.keylo;
+    a.keyhi = ws.keyhi;
+    a.ucount = ws.ucount;
+    a.err = ws.err;
+    a.G = tu.G;
+    a.dense_bits = ws.dense_bits;
+    a.dense_vals = ws.dense_vals;
+    a.dense_words = ws.dense_words;
+    a.ncols = B->ncols;
+    a.unit_lo = 0;
+    a.unit_hi = INT64_MAX;
+    return a;
+}
+
+static BinArgs bin_args(const hcsp_operand *A, const hcsp_csr *B, const Workspace &ws, const Tune &tu,
+                        int64_t nunits, int64_t *c_rp)
+{
+    BinArgs b;
+    std::memset(&b, 0, sizeof b);
+    if (A->kind == HCSP_OP_CSR) {
+        b.a_rp = A->csr.row_ptr;
+        b.a_col = A->csr.col;
+    } else {
+        b.cl_row_ptr = A->cl.cl_row_ptr;
+        b.perm = A->cl.perm;
+        b.cl_col_ptr = A->cl.cl_col_ptr;
+        b.cl_col = A->cl.cl_col;
+    }
+    b.b_rp = B->row_ptr;
+    b.b_col = B->col;
+    b.nunits = nunits;
+    b.ws = ws;
+    b.c_rp = c_rp;
+    b.sym_tmax_log2 = tu.sym_tmax_log2;
+    num_tmax_classes(tu, A->kind == HCSP_OP_CLUSTER, b.num_tmax_by_class);
+    b.load_pct = tu.load_pct;
+    return b;
+}
+
+// Launch geometry for one bin: groups of G lanes, as many per block as the
+// block's shared-memory target allows.
+static void geometry(int64_t group_bytes, int G, int64_t count, int *blocks, int *threads, size_t *lds)
+{
+    const int64_t target = 64 * 1024;
+    int64_t gpb = std::max<int64_t>(1, std::min<int64_t>(256 / G, target / std::max<int64_t>(group_bytes, 1)));
+    *threads = (int)(gpb * G);
+    *lds = (size_t)(gpb * group_bytes);
+    *blocks = (int)((count + gpb - 1) / gpb);
+}
+
+static int ensure_lds(size_t lds, int64_t budget)
+{
+    if ((int64_t)lds > budget) return fail(HCSP_E_UNSUPPORTED, "shared-memory table larger than the device allows");
+    return HCSP_OK;
+}
+
+}  // namespace hcsp
+
+using namespace hcsp;
+
+extern "C" {
+
+const char *hcsp_version(void) { return "hcsp 0.1 (gfx950)"; }
+
+const char *hcsp_strerror(int status)
+{
+    switch (status) {
+    case HCSP_OK: return "ok";
+    case HCSP_E_INVALID: return "invalid argument";
+    case HCSP_E_PTR: return "malformed row offsets";
+    case HCSP_E_RANGE: return "column index out of range";
+    case HCSP_E_UNSORTED: return "columns not strictly increasing within a row";
+    case HCSP_E_CAPACITY: return "buffer too small";
+    case HCSP_E_HIP: return "HIP runtime error";
+    case HCSP_E_NOMEM: return "host out of memory";
+    case HCSP_E_UNSUPPORTED: return "unsupported";
+    case HCSP_E_OVERFLOW: return "index overflow";
+    default: return "unknown status";
+    }
+}
+
+const char *hcsp_last_error(void) { return g_err.c_str(); }
+
+int hcsp_csr_check(const hcsp_csr *A, void *ws_d, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (!A || !A->row_ptr) return fail(HCSP_E_INVALID, "null matrix");
+    if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0) return fail(HCSP_E_INVALID, "negative size");
+    if (A->nnz > 0 && !A->col) return fail(HCSP_E_INVALID, "null column array");
+    if (!ws_d || ws_bytes < 64) return fail(HCSP_E_CAPACITY, "csr_check needs 64 bytes of workspace");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *flags = (uint32_t *)ws_d;
+    HCSP_HIP(launch_fill_u32(flags, 1, 0u, s));
+    HCSP_HIP(launch_csr_check(*A, flags, s));
+    uint32_t h = 0;
+    HCSP_HIP(hipMemcpyAsync(&h, flags, 4, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    if (h & kErrPtr) return fail(HCSP_E_PTR, "row offsets are not a valid CSR offset array");
+    if (h & kErrRange) return fail(HCSP_E_RANGE, "a column index is outside [0, ncols)");
+    if (h & kErrUnsorted) return fail(HCSP_E_UNSORTED, "columns are not strictly increasing within a row");
+    return HCSP_OK;
+}
+
+int hcsp_cluster_workspace(int64_t nrows, int64_t ncl, size_t *bytes)
+{
+    clear_error();
+    if (!bytes || nrows < 0 || ncl < 0) return fail(HCSP_E_INVALID, "bad arguments");
+    *bytes = align_up(8 * scan_tmp_elems(ncl + 1), 256) + 256;
+    return HCSP_OK;
+}
+
+int hcsp_cluster_count(const hcsp_csr *A, const int32_t *perm_d, const int64_t *cl_row_ptr_d, int64_t ncl,
+                       int64_t *cl_col_ptr_d, int64_t *cl_val_ptr_d, int64_t *ncc_h, int64_t *nslots_h,
+                       int32_t *max_cluster_h, void *ws_d, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_csr_shape(A, "A", true);
+    if (rc) return rc;
+    if (ncl < 0 || (ncl > 0 && (!perm_d || !cl_row_ptr_d)) || !cl_col_ptr_d || !cl_val_ptr_d || !ncc_h ||
+        !nslots_h)
+        return fail(HCSP_E_INVALID, "bad arguments");
+    size_t need = 0;
+    hcsp_cluster_workspace(A->nrows, ncl, &need);
+    if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "cluster workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *maxs = (int32_t *)ws_d;
+    int64_t *tmp = (int64_t *)((char *)ws_d + 256);
+    HCSP_HIP(launch_fill_u32((uint32_t *)maxs, 1, 0u, s));
+    HCSP_HIP(launch_fill_i64(cl_col_ptr_d + ncl, 1, 0, s));
+    HCSP_HIP(launch_fill_i64(cl_val_ptr_d + ncl, 1, 0, s));
+    HCSP_HIP(launch_cluster_count(*A, perm_d, cl_row_ptr_d, ncl, cl_col_ptr_d, cl_val_ptr_d, maxs, s));
+    HCSP_HIP(launch_scan_exclusive(cl_col_ptr_d, ncl + 1, tmp, s));
+    HCSP_HIP(launch_scan_exclusive(cl_val_ptr_d, ncl + 1, tmp, s));
+    int32_t mx = 0;
+    HCSP_HIP(hipMemcpyAsync(ncc_h, cl_col_ptr_d + ncl, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipMemcpyAsync(nslots_h, cl_val_ptr_d + ncl, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipMemcpyAsync(&mx, maxs, 4, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    if (mx > 16) return fail(HCSP_E_INVALID, "a cluster of the plan has 0 or more than 16 rows");
+    if (max_cluster_h) *max_cluster_h = mx;
+    return HCSP_OK;
+}
+
+int hcsp_cluster_fill(const hcsp_csr *A, const hcsp_csr_cluster *out, void *stream)
+{
+    clear_error();
+    int rc = check_csr_shape(A, "A", true);
+    if (rc) return rc;
+    if (!out || out->nclusters < 0 || (out->nclusters > 0 && (!out->perm || !out->cl_row_ptr)) ||
+        !out->cl_col_ptr || !out->cl_val_ptr || (out->ncc > 0 && (!out->cl_col || !out->cl_mask)) ||
+        (out->nslots > 0 && !out->cl_val))
+        return fail(HCSP_E_INVALID, "bad CSR_Cluster output");
+    HCSP_HIP(launch_cluster_fill(*A, *out, (hipStream_t)stream));
+    return HCSP_OK;
+}
+
+int hcsp_spgemm_workspace(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, size_t *bytes)
+{
+    clear_error();
+    OpView v;
+    int rc = check_operands(A, B, &v);
+    if (rc) return rc;
+    if (!bytes) return fail(HCSP_E_INVALID, "null bytes");
+    Tune tu;
+    rc = make_tune(opts, B, false, &tu);
+    if (rc) return rc;
+    Workspace ws;
+    *bytes = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, nullptr, &ws);
+    return HCSP_OK;
+}
+
+int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, int64_t *C_row_ptr_d,
+                         hcsp_sym_info *info, void *ws_d, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    OpView v;
+    int rc = check_operands(A, B, &v);
+    if (rc) return rc;
+    if (!C_row_ptr_d || !info) return fail(HCSP_E_INVALID, "null output");
+    Tune tu;
+    rc = make_tune(opts, B, true, &tu);
+    if (rc) return rc;
+    Workspace ws;
+    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, (char *)ws_d, &ws);
+    if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    std::memset(info, 0, sizeof *info);
+
+    HCSP_HIP(launch_fill_i64(ws.sym_count, HCSP_MAX_BINS, 0, s));
+    HCSP_HIP(launch_fill_i64(ws.num_count, HCSP_MAX_BINS, 0, s));
+    HCSP_HIP(launch_fill_i64(ws.cursor, HCSP_MAX_BINS, 0, s));
+    HCSP_HIP(launch_fill_u32(ws.err, 1, 0u, s));
+    HCSP_HIP(launch_fill_i64(C_row_ptr_d + v.nrows, 1, 0, s));
+
+    BinArgs ba = bin_args(A, B, ws, tu, v.nunits, C_row_ptr_d);
+    HCSP_HIP(launch_work(v.cluster, ba, s));
+    HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.sym_count, ws.cursor, kSymBins, ws.order_sym, s));
+    int64_t cnt[HCSP_MAX_BINS];
+    HCSP_HIP(hipMemcpyAsync(cnt, ws.sym_count, 8 * kSymBins, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+
+    SpArgs a = base_args(A, B, ws, tu);
+    a.order = ws.order_sym;
+    a.c_rp = C_row_ptr_d;
+    int64_t start = 0;
+    for (int b = 0; b < kSymBins; ++b) {
+        const int64_t c = cnt[b];
+        info->sym_bin_count[b] = c;
+        if (c > 0 && b != kBinEmpty) {
+            a.bin_begin = start;
+            a.count = c;
+            if (b == kSymGlobal) {
+                const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
+                HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, s));
+                HCSP_HIP(launch_sym_dense(v.cluster, a, waves / 4, s));
+            } else {
+                const int sc = (b - 1) / kSymT;
+                const int l2 = (b - 1) % kSymT + kSymLog2Min;
+                a.T = 1 << l2;
+                a.log2T = l2;
+                const int64_t gb = sym_group_bytes(v.cluster, a.T);
+                a.group_bytes = (int)gb;
+                int blocks, threads;
+                size_t lds;
+                geometry(gb, tu.G, c, &blocks, &threads, &lds);
+                rc = ensure_lds(lds, tu.lds_budget);
+                if (rc) return rc;
+                HCSP_HIP(launch_sym(sc, v.cluster, a, blocks, threads, lds, s));
+            }
+        }
+        start += c;
+    }
+    HCSP_HIP(launch_scan_exclusive(C_row_ptr_d, v.nrows + 1, ws.scan_tmp, s));
+    HCSP_HIP(launch_fill_i64(ws.cursor, HCSP_MAX_BINS, 0, s));
+    HCSP_HIP(launch_numbin(v.cluster, ba, s));
+    HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.num_count, ws.cursor, kNumBins, ws.order_num, s));
+    int64_t ncnt[HCSP_MAX_BINS];
+    int64_t nnz = 0;
+    HCSP_HIP(hipMemcpyAsync(ncnt, ws.num_count, 8 * kNumBins, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipMemcpyAsync(&nnz, C_row_ptr_d + v.nrows, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    info->nnz = nnz;
+    info->units = v.nunits;
+    for (int b = 0; b < kNumBins; ++b) info->num_bin_count[b] = ncnt[b];
+    info->lanes = tu.G;
+    info->valid = 1;
+    return HCSP_OK;
+}
+
+int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, const hcsp_sym_info *info,
+                        const int64_t *C_row_ptr_d, int32_t *C_col_d, double *C_val_d, int64_t capacity, void *ws_d,
+                        size_t ws_bytes, void *stream)
+{
+    clear_error();
+    OpView v;
+    int rc = check_operands(A, B, &v);
+    if (rc) return rc;
+    if (!info || !info->valid || info->units != v.nunits) return fail(HCSP_E_INVALID, "info is not from a matching symbolic call");
+    if (!C_row_ptr_d || capacity < 0 || (capacity > 0 && (!C_col_d || !C_val_d)))
+        return fail(HCSP_E_INVALID, "bad output arrays");
+    Tune tu;
+    rc = make_tune(opts, B, true, &tu);
+    if (rc) return rc;
+    if (tu.G != info->lanes) return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
+    Workspace ws;
+    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, (char *)ws_d, &ws);
+    if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    hcsp_opts z;
+    std::memset(&z, 0, sizeof z);
+    const hcsp_opts *o = opts ? opts : &z;
+
+    HCSP_HIP(launch_fill_u32(ws.err, 1, 0u, s));
+    SpArgs a = base_args(A, B, ws, tu);
+    a.order = ws.order_num;
+    a.c_rp = const_cast<int64_t *>(C_row_ptr_d);
+    a.c_col = C_col_d;
+    a.c_val = C_val_d;
+    a.cap = capacity;
+    a.out_base = o->out_base;
+    a.unit_lo = o->unit_lo;
+    a.unit_hi = o->unit_hi > 0 ? o->unit_hi : INT64_MAX;
+    int64_t start = 0;
+    for (int b = 0; b < kNumBins; ++b) {
+        const int64_t c = info->num_bin_count[b];
+        if (c > 0 && b != kBinEmpty) {
+            a.bin_begin = start;
+            a.count = c;
+            if (b == kNumGlobal) {
+                const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
+                HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, s));
+                HCSP_HIP(launch_num_dense(v.cluster, a, waves / 4, s));
+            } else {
+                const int sc = (b - 1) / kNumT;
+                const int t = (b - 1) % kNumT;
+                a.T = num_table(t);
+                const int64_t gb = num_group_bytes(v.cluster, sc, a.T, tu.G);
+                a.group_bytes = (int)gb;
+                int blocks, threads;
+                size_t lds;
+                geometry(gb, tu.G, c, &blocks, &threads, &lds);
+                rc = ensure_lds(lds, tu.lds_budget);
+                if (rc) return rc;
+                HCSP_HIP(launch_num(sc, v.cluster, a, blocks, threads, lds, s));
+            }
+        }
+        start += c;
+    }
+    if (o->flags & HCSP_F_SYNC_CHECK) {
+        uint32_t e = 0;
+        HCSP_HIP(hipMemcpyAsync(&e, ws.err, 4, hipMemcpyDeviceToHost, s));
+        HCSP_HIP(hipStreamSynchronize(s));
+        if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "output capacity too small for the requested units");
+        if (e & kErrCount) return fail(HCSP_E_INVALID, "row counts differ from the symbolic phase (inputs changed?)");
+    }
+    return HCSP_OK;
+}
+
+}  // extern "C"

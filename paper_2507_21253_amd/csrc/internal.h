@@ -1,0 +1,191 @@
+// Host-side internals of libhcsp: error reporting, bin geometry, workspace
+// layout and the kernel-launch interface between the host runtime and the
+// gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/hcsp.h"
+
+namespace hcsp {
+
+// ------------------------------------------------------------ error reporting
+void set_error(const std::string &msg);
+void clear_error();
+int fail(int code, const std::string &msg);
+
+#define HCSP_HIP(call)                                                                 \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::hcsp::fail(HCSP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------ bin geometry
+// Units (rows of a CSR A, clusters of a CSR_Cluster A) are sorted into bins
+// before each phase.  A bin fixes the cluster-size class (S = 1, 2, 4, 8, 16)
+// and the shared-memory table size, so one launch handles units of one
+// shape.  Bin 0 holds units with no work; the last bin holds units too big
+// for shared memory (the dense global-memory path).
+constexpr int kSClasses = 5;                 // S = 1 << sclass
+constexpr int kSymLog2Min = 6;               // symbolic tables: 64 .. 2^kSymLog2Max slots
+constexpr int kSymLog2Max = 14;
+constexpr int kSymT = kSymLog2Max - kSymLog2Min + 1;
+constexpr int kNumT = 14;                    // numeric table sizes, see kNumTable
+constexpr int kBinEmpty = 0;
+constexpr int kSymBins = 2 + kSClasses * kSymT;   // + empty + global
+constexpr int kNumBins = 2 + kSClasses * kNumT;
+constexpr int kSymGlobal = kSymBins - 1;
+constexpr int kNumGlobal = kNumBins - 1;
+constexpr int kTail = 32;                    // numeric probe tail past the hashed range
+static_assert(kSymBins <= HCSP_MAX_BINS && kNumBins <= HCSP_MAX_BINS, "bin count");
+
+__host__ __device__ inline int num_table(int t)
+{
+    // 64, 96, 128, 192, ... : powers of two and their 3/2 multiples
+    return (t & 1) ? (3 << (5 + (t >> 1))) : (64 << (t >> 1));
+}
+
+__host__ __device__ inline int sclass_of(int s)
+{
+    return s <= 1 ? 0 : s <= 2 ? 1 : s <= 4 ? 2 : s <= 8 ? 3 : 4;
+}
+
+// Shared-memory bytes of one group's tables.
+__host__ __device__ inline int64_t sym_group_bytes(bool cl, int T)
+{
+    return (int64_t)T * (cl ? 8 : 4);                           // key (+ row mask)
+}
+__host__ __device__ inline int64_t num_group_bytes(bool cl, int sclass, int T, int G)
+{
+    const int S = 1 << sclass;
+    const int64_t TX = (int64_t)T + kTail;
+    int64_t b = TX * 4;                                         // keys
+    if (cl) b += TX * 4;                                        // row masks
+    b = (b + 7) & ~7ll;
+    b += TX * 8 * S;                                            // values, one column per member row
+    b += (int64_t)G * S * 8;                                    // the current items' A values
+    b += TX * 2;                                                // sorted slot order
+    return (b + 15) & ~15ll;
+}
+
+// Tuning derived from hcsp_opts.
+struct Tune {
+    int G;               // lanes per group
+    int load_pct;        // numeric table fill target
+    int sym_tmax_log2;   // largest symbolic table
+    int num_tmax;        // largest numeric table
+    int dense_slots;     // concurrent dense accumulators
+    int64_t lds_budget;  // shared memory per workgroup we plan for
+};
+
+// ------------------------------------------------------------ workspace
+struct Workspace {
+    // per unit
+    int64_t *probes;     // sum of |B_k| over the unit's columns
+    int32_t *keylo, *keyhi;
+    int32_t *ucount;     // distinct output columns of the unit (symbolic result)
+    uint8_t *bin;        // current bin of the unit
+    int32_t *order_sym, *order_num;
+    // counters
+    int64_t *sym_count;  // [HCSP_MAX_BINS]
+    int64_t *num_count;
+    int64_t *cursor;     // [HCSP_MAX_BINS] scatter cursors
+    uint32_t *err;       // error flags
+    int64_t *scan_tmp;   // block sums of the scan
+    // dense path
+    uint32_t *dense_bits;
+    double *dense_vals;
+    int64_t dense_words; // 32-bit words per bitmap
+    int dense_slots;
+    size_t bytes;
+};
+
+size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, char *base,
+                        Workspace *ws);
+
+// ------------------------------------------------------------ kernel interface
+struct SpArgs {
+    // A as CSR
+    const int64_t *a_rp;
+    const int32_t *a_col;
+    const double *a_val;
+    // A as CSR_Cluster
+    const int64_t *cl_row_ptr;
+    const int32_t *perm;
+    const int64_t *cl_col_ptr;
+    const int32_t *cl_col;
+    const uint16_t *cl_mask;
+    const int64_t *cl_val_ptr;
+    const double *cl_val;
+    // B
+    const int64_t *b_rp;
+    const int32_t *b_col;
+    const double *b_val;
+    // units of this launch
+    const int32_t *order;
+    int64_t bin_begin, count;
+    const int32_t *keylo, *keyhi;
+    int32_t *ucount;
+    // C
+    int64_t *c_rp;
+    int32_t *c_col;
+    double *c_val;
+    int64_t cap, out_base;
+    int64_t unit_lo, unit_hi;
+    uint32_t *err;
+    // geometry
+    int G, T, log2T, group_bytes;
+    // dense path
+    uint32_t *dense_bits;
+    double *dense_vals;
+    int64_t dense_words;
+    int64_t ncols;
+};
+
+// error flag bits
+enum : uint32_t { kErrCapacity = 1u, kErrCount = 2u, kErrPtr = 4u, kErrRange = 8u, kErrUnsorted = 16u };
+
+// launchers (kernels.hip)
+hipError_t launch_sym(int sclass, bool cluster, const SpArgs &a, int blocks, int threads, size_t lds,
+                      hipStream_t s);
+hipError_t launch_num(int sclass, bool cluster, const SpArgs &a, int blocks, int threads, size_t lds,
+                      hipStream_t s);
+hipError_t launch_sym_dense(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
+hipError_t launch_num_dense(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
+
+// launchers (util.hip)
+struct BinArgs {
+    const int64_t *a_rp;
+    const int32_t *a_col;
+    const int64_t *cl_row_ptr;
+    const int32_t *perm;
+    const int64_t *cl_col_ptr;
+    const int32_t *cl_col;
+    const int64_t *b_rp;
+    const int32_t *b_col;
+    int64_t nunits;
+    Workspace ws;
+    int64_t *c_rp;
+    int sym_tmax_log2;
+    int num_tmax_by_class[kSClasses];
+    int load_pct;
+};
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s);
+hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
+hipError_t launch_scatter(const uint8_t *bin, int64_t n, const int64_t *counts, int64_t *cursor, int nbins,
+                          int32_t *order, hipStream_t s);
+hipError_t launch_scan_exclusive(int64_t *data, int64_t n, int64_t *tmp, hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+hipError_t launch_csr_check(const hcsp_csr &A, uint32_t *flags, hipStream_t s);
+
+// launchers (cluster.hip)
+hipError_t launch_cluster_count(const hcsp_csr &A, const int32_t *perm, const int64_t *cl_row_ptr, int64_t ncl,
+                                int64_t *cl_col_cnt, int64_t *cl_val_cnt, int32_t *maxsize, hipStream_t s);
+hipError_t launch_cluster_fill(const hcsp_csr &A, const hcsp_csr_cluster &out, hipStream_t s);
+
+}  // namespace hcsp

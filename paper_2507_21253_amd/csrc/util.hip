@@ -1,0 +1,323 @@
+// Support kernels: fills, per-unit work estimate and binning, counting-sort
+// scatter of units into bins, a device-wide exclusive scan (int64), and CSR
+// validation.
+#include <climits>
+
+#include "device.h"
+#include "internal.h"
+
+namespace hcsp {
+
+// ------------------------------------------------------------------ fills
+template <class T>
+__global__ void k_fill(T *p, int64_t n, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+static hipError_t fill(T *p, int64_t n, T v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s) { return fill(p, n, v, s); }
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) { return fill(p, n, v, s); }
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) { return fill(p, n, v, s); }
+
+// ------------------------------------------------------------------ binning
+__device__ __forceinline__ int ceil_log2(int64_t x)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < x) ++l;
+    return l;
+}
+
+__device__ __forceinline__ int sym_bin(int sc, int64_t probes, int tmax_log2)
+{
+    int l = ceil_log2(probes);
+    if (l < kSymLog2Min) l = kSymLog2Min;
+    if (l > tmax_log2) return kSymGlobal;
+    return 1 + sc * kSymT + (l - kSymLog2Min);
+}
+
+// One group of 16 lanes per unit: probes = sum of |B_k| over the unit's
+// columns k (an upper bound on its distinct output columns), the smallest
+// and largest output column it can reach, and its symbolic bin.  Units with
+// no products get their zero row counts here.
+template <bool CL>
+__global__ void __launch_bounds__(256) k_work(BinArgs a)
+{
+    __shared__ int hist[kSymBins];
+    for (int i = threadIdx.x; i < kSymBins; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const Group g = make_group(16);
+    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    if (u < a.nunits) {
+        int64_t it0, it1, pos0 = u;
+        int s = 1;
+        if (CL) {
+            it0 = a.cl_col_ptr[u];
+            it1 = a.cl_col_ptr[u + 1];
+            pos0 = a.cl_row_ptr[u];
+            s = (int)(a.cl_row_ptr[u + 1] - pos0);
+        } else {
+            it0 = a.a_rp[u];
+            it1 = a.a_rp[u + 1];
+        }
+        int64_t probes = 0;
+        int lo = INT_MAX, hi = -1;
+        for (int64_t q = it0 + g.gl; q < it1; q += 16) {
+            const int k = CL ? a.cl_col[q] : a.a_col[q];
+            const int64_t bs = a.b_rp[k], be = a.b_rp[k + 1];
+            if (be > bs) {
+                probes += be - bs;
+                lo = min(lo, a.b_col[bs]);
+                hi = max(hi, a.b_col[be - 1]);
+            }
+        }
+        probes = gsum64(g, probes);
+        lo = gmin32(g, lo);
+        hi = gmax32(g, hi);
+        const int sc = sclass_of(s);
+        const int bin = probes == 0 ? kBinEmpty : sym_bin(sc, probes, CL ? a.sym_tmax_log2 - 1 : a.sym_tmax_log2);
+        if (g.gl == 0) {
+            a.ws.probes[u] = probes;
+            a.ws.keylo[u] = lo;
+            a.ws.keyhi[u] = hi;
+            a.ws.bin[u] = (uint8_t)bin;
+            atomicAdd(&hist[bin], 1);
+            if (bin == kBinEmpty) {
+                a.ws.ucount[u] = 0;
+                for (int l = 0; l < s; ++l) a.c_rp[CL ? (int64_t)a.perm[pos0 + l] : u] = 0;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSymBins; i += blockDim.x)
+        if (hist[i]) atomicAdd((unsigned long long *)&a.ws.sym_count[i], (unsigned long long)hist[i]);
+}
+
+hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s)
+{
+    if (a.nunits <= 0) return hipSuccess;
+    const int64_t blocks = (a.nunits * 16 + 255) / 256;
+    if (cluster) hipLaunchKernelGGL((k_work<true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_work<false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Numeric bin from the exact number of distinct output columns found by the
+// symbolic phase: the smallest table that keeps the fill below load_pct.
+template <bool CL>
+__global__ void __launch_bounds__(256) k_numbin(BinArgs a)
+{
+    __shared__ int hist[kNumBins];
+    for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < a.nunits) {
+        const int s = CL ? (int)(a.cl_row_ptr[u + 1] - a.cl_row_ptr[u]) : 1;
+        const int sc = sclass_of(s);
+        const int32_t U = a.ws.ucount[u];
+        int bin;
+        if (a.ws.probes[u] == 0 || U == 0) {
+            bin = kBinEmpty;
+        } else if (U == INT32_MAX) {
+            bin = kNumGlobal;
+        } else {
+            const int64_t need = ((int64_t)U * 100 + a.load_pct - 1) / a.load_pct;
+            bin = kNumGlobal;
+            for (int t = 0; t < kNumT; ++t) {
+                const int T = num_table(t);
+                if (T > a.num_tmax_by_class[sc]) break;
+                if (T >= need) {
+                    bin = 1 + sc * kNumT + t;
+                    break;
+                }
+            }
+        }
+        a.ws.bin[u] = (uint8_t)bin;
+        atomicAdd(&hist[bin], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNumBins; i += blockDim.x)
+        if (hist[i]) atomicAdd((unsigned long long *)&a.ws.num_count[i], (unsigned long long)hist[i]);
+}
+
+hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s)
+{
+    if (a.nunits <= 0) return hipSuccess;
+    const int64_t blocks = (a.nunits + 255) / 256;
+    if (cluster) hipLaunchKernelGGL((k_numbin<true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_numbin<false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Counting-sort scatter: unit u goes to order[start(bin) + slot].  Each
+// block ranks its units per bin in shared memory and reserves one range per
+// bin with a single atomic, so units of one block stay adjacent.
+__global__ void __launch_bounds__(256) k_scatter(const uint8_t *bin, int64_t n, const int64_t *counts,
+                                                 int64_t *cursor, int nbins, int32_t *order)
+{
+    __shared__ int64_t start[HCSP_MAX_BINS];
+    __shared__ int local[HCSP_MAX_BINS];
+    __shared__ int64_t base[HCSP_MAX_BINS];
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int b = 0; b < nbins; ++b) {
+            start[b] = acc;
+            acc += counts[b];
+        }
+    }
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) local[b] = 0;
+    __syncthreads();
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int b = -1, r = 0;
+    if (u < n) {
+        b = bin[u];
+        r = atomicAdd(&local[b], 1);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < nbins; x += blockDim.x)
+        base[x] = local[x] ? (int64_t)atomicAdd((unsigned long long *)&cursor[x], (unsigned long long)local[x]) : 0;
+    __syncthreads();
+    if (u < n) {
+        const int64_t pos = start[b] + base[b] + r;
+        if (pos >= 0 && pos < n) order[pos] = (int32_t)u;
+    }
+}
+
+hipError_t launch_scatter(const uint8_t *bin, int64_t n, const int64_t *counts, int64_t *cursor, int nbins,
+                          int32_t *order, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, bin, n, counts, cursor,
+                       nbins, order);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int64_t kScanChunk = (int64_t)kScanThreads * kScanItems;
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1; }
+
+// Block-wide exclusive scan of one value per thread; returns the block total.
+__device__ int64_t block_exclusive(int64_t v, int64_t *out)
+{
+    __shared__ int64_t wsum[kScanThreads / kWave];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int64_t wbase = 0, tot = 0;
+    for (int i = 0; i < kScanThreads / kWave; ++i) {
+        if (i < w) wbase += wsum[i];
+        tot += wsum[i];
+    }
+    *out = wbase + inc - v;
+    __syncthreads();
+    return tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int64_t *d, int64_t n, int64_t *tmp)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
+    int64_t s = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t x = b0 + (int64_t)i * kScanThreads + threadIdx.x;
+        if (x < n) s += d[x];
+    }
+    int64_t ex;
+    const int64_t tot = block_exclusive(s, &ex);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_top(int64_t *tmp, int64_t nb)
+{
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
+        const int64_t x = c0 + threadIdx.x;
+        const int64_t v = x < nb ? tmp[x] : 0;
+        int64_t ex;
+        const int64_t tot = block_exclusive(v, &ex);
+        if (x < nb) tmp[x] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(int64_t *d, int64_t n, const int64_t *tmp)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t x = b0 + i;
+        v[i] = x < n ? d[x] : 0;
+        s += v[i];
+    }
+    int64_t ex;
+    block_exclusive(s, &ex);
+    int64_t run = tmp[blockIdx.x] + ex;
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t x = b0 + i;
+        if (x < n) d[x] = run;
+        run += v[i];
+    }
+}
+
+hipError_t launch_scan_exclusive(int64_t *data, int64_t n, int64_t *tmp, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    // k_scan_reduce sums strided chunks; k_scan_down scans contiguous ones: both
+    // cover block b's elements [b*chunk, (b+1)*chunk), so the block totals agree.
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ validation
+__global__ void __launch_bounds__(256) k_csr_check(const int64_t *rp, const int32_t *col, int64_t nrows,
+                                                   int64_t ncols, int64_t nnz, uint32_t *flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || rp[nrows] != nnz)) atomicOr(flags, kErrPtr);
+    if (i >= nrows) return;
+    const int64_t b = rp[i], e = rp[i + 1];
+    if (b > e || b < 0 || e > nnz) {
+        atomicOr(flags, kErrPtr);
+        return;
+    }
+    int prev = -1;
+    uint32_t f = 0;
+    for (int64_t p = b; p < e; ++p) {
+        const int c = col[p];
+        if (c < 0 || (int64_t)c >= ncols) f |= kErrRange;
+        if (c <= prev) f |= kErrUnsorted;
+        prev = c;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_csr_check(const hcsp_csr &A, uint32_t *flags, hipStream_t s)
+{
+    const int64_t blocks = (A.nrows + 256) / 256;
+    hipLaunchKernelGGL(k_csr_check, dim3((unsigned)blocks), dim3(256), 0, s, A.row_ptr, A.col, A.nrows, A.ncols,
+                       A.nnz, flags);
+    return hipGetLastError();
+}
+
+}  // namespace hcsp

@@ -1,0 +1,107 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point the public header declares, and its host cluster plans give
+exactly the oracle's plans."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_21253_amd as hc
+import synth
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "hcsp.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hcsp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hc.lib()
+    names = declared_symbols()
+    assert len(names) == 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hc._SIGS), "binding and header disagree"
+    assert hc.version().startswith("hcsp")
+    assert hc.strerror(-5) == "buffer too small"
+
+
+def same_plan(p, q):
+    np.testing.assert_array_equal(p.perm, q.perm)
+    np.testing.assert_array_equal(p.cl_row_ptr, q.cl_row_ptr)
+
+
+@pytest.mark.parametrize("K", [1, 3, 8, 16])
+def test_plan_fixed_matches_oracle(K):
+    pi = synth.perm(37, 5)
+    same_plan(hc.plan_fixed(37, K), oracle.plan_fixed(37, K))
+    same_plan(hc.plan_fixed(37, K, pi), oracle.plan_fixed(37, K, pi))
+
+
+def inputs():
+    yield "uniform", synth.uniform(300, 120, 6, 3)
+    yield "stencil27", synth.stencil(27, 6, 2)
+    M, _, _ = synth.workload_stencil27(7, 2, 3)
+    yield "stencil27_relabel", M
+    yield "rmat10", synth.rmat(10, 16, 0.57, 0.19, 0.19, 4)
+    yield "stencil5", synth.stencil(5, 20, 1)
+
+
+@pytest.mark.parametrize("t,maxc", [((3, 10), 8), ((1, 5), 4), ((0, 1), 16), ((1, 2), 2)])
+def test_plan_variable_matches_oracle(t, maxc):
+    for name, A in inputs():
+        same_plan(hc.plan_variable(A, t, maxc), oracle.plan_variable(A, t, maxc))
+        pi = synth.perm(A.nrows, 11)
+        same_plan(hc.plan_variable(A, t, maxc, pi), oracle.plan_variable(A, t, maxc, pi))
+
+
+@pytest.mark.parametrize("sim", [hc.SIM_ROOT, hc.SIM_UNION])
+@pytest.mark.parametrize("t,maxc", [((3, 10), 8), ((1, 5), 4), ((1, 3), 16), ((1, 2), 2), ((3, 10), 1)])
+def test_plan_hierarchical_matches_oracle(sim, t, maxc):
+    for name, A in inputs():
+        ref = oracle.plan_hierarchical(A, t, maxc, sim)
+        for nthreads in (1, 3):
+            same_plan(hc.plan_hierarchical(A, t, maxc, sim, nthreads), ref)
+        pi = synth.perm(A.nrows, 12)
+        same_plan(hc.plan_hierarchical(A, t, maxc, sim, 2, pi), oracle.plan_hierarchical(A, t, maxc, sim, pi))
+
+
+def test_plan_hierarchical_larger_multithreaded():
+    M, _, _ = synth.workload_stencil27(20, 2, 3)
+    same_plan(hc.plan_hierarchical(M, (3, 10), 8, hc.SIM_ROOT, 8), oracle.plan_hierarchical(M, (3, 10), 8))
+
+
+def test_plan_argument_errors():
+    A = synth.uniform(10, 10, 3, 1)
+    with pytest.raises(hc.HcspError) as e:
+        hc.plan_fixed(10, 0)
+    assert e.value.status == -1
+    with pytest.raises(hc.HcspError):
+        hc.plan_variable(A, (1, 0), 8)
+    with pytest.raises(hc.HcspError):
+        hc.plan_hierarchical(A, (3, 10), 17)
+    bad = np.zeros(10, np.int32)                      # not a permutation
+    with pytest.raises(hc.HcspError) as e:
+        hc.plan_hierarchical(A, (3, 10), 8, perm_in=bad)
+    assert "permutation" in str(e.value)
+
+
+def test_workspace_query_is_host_only():
+    # shape checks and the size query need no device
+    B = hc.DeviceCSR.__new__(hc.DeviceCSR)
+    op = hc.c_operand()
+    op.kind = hc.OP_CSR
+    op.csr = hc.c_csr(100, 50, 10, 1, 1, 1)
+    b = hc.c_csr(50, 70, 10, 1, 1, 1)
+    n = ctypes.c_size_t()
+    rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b), None, ctypes.byref(n))
+    assert rc == 0 and n.value > 0
+    b.nrows = 49                                      # A.ncols != B.nrows
+    rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b), None, ctypes.byref(n))
+    assert rc == -1 and "B.nrows" in hc.last_error()

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Structure and values must match bit for bit: both sides add each output
+entry's products in ascending k with fused multiply-adds from +0.0, so any
+difference is a bug (the 1e-12 relative tolerance the product contract allows
+is never needed here).  Sizes span several bins, ragged rows and empty rows.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2507_21253_amd as hc  # noqa: E402
+
+
+def to_dev(H):
+    return hc.DeviceCSR.from_host(H)
+
+
+def gpu_product(A_dev, B_dev, o=None):
+    torch.cuda.synchronize()
+    C = hc.spgemm(A_dev, B_dev, o)
+    torch.cuda.synchronize()
+    return C.to_host()
+
+
+def assert_same(Cg, Cr, where=""):
+    np.testing.assert_array_equal(Cg.rp, Cr.rp, err_msg="row_ptr " + where)
+    np.testing.assert_array_equal(Cg.col, Cr.col, err_msg="col " + where)
+    np.testing.assert_array_equal(Cg.val, Cr.val, err_msg="val " + where)
+
+
+def ragged(seed, n, m, p):
+    """Rows of very different lengths, some empty; explicit zeros stored."""
+    rng = np.random.default_rng(seed)
+    dens = rng.choice([0.0, 0.01, 0.05, 0.3, 0.9], size=n)
+    pat = rng.random((n, m)) < dens[:, None]
+    vals = rng.uniform(-1, 1, (n, m))
+    vals[rng.random((n, m)) < 0.05] = 0.0
+    A = synth.from_dense(np.where(pat, vals, 0.0), pat)
+    pb = rng.random((m, p)) < rng.choice([0.0, 0.02, 0.1, 0.5], size=m)[:, None]
+    B = synth.from_dense(np.where(pb, rng.uniform(-1, 1, (m, p)), 0.0), pb)
+    return A, B
+
+
+def test_uniform_2000_bitwise():
+    A = synth.workload_uniform_2000()
+    Ad = to_dev(A)
+    assert_same(gpu_product(Ad, Ad), oracle.spgemm(A, A))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ragged_random_bitwise(seed):
+    rng = np.random.default_rng(100 + seed)
+    n, m, p = (int(x) for x in rng.integers(1, 400, 3))
+    A, B = ragged(seed, n, m, p)
+    assert_same(gpu_product(to_dev(A), to_dev(B)), oracle.spgemm(A, B), "seed %d" % seed)
+
+
+@pytest.mark.parametrize("kind,m", [(5, 40), (7, 14), (27, 10)])
+def test_stencils_bitwise(kind, m):
+    S = synth.stencil(kind, m, 7)
+    Sd = to_dev(S)
+    assert_same(gpu_product(Sd, Sd), oracle.spgemm(S, S))
+
+
+def test_relabelled_stencil_bitwise():
+    M, _, _ = synth.workload_stencil27(12, 2, 3)
+    Md = to_dev(M)
+    assert_same(gpu_product(Md, Md), oracle.spgemm(M, M))
+
+
+@pytest.mark.parametrize("lanes", [8, 16, 32, 64])
+def test_lane_group_sizes(lanes):
+    A = synth.uniform(700, 500, 9, 5)
+    B = synth.uniform(500, 900, 21, 6)
+    assert_same(gpu_product(to_dev(A), to_dev(B), hc.opts(lanes=lanes)), oracle.spgemm(A, B))
+
+
+def plans_for(A):
+    yield "fixed4", hc.plan_fixed(A.nrows, 4)
+    yield "fixed16_perm", hc.plan_fixed(A.nrows, 16, synth.perm(A.nrows, 9))
+    yield "variable", hc.plan_variable(A, (3, 10), 8)
+    yield "variable_t0", hc.plan_variable(A, (0, 1), 3)
+    yield "hier_root", hc.plan_hierarchical(A, (3, 10), 8, hc.SIM_ROOT)
+    yield "hier_union", hc.plan_hierarchical(A, (3, 10), 8, hc.SIM_UNION)
+    yield "hier_perm16", hc.plan_hierarchical(A, (1, 5), 16, hc.SIM_ROOT, perm_in=synth.perm(A.nrows, 4))
+
+
+def host_cluster_of(Dc):
+    return dict(cl_col_ptr=Dc.cl_col_ptr.cpu().numpy(), cl_col=Dc.cl_col.cpu().numpy(),
+                cl_mask=Dc.cl_mask.cpu().numpy().view(np.uint16), cl_val_ptr=Dc.cl_val_ptr.cpu().numpy(),
+                cl_val=Dc.cl_val.cpu().numpy())
+
+
+def test_cluster_build_matches_oracle():
+    M, _, _ = synth.workload_stencil27(9, 2, 3)
+    Md = to_dev(M)
+    for name, plan in plans_for(M):
+        ref = oracle.cluster_build(M, oracle.Plan(plan.perm, plan.cl_row_ptr))
+        Dc = hc.cluster_build(Md, plan)
+        torch.cuda.synchronize()
+        got = host_cluster_of(Dc)
+        for k in got:
+            np.testing.assert_array_equal(got[k], getattr(ref, k), err_msg="%s %s" % (name, k))
+        assert Dc.max_cluster == int(np.diff(plan.cl_row_ptr).max())
+
+
+@pytest.mark.parametrize("which", ["stencil_relabel", "uniform", "ragged"])
+def test_clustered_product_bitwise(which):
+    if which == "stencil_relabel":
+        A, _, _ = synth.workload_stencil27(10, 2, 3)
+        B = A
+    elif which == "uniform":
+        A = synth.uniform(600, 400, 8, 3)
+        B = synth.uniform(400, 700, 12, 4)
+    else:
+        A, B = ragged(7, 300, 250, 280)
+    ref = oracle.spgemm(A, B)
+    Ad, Bd = to_dev(A), to_dev(B)
+    for name, plan in plans_for(A):
+        Dc = hc.cluster_build(Ad, plan)
+        assert_same(gpu_product(Dc, Bd), ref, name)
+
+
+def test_forced_dense_path_bitwise():
+    # tiny shared-memory tables push every unit onto the global-memory path
+    A = synth.uniform(300, 200, 20, 8)
+    B = synth.uniform(200, 350, 25, 9)
+    o = hc.opts(sym_tmax_log2=7, num_tmax=96)
+    ref = oracle.spgemm(A, B)
+    assert_same(gpu_product(to_dev(A), to_dev(B), o), ref, "csr")
+    plan = hc.plan_hierarchical(A, (1, 10), 8)
+    assert_same(gpu_product(hc.cluster_build(to_dev(A), plan), to_dev(B), o), ref, "cluster")
+
+
+def test_rmat_small_bitwise():
+    R = synth.rmat(12, 16, 0.57, 0.19, 0.19, 4)
+    Rd = to_dev(R)
+    ref = oracle.spgemm(R, R)
+    assert_same(gpu_product(Rd, Rd), ref, "csr")
+    plan = hc.plan_hierarchical(R, (3, 10), 8)
+    assert_same(gpu_product(hc.cluster_build(Rd, plan), Rd), ref, "hier")
+
+
+def test_empty_and_degenerate():
+    Z = synth.HostCSR(np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0), 5, 4)
+    B = synth.uniform(4, 7, 2, 1)
+    C = gpu_product(to_dev(Z), to_dev(B))
+    assert C.rp.tolist() == [0] * 6 and len(C.col) == 0
+    A = synth.uniform(5, 4, 2, 2)
+    Bz = synth.HostCSR(np.zeros(5, np.int64), np.zeros(0, np.int32), np.zeros(0), 4, 9)
+    C = gpu_product(to_dev(A), to_dev(Bz))
+    assert C.rp.tolist() == [0] * 6
+    one = synth.from_dense(np.array([[2.0]]))
+    C = gpu_product(to_dev(one), to_dev(one))
+    assert C.col.tolist() == [0] and C.val.tolist() == [4.0]
+
+
+def test_panels_with_out_base():
+    A = synth.uniform(1000, 800, 7, 21)
+    B = synth.uniform(800, 900, 11, 22)
+    Ad, Bd = to_dev(A), to_dev(B)
+    P = hc.Product(Ad, Bd)
+    nnz = P.symbolic()
+    rp = P.C_row_ptr.cpu().numpy()
+    col = np.empty(nnz, np.int32)
+    val = np.empty(nnz)
+    for lo, hi in [(0, 333), (333, 334), (334, 1000)]:
+        base, end = int(rp[lo]), int(rp[hi])
+        bc = torch.empty(end - base, dtype=torch.int32, device="cuda")
+        bv = torch.empty(end - base, dtype=torch.float64, device="cuda")
+        o = hc.opts(unit_lo=lo, unit_hi=hi, out_base=base, flags=hc.F_SYNC_CHECK)
+        hc.spgemm_numeric(Ad, Bd, P.info, P.C_row_ptr, bc, bv, P.ws, o, capacity=end - base)
+        col[base:end] = bc.cpu().numpy()
+        val[base:end] = bv.cpu().numpy()
+    ref = oracle.spgemm(A, B)
+    np.testing.assert_array_equal(rp, ref.rp)
+    np.testing.assert_array_equal(col, ref.col)
+    np.testing.assert_array_equal(val, ref.val)
+
+
+def test_capacity_too_small_is_reported_and_bounded():
+    A = synth.uniform(200, 200, 6, 31)
+    Ad = to_dev(A)
+    P = hc.Product(Ad, Ad)
+    nnz = P.symbolic()
+    cap = nnz // 2
+    guard = 4096
+    bc = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
+    bv = torch.full((cap + guard,), -7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(hc.HcspError) as e:
+        hc.spgemm_numeric(Ad, Ad, P.info, P.C_row_ptr, bc, bv, P.ws, hc.opts(flags=hc.F_SYNC_CHECK), capacity=cap)
+    assert e.value.status == -5
+    assert bool((bc[cap:] == -7).all()) and bool((bv[cap:] == -7.0).all())
+
+
+def test_csr_check_reports_malformed_inputs():
+    A = synth.uniform(50, 40, 5, 3)
+    assert hc.csr_check(to_dev(A)) == 0
+    bad = synth.HostCSR(A.rp.copy(), A.col.copy(), A.val, 50, 40)
+    bad.col[7], bad.col[8] = bad.col[8], bad.col[7]
+    assert hc.csr_check(to_dev(bad)) == -4
+    bad = synth.HostCSR(A.rp.copy(), A.col.copy(), A.val, 50, 40)
+    bad.col[3] = 40
+    assert hc.csr_check(to_dev(bad)) == -3
+    bad = synth.HostCSR(A.rp.copy(), A.col.copy(), A.val, 50, 40)
+    bad.rp[10] = bad.rp[11] + 1
+    assert hc.csr_check(to_dev(bad)) == -2
+
+
+def test_run_twice_bitwise_identical():
+    M, _, _ = synth.workload_stencil27(12, 5, 6)
+    Md = to_dev(M)
+    plan = hc.plan_hierarchical(M, (3, 10), 8)
+    Dc = hc.cluster_build(Md, plan)
+    P = hc.Product(Dc, Md)
+    C1 = P.run().to_host()
+    C2 = P.run().to_host()
+    assert_same(C1, C2)
