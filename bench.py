@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: clustered vs plain Gustavson SpGEMM on one MI355X.
+
+Workload (default): C = M*M for M the 27-point stencil on a 100^3 grid with
+values U(-1,1), symmetrically relabelled by a seeded random permutation so
+the natural locality is gone.  Hierarchical clustering (Alg. 3, jacc_th 0.3,
+max cluster 8) then regroups similar rows into CSR_Cluster and the product
+runs cluster-wise (Alg. 1).  One step = symbolic phase (binning, counts,
+scan), the nnz read-back, and the numeric phase of the clustered product;
+the plain-CSR product of the same matrix is timed the same way for the
+comparison.  Clustering itself (host plan + device CSR_Cluster build) is
+preprocessing, timed once and reported in units of one SpGEMM.
+
+Prints one JSON line.  ``--mode copy`` runs only a plain device copy of known
+size (the calibration run for hardware byte counters).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def csr_bytes(nrows: int, nnz: int) -> int:
+    return 8 * (nrows + 1) + 12 * nnz
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--m", type=int, default=100, help="stencil grid side")
+    p.add_argument("--max-cluster", type=int, default=8)
+    p.add_argument("--sim", choices=["root", "union"], default="root")
+    p.add_argument("--lanes", type=int, default=0)
+    p.add_argument("--mode", choices=["bench", "copy"], default="bench")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-threads", type=int, default=0)
+    p.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per numeric launch")
+    return p.parse_args()
+
+
+def copy_mode(args):
+    import torch
+    n = 1 << 28  # 2 GiB of float64
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    print(json.dumps({"mode": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "ms": ms,
+                      "gbs": 16 * n / ms / 1e6}), flush=True)
+
+
+def time_product(P, steps, warmup, torch):
+    """Runs warmup + timed steps of symbolic+numeric; returns per-step wall ms and phase ms."""
+    for _ in range(warmup):
+        P.run()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(s)
+        P.symbolic()
+        ev[i][1].record(s)
+        P.numeric()
+        ev[i][2].record(s)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    sym = float(np.mean([a.elapsed_time(b) for a, b, c in ev]))
+    num = float(np.mean([b.elapsed_time(c) for a, b, c in ev]))
+    return wall, sym, num
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (sharding is a design note); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.mode == "copy":
+        copy_mode(args)
+        return
+    import paper_2507_21253_amd as hc
+    import synth
+
+    m = args.m
+    t = time.perf_counter()
+    M, S, q = synth.workload_stencil27(m, 2, 3)
+    log("inputs: %d rows, nnz %d (%.1fs)" % (M.nrows, M.nnz, time.perf_counter() - t))
+    rowlen = np.diff(M.rp)
+    products = int(rowlen[M.col].sum())
+    flop = 2 * products
+
+    # ---- preprocessing: hierarchical plan on the host, CSR_Cluster on the device
+    ncpu = len(os.sched_getaffinity(0))
+    t = time.perf_counter()
+    plan = hc.plan_hierarchical(M, (3, 10), args.max_cluster, hc.SIM_UNION if args.sim == "union" else hc.SIM_ROOT,
+                                nthreads=ncpu)
+    t_plan = time.perf_counter() - t
+    log("plan: %d clusters (%.2fs, %d threads)" % (plan.nclusters, t_plan, ncpu))
+    Md = hc.DeviceCSR.from_host(M)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        Dc = hc.cluster_build(Md, plan)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Dc = hc.cluster_build(Md, plan)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t
+    log("CSR_Cluster: ncc %d nslots %d max %d (%.3fs)" % (Dc.ncc, Dc.nslots, Dc.max_cluster, t_build))
+
+    o = hc.opts(lanes=args.lanes)
+    P_cl = hc.Product(Dc, Md, o)
+    P_pl = hc.Product(Md, Md, o)
+    wall_cl, sym_cl, num_cl = time_product(P_cl, args.steps, args.warmup, torch)
+    nnzC = P_cl.info.nnz
+    wall_pl, sym_pl, num_pl = time_product(P_pl, args.steps, args.warmup, torch)
+    assert P_pl.info.nnz == nnzC
+    if m >= 3:
+        assert nnzC == (5 * m - 6) ** 3, "nnz(C) differs from the closed form"
+    log("clustered: %.3f ms/step (sym %.3f, num %.3f); plain: %.3f ms/step (sym %.3f, num %.3f)"
+        % (wall_cl, sym_cl, num_cl, wall_pl, sym_pl, num_pl))
+
+    bytes_A = csr_bytes(M.nrows, M.nnz)
+    bytes_Acl = Dc.bytes()
+    bytes_C = csr_bytes(M.nrows, nnzC)
+    comp_cl = bytes_Acl + bytes_A + bytes_C          # A in CSR_Cluster, B = M in CSR, C
+    comp_pl = 2 * bytes_A + bytes_C
+    gflops_cl = flop / (wall_cl * 1e-3) / 1e9
+    gflops_pl = flop / (wall_pl * 1e-3) / 1e9
+    # dominant kernel family: the numeric launches; its algorithmic bytes are A (clustered), B and C
+    ach = comp_cl / (num_cl * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        tr = json.load(open(args.traffic))
+        traffic = tr.get("numeric_hbm_bytes")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        nth = args.cpu_threads or ncpu
+        oracle.spgemm_mt(M, M, nth, structure_only=True)  # warm the pages
+        runs = []
+        for _ in range(2):
+            t = time.perf_counter()
+            Cref = oracle.spgemm_mt(M, M, nth)
+            runs.append(time.perf_counter() - t)
+        assert Cref.nnz == nnzC
+        tcpu = float(np.mean(runs))
+        cpu = {"value": round(flop / tcpu / 1e9, 3), "unit": "GFLOP/s", "cores": nth, "kind": "oracle",
+               "sample": "full C = M*M (count pass + fill pass), mean of %d runs, %.2f s each" % (len(runs), tcpu)}
+        del Cref
+
+    out = {
+        "metric": "SpGEMM GFLOP/s + achieved HBM GB/s, CSR_Cluster vs plain CSR on 1 MI355X",
+        "value": round(gflops_cl, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_cl, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "stencil27_%d^3_relabelled_A2" % m, "nrows": M.nrows, "nnz_A": M.nnz,
+                   "nnz_C": nnzC, "products": products, "clustering": "hierarchical",
+                   "jacc_th": "3/10", "max_cluster": args.max_cluster, "similarity": args.sim},
+        "gbs_compulsory": round(comp_cl / (wall_cl * 1e-3) / 1e9, 2),
+        "phases_ms": {"symbolic_incl_readback": round(sym_cl, 4), "numeric": round(num_cl, 4)},
+        "plain_csr": {"gflops": round(gflops_pl, 3), "ms_per_step": round(wall_pl, 4),
+                      "gbs_compulsory": round(comp_pl / (wall_pl * 1e-3) / 1e9, 2),
+                      "phases_ms": {"symbolic_incl_readback": round(sym_pl, 4), "numeric": round(num_pl, 4)}},
+        "speedup_clustered_vs_plain": round(wall_pl / wall_cl, 3),
+        "preprocessing": {"plan_host_s": round(t_plan, 3), "plan_threads": ncpu, "cluster_build_s": round(t_build, 4),
+                          "in_spgemms": round((t_plan + t_build) / (wall_cl * 1e-3), 1),
+                          "nclusters": plan.nclusters, "ncc": Dc.ncc, "nslots": Dc.nslots,
+                          "csr_cluster_over_csr_bytes": round(bytes_Acl / bytes_A, 3)},
+        "roofline": {"bound": "hbm", "kernel": "k_num (numeric phase launches)", "achieved": round(ach, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes": comp_cl},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

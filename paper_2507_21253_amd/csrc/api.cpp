@@ -42,7 +42,7 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->order_num = (int32_t *)take(4 * nu);
     ws->sym_count = (int64_t *)take(8 * HCSP_MAX_BINS);
     ws->num_count = (int64_t *)take(8 * HCSP_MAX_BINS);
-    ws->cursor = (int64_t *)take(8 * HCSP_MAX_BINS);
+    ws->bin_hist = (int32_t *)take(4 * (size_t)kBinBlocks * HCSP_MAX_BINS);
     ws->err = (uint32_t *)take(256);
     ws->scan_tmp = (int64_t *)take(8 * scan_tmp_elems(std::max(nrows, nunits) + 1));
     ws->dense_words = (std::max<int64_t>(ncols, 1) + 31) / 32;
@@ -70,37 +70,18 @@ static int64_t lds_limit()
     return cache[dev];
 }
 
-static int floor_log2(int64_t x)
-{
-    int l = 0;
-    while (((int64_t)2 << l) <= x) ++l;
-    return l;
-}
-
-static int pow2_at_least(int64_t x)
-{
-    int v = 1;
-    while (v < x && v < 64) v <<= 1;
-    return v;
-}
-
 static int make_tune(const hcsp_opts *o, const hcsp_csr *B, bool need_device, Tune *t)
 {
     hcsp_opts z;
     std::memset(&z, 0, sizeof z);
     if (!o) o = &z;
-    if (o->lanes) {
-        if (o->lanes != 8 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64)
-            return fail(HCSP_E_INVALID, "opts.lanes must be 0, 8, 16, 32 or 64");
-        t->G = o->lanes;
-    } else {
-        const int64_t avg = B->nrows > 0 ? (B->nnz + B->nrows - 1) / B->nrows : 1;
-        t->G = std::min(64, std::max(16, pow2_at_least(avg)));
-    }
+    if (o->lanes != 0 && o->lanes != 64) return fail(HCSP_E_INVALID, "opts.lanes must be 0 or 64");
+    t->G = 64;
     t->load_pct = o->load_pct ? o->load_pct : 60;
     if (t->load_pct < 10 || t->load_pct > 95) return fail(HCSP_E_INVALID, "opts.load_pct must be in 10..95");
     t->lds_budget = need_device ? lds_limit() : 64 * 1024;
-    int sym = std::min(kSymLog2Max, floor_log2(t->lds_budget / 4));
+    int sym = kSymLog2Max;
+    while (sym > kSymLog2Min && sym_wave_bytes(true, 1 << sym) > t->lds_budget) --sym;
     if (o->sym_tmax_log2) sym = std::max(kSymLog2Min + 1, std::min(sym, (int)o->sym_tmax_log2));
     t->sym_tmax_log2 = sym;
     t->num_tmax = o->num_tmax ? o->num_tmax : (1 << 30);
@@ -119,7 +100,7 @@ static void num_tmax_classes(const Tune &tu, bool cl, int out[kSClasses])
         int best = 0;
         for (int t = 0; t < kNumT; ++t) {
             const int T = num_table(t);
-            if (T <= tu.num_tmax && num_group_bytes(cl, sc, T, tu.G) <= tu.lds_budget) best = T;
+            if (T <= tu.num_tmax && num_wave_bytes(cl, sc, T) <= tu.lds_budget) best = T;
         }
         out[sc] = best;
     }
@@ -172,6 +153,8 @@ static int check_operands(const hcsp_operand *A, const hcsp_csr *B, OpView *v)
         return fail(HCSP_E_INVALID, "unknown operand kind");
     }
     if (v->ncols != B->nrows) return fail(HCSP_E_INVALID, "A.ncols != B.nrows");
+    if (B->nnz >= (1ll << 29))
+        return fail(HCSP_E_UNSUPPORTED, "B must have fewer than 2^29 entries (32-bit byte offsets)");
     return HCSP_OK;
 }
 
@@ -234,15 +217,15 @@ static BinArgs bin_args(const hcsp_operand *A, const hcsp_csr *B, const Workspac
     return b;
 }
 
-// Launch geometry for one bin: groups of G lanes, as many per block as the
-// block's shared-memory target allows.
-static void geometry(int64_t group_bytes, int G, int64_t count, int *blocks, int *threads, size_t *lds)
+// Launch geometry for one bin: one wavefront per unit, up to four per block
+// as the block's shared-memory target allows.
+static void geometry(int64_t wave_bytes, int64_t count, int *blocks, int *threads, size_t *lds)
 {
     const int64_t target = 64 * 1024;
-    int64_t gpb = std::max<int64_t>(1, std::min<int64_t>(256 / G, target / std::max<int64_t>(group_bytes, 1)));
-    *threads = (int)(gpb * G);
-    *lds = (size_t)(gpb * group_bytes);
-    *blocks = (int)((count + gpb - 1) / gpb);
+    const int64_t wpb = std::max<int64_t>(1, std::min<int64_t>(4, target / std::max<int64_t>(wave_bytes, 1)));
+    *threads = (int)(wpb * 64);
+    *lds = (size_t)(wpb * wave_bytes);
+    *blocks = (int)((count + wpb - 1) / wpb);
 }
 
 static int ensure_lds(size_t lds, int64_t budget)
@@ -385,13 +368,12 @@ int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
 
     HCSP_HIP(launch_fill_i64(ws.sym_count, HCSP_MAX_BINS, 0, s));
     HCSP_HIP(launch_fill_i64(ws.num_count, HCSP_MAX_BINS, 0, s));
-    HCSP_HIP(launch_fill_i64(ws.cursor, HCSP_MAX_BINS, 0, s));
     HCSP_HIP(launch_fill_u32(ws.err, 1, 0u, s));
     HCSP_HIP(launch_fill_i64(C_row_ptr_d + v.nrows, 1, 0, s));
 
     BinArgs ba = bin_args(A, B, ws, tu, v.nunits, C_row_ptr_d);
     HCSP_HIP(launch_work(v.cluster, ba, s));
-    HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.sym_count, ws.cursor, kSymBins, ws.order_sym, s));
+    HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.bin_hist, kSymBins, ws.sym_count, ws.order_sym, s));
     int64_t cnt[HCSP_MAX_BINS];
     HCSP_HIP(hipMemcpyAsync(cnt, ws.sym_count, 8 * kSymBins, hipMemcpyDeviceToHost, s));
     HCSP_HIP(hipStreamSynchronize(s));
@@ -415,11 +397,11 @@ int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
                 const int l2 = (b - 1) % kSymT + kSymLog2Min;
                 a.T = 1 << l2;
                 a.log2T = l2;
-                const int64_t gb = sym_group_bytes(v.cluster, a.T);
+                const int64_t gb = sym_wave_bytes(v.cluster, a.T);
                 a.group_bytes = (int)gb;
                 int blocks, threads;
                 size_t lds;
-                geometry(gb, tu.G, c, &blocks, &threads, &lds);
+                geometry(gb, c, &blocks, &threads, &lds);
                 rc = ensure_lds(lds, tu.lds_budget);
                 if (rc) return rc;
                 HCSP_HIP(launch_sym(sc, v.cluster, a, blocks, threads, lds, s));
@@ -428,9 +410,8 @@ int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
         start += c;
     }
     HCSP_HIP(launch_scan_exclusive(C_row_ptr_d, v.nrows + 1, ws.scan_tmp, s));
-    HCSP_HIP(launch_fill_i64(ws.cursor, HCSP_MAX_BINS, 0, s));
     HCSP_HIP(launch_numbin(v.cluster, ba, s));
-    HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.num_count, ws.cursor, kNumBins, ws.order_num, s));
+    HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.bin_hist, kNumBins, ws.num_count, ws.order_num, s));
     int64_t ncnt[HCSP_MAX_BINS];
     int64_t nnz = 0;
     HCSP_HIP(hipMemcpyAsync(ncnt, ws.num_count, 8 * kNumBins, hipMemcpyDeviceToHost, s));
@@ -491,11 +472,11 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                 const int sc = (b - 1) / kNumT;
                 const int t = (b - 1) % kNumT;
                 a.T = num_table(t);
-                const int64_t gb = num_group_bytes(v.cluster, sc, a.T, tu.G);
+                const int64_t gb = num_wave_bytes(v.cluster, sc, a.T);
                 a.group_bytes = (int)gb;
                 int blocks, threads;
                 size_t lds;
-                geometry(gb, tu.G, c, &blocks, &threads, &lds);
+                geometry(gb, c, &blocks, &threads, &lds);
                 rc = ensure_lds(lds, tu.lds_budget);
                 if (rc) return rc;
                 HCSP_HIP(launch_num(sc, v.cluster, a, blocks, threads, lds, s));

@@ -1,0 +1,619 @@
+// Symbolic and numeric SpGEMM kernels for gfx950, shared-memory path.
+//
+// Work unit: one row of a CSR A, or one cluster of a CSR_Cluster A (paper,
+// Alg. 1: for a cluster, every union column k is visited once, row k of B is
+// read once, and each entry b_kj updates every member row l whose mask bit
+// is set: c_lj += a_lk * b_kj).  A CSR row is a cluster of one row.
+//
+// One wavefront owns one unit and a private slice of shared memory (LDS).
+// The unit's products are taken as one flattened list in ascending k (item
+// = one column k of the unit, contributing the entries of row k of B), and
+// the wavefront walks it 64 entries per pass, so short rows of B still fill
+// every lane.  Within a pass all lanes probe the hash table at once; the
+// fused multiply-adds are then applied item by item (a scalar loop over the
+// few items a pass touches), so an output c_lj receives its products in
+// ascending k, each by one fma starting from +0.0 — the same sequence the
+// row-by-row Gustavson reference performs.  Entries of one row of B have
+// distinct columns, so lanes of one sub-step never share a slot, and the
+// wavefront's LDS operations stay in program order across sub-steps.
+//
+// The kernels are bound by instruction issue, so the pass loop is written
+// to keep the common path branch-free: a probe is one LDS compare-and-swap
+// (taking the slot if empty, confirming it if it already holds the key);
+// lanes past the end of the list work on a reserved dummy slot instead of
+// being masked off; B is addressed by 32-bit offsets from a scalar base; and
+// the loads of several passes are issued before any of them is consumed.
+#include <climits>
+
+#include "unit.h"
+
+namespace hcsp {
+
+// passes whose B loads are in flight together (fewer for wide clusters, whose
+// per-member updates need more registers)
+template <int S>
+struct Depth {
+    static constexpr int R = S >= 8 ? 2 : (S >= 4 ? 4 : 8);
+};
+constexpr int kRoundW = 4096;               // products per round
+constexpr int kRoundPasses = kRoundW / 64;  // == 64: one start-bit word per lane
+constexpr int kDummyKey = INT_MAX;          // key of the reserved slot used by idle lanes
+
+// 16-byte item record: one column k of the unit inside the current round.
+struct __align__(16) ItemRec {
+    uint32_t bs;  // offset in B of the item's first product in this round
+    int32_t P;    // first position of the item in the round's flattened list
+    uint32_t x;   // CSR: low word of a_ik.  Cluster: member-row mask of the column
+    uint32_t y;   // CSR: high word of a_ik. Cluster: lane holding the item's A values
+};
+static_assert(sizeof(ItemRec) == 16, "ItemRec layout");
+
+__device__ __forceinline__ uint64_t lanemask_lt(int L) { return (1ull << L) - 1ull; }
+__device__ __forceinline__ uint64_t lanemask_le(int L) { return L == 63 ? ~0ull : ((2ull << L) - 1ull); }
+
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = (int)__lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane((int)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// B entry at a 32-bit element offset from the array base (scalar base +
+// vector offset addressing).
+__device__ __forceinline__ int ld_col(const int32_t *base, uint32_t off)
+{
+    return *(const int32_t *)((const char *)base + (uint64_t)(off << 2));
+}
+__device__ __forceinline__ double ld_val(const double *base, uint32_t off)
+{
+    return *(const double *)((const char *)base + (uint64_t)(off << 3));
+}
+
+// ---------------------------------------------------------------- LDS layout
+// Slot counts include one reserved dummy slot at the end.
+struct SymLayout {
+    int keys, masks, items, sbits, bytes;
+    __host__ __device__ SymLayout(bool cl, int T)
+    {
+        keys = 0;
+        masks = keys + 4 * (T + 1);
+        items = (masks + (cl ? 4 * (T + 1) : 0) + 15) & ~15;
+        sbits = items + 16 * 64;
+        bytes = (sbits + 8 * kRoundPasses + 15) & ~15;
+    }
+};
+
+struct NumLayout {
+    int keys, masks, vals, aval, order, items, sbits, occw, pre, bytes;
+    __host__ __device__ NumLayout(bool cl, int S, int TX)
+    {
+        const int nw = (TX + 63) / 64;
+        keys = 0;
+        masks = keys + 4 * (TX + 1);
+        vals = (masks + (cl ? 4 * (TX + 1) : 0) + 15) & ~15;
+        aval = vals + 8 * S * (TX + 1);
+        order = aval + (cl ? 8 * S * 64 : 0);
+        items = (order + 2 * TX + 15) & ~15;
+        sbits = items + 16 * 64;
+        occw = sbits + 8 * kRoundPasses;
+        pre = occw + 8 * nw;
+        bytes = (pre + 4 * nw + 15) & ~15;
+    }
+};
+
+int64_t sym_wave_bytes(bool cl, int T) { return SymLayout(cl, T).bytes; }
+int64_t num_wave_bytes(bool cl, int sclass, int T) { return NumLayout(cl, 1 << sclass, T + kTail).bytes; }
+
+// ---------------------------------------------------------------- rounds
+// Loads the next round of items into LDS: lane i takes column q0+i of the
+// unit; the non-empty ones are compacted, their products laid out back to
+// back (positions P), and a start bit set at each P.  For a cluster's numeric
+// phase lane i also stages the column's member values in aval[i*S ..].  An item longer than
+// what fits is cut and resumed in the next round (q0, off0 advance).
+// Returns the number of products in the round.
+template <bool CL, int S, bool NUM>
+__device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, int64_t &q0, int &off0,
+                                          ItemRec *items, uint64_t *sbits, double *aval)
+{
+    const int lane = (int)__lane_id();
+    sbits[lane] = 0ull;
+    const int64_t q = q0 + lane;
+    int64_t bs = 0;
+    int bl = 0;
+    uint32_t m = 1u;
+    double a1 = 0.0;
+    if (q < v.it1) {
+        const int k = CL ? a.cl_col[q] : a.a_col[q];
+        if (CL) m = a.cl_mask[q];
+        bs = a.b_rp[k];
+        bl = (int)(a.b_rp[k + 1] - bs);
+        if (NUM) {
+            if (CL) {
+                const double *src = a.cl_val + v.vbase + (q - v.it0) * v.s;
+#pragma unroll
+                for (int l = 0; l < S; ++l)
+                    if (l < v.s) aval[lane * S + l] = src[l];
+            } else {
+                a1 = a.a_val[q];
+            }
+        }
+    }
+    if (lane == 0) {
+        bs += off0;
+        bl -= off0;
+    }
+    const int blc = min(bl, kRoundW);
+    const int incl = wave_incl_scan(blc);
+    const int P = incl - blc;
+    const int E = min(__shfl(incl, 63), kRoundW);
+    const bool in = blc > 0 && P < kRoundW;
+    const uint64_t inb = __ballot(in);
+    if (in) {
+        ItemRec r;
+        r.bs = (uint32_t)bs;
+        r.P = P;
+        if (CL) {
+            r.x = m;
+            r.y = (uint32_t)lane;
+        } else {
+            const uint64_t ab = (uint64_t)__double_as_longlong(a1);
+            r.x = (uint32_t)ab;
+            r.y = (uint32_t)(ab >> 32);
+        }
+        items[__popcll(inb & lanemask_lt(lane))] = r;
+        atomicOr((unsigned long long *)&sbits[P >> 6], 1ull << (P & 63));
+    }
+    const uint64_t cutb = __ballot(in && (int64_t)P + bl > kRoundW);
+    if (cutb) {
+        const int cl = __ffsll((unsigned long long)cutb) - 1;
+        const int used = kRoundW - __shfl(P, cl);
+        off0 = (cl == 0 ? off0 : 0) + used;
+        q0 += cl;
+    } else {
+        const uint64_t rest = __ballot(!in && blc > 0);
+        if (rest) {
+            q0 += __ffsll((unsigned long long)rest) - 1;
+        } else {
+            q0 = min(q0 + 64, v.it1);
+        }
+        off0 = 0;
+    }
+    return E;
+}
+
+// One lane's share of one pass: its entry of the flattened product list.
+// Lanes past the end get the dummy key and read B at offset 0.
+template <bool CL, bool NUM>
+struct Pass {
+    int j;
+    int t;        // item index (lanes past the end: the last item)
+    uint32_t m;   // cluster: the item's row mask (symbolic)
+    double b, a;
+};
+
+template <bool CL, bool NUM>
+__device__ __forceinline__ Pass<CL, NUM> fetch_pass(const SpArgs &a, const ItemRec *items, uint64_t w, int cum,
+                                                    int e, int E, uint64_t le)
+{
+    Pass<CL, NUM> d;
+    d.t = cum + __popcll(w & le) - 1;
+    const ItemRec it = items[d.t];
+    const bool ok = e < E;
+    const uint32_t off = ok ? it.bs + (uint32_t)(e - it.P) : 0u;
+    const int j = ld_col(a.b_col, off);
+    d.j = ok ? j : kDummyKey;
+    d.m = CL ? it.x : 1u;
+    if (NUM) {
+        const double b = ld_val(a.b_val, off);
+        d.b = ok ? b : 0.0;
+        d.a = CL ? 0.0 : __longlong_as_double(((long long)it.y << 32) | it.x);
+    }
+    return d;
+}
+
+// ================================================================ symbolic
+// Counts, per member row, its distinct output columns, and per unit the
+// distinct columns of the union (used to size the numeric tables) and their
+// smallest and largest value (used by the numeric phase's hash).  Keys go
+// into a power-of-two open-addressing table with a multiplicative hash; the
+// table has at least as many slots as the unit has products, so it never
+// fills.  For clusters each key carries the OR of the masks of the columns k
+// that reached it: row l's count is the number of keys with bit l set.
+template <int S, bool CL>
+__global__ void __launch_bounds__(256) k_sym(SpArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = (int)__lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t ui = xcd_block() * (blockDim.x >> 6) + wib;
+    if (ui >= a.count) return;
+    const int u = a.order[a.bin_begin + ui];
+    const int T = a.T;
+    const SymLayout L(CL, T);
+    unsigned char *base = smem + (size_t)wib * a.group_bytes;
+    int *keys = (int *)(base + L.keys);
+    uint32_t *masks = (uint32_t *)(base + L.masks);
+    ItemRec *items = (ItemRec *)(base + L.items);
+    uint64_t *sbits = (uint64_t *)(base + L.sbits);
+    for (int i = lane; i <= T; i += 64) {
+        keys[i] = i == T ? kDummyKey : kEmpty;
+        if (CL) masks[i] = 0u;
+    }
+    const UnitView v = unit_view<CL>(a, u);
+    const uint32_t hmask = (uint32_t)T - 1u;
+    const int hshift = 32 - a.log2T;
+    const uint64_t le = lanemask_le(lane);
+    int inserted = 0;
+    int kmin = INT_MAX, kmax = -1;
+    int64_t q0 = v.it0;
+    int off0 = 0;
+
+    // one compare-and-swap takes an empty slot or confirms the key already
+    // there; only collisions walk on
+    auto probe = [&](const Pass<CL, false> &d) {
+        uint32_t h = d.j == kDummyKey ? (uint32_t)T : ((uint32_t)d.j * 2654435761u) >> hshift;
+        int old = atomicCAS(&keys[h], kEmpty, d.j);
+        while (old != kEmpty && old != d.j) {
+            h = (h + 1u) & hmask;
+            old = atomicCAS(&keys[h], kEmpty, d.j);
+        }
+        inserted += old == kEmpty;
+        if (CL) atomicOr(&masks[h], d.m);
+    };
+
+    constexpr int kR = 8;
+    while (q0 < v.it1) {
+        const int E = load_round<CL, S, false>(a, v, q0, off0, items, sbits, nullptr);
+        const int npass = (E + 63) >> 6;
+        int cum = 0, p = 0;
+        for (; p + kR <= npass; p += kR) {
+            Pass<CL, false> d[kR];
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr) {
+                const uint64_t w = uniform64(sbits[p + rr]);
+                d[rr] = fetch_pass<CL, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                cum += __popcll(w);
+            }
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr) {
+                if (d[rr].j != kDummyKey) {
+                    kmin = min(kmin, d[rr].j);
+                    kmax = max(kmax, d[rr].j);
+                }
+                probe(d[rr]);
+            }
+        }
+        for (; p < npass; ++p) {
+            const uint64_t w = uniform64(sbits[p]);
+            const Pass<CL, false> d = fetch_pass<CL, false>(a, items, w, cum, (p << 6) + lane, E, le);
+            cum += __popcll(w);
+            if (d.j != kDummyKey) {
+                kmin = min(kmin, d.j);
+                kmax = max(kmax, d.j);
+            }
+            probe(d);
+        }
+    }
+    int U = inserted;
+    for (int o = 32; o > 0; o >>= 1) {
+        U += __shfl_xor(U, o);
+        kmin = min(kmin, __shfl_xor(kmin, o));
+        kmax = max(kmax, __shfl_xor(kmax, o));
+    }
+    if (lane == 0) {
+        a.keylo[u] = kmin;
+        a.keyhi[u] = kmax;
+    }
+    if (!CL) {
+        if (lane == 0) {
+            a.c_rp[u] = U;
+            a.ucount[u] = U;
+        }
+        return;
+    }
+    int cnt[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) cnt[l] = 0;
+    for (int c0 = 0; c0 < T; c0 += 64) {
+        const int sidx = c0 + lane;
+        const bool occ = sidx < T && keys[sidx] != kEmpty;
+        const uint32_t mm = occ ? masks[sidx] : 0u;
+#pragma unroll
+        for (int l = 0; l < S; ++l) cnt[l] += __popcll(__ballot((mm >> l) & 1u));
+    }
+    if (lane < v.s && lane < S) {
+        int c = 0;
+#pragma unroll
+        for (int l = 0; l < S; ++l)
+            if (l == lane) c = cnt[l];
+        a.c_rp[member_row<CL>(a, v, lane)] = c;
+    }
+    if (lane == 0) a.ucount[u] = U;
+}
+
+// ================================================================ numeric
+// Keys go into a table of T slots plus a short tail, placed by an
+// order-preserving hash h(j) = floor((j - lo) * T / (hi - lo + 1)) (lo/hi:
+// the unit's smallest and largest output column) with linear probing.
+// Because h never decreases with j and probing only moves forward, the
+// occupied slots form runs whose keys are all smaller than the keys of any
+// later run: a key x stored past an empty slot e must have h(x) > e, which
+// bounds every key stored before e.  Sorting a row therefore only needs each
+// key's rank inside its run.  If a probe ever wraps past the tail that order
+// is lost and ranks are computed by full comparison instead.
+template <int S, bool CL>
+__global__ void __launch_bounds__(256) k_num(SpArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = (int)__lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t ui = xcd_block() * (blockDim.x >> 6) + wib;
+    if (ui >= a.count) return;
+    const int u = a.order[a.bin_begin + ui];
+    if (u < a.unit_lo || u >= a.unit_hi) return;
+
+    const int T = a.T, TX = a.T + kTail;
+    const NumLayout L(CL, S, TX);
+    unsigned char *base = smem + (size_t)wib * a.group_bytes;
+    int *keys = (int *)(base + L.keys);
+    uint32_t *masks = (uint32_t *)(base + L.masks);
+    double *vals = (double *)(base + L.vals);
+    double *aval = (double *)(base + L.aval);
+    uint16_t *order = (uint16_t *)(base + L.order);
+    ItemRec *items = (ItemRec *)(base + L.items);
+    uint64_t *sbits = (uint64_t *)(base + L.sbits);
+    uint64_t *occw = (uint64_t *)(base + L.occw);
+    int *pre = (int *)(base + L.pre);
+    const int VS = TX + 1;  // value column stride (slots incl. the dummy)
+
+    const UnitView v = unit_view<CL>(a, u);
+    for (int i = lane; i <= TX; i += 64) {
+        keys[i] = i == TX ? kDummyKey : kEmpty;
+        if (CL) masks[i] = 0u;
+#pragma unroll
+        for (int l = 0; l < S; ++l)
+            if (l < v.s) vals[l * VS + i] = 0.0;
+    }
+    const int lo = a.keylo[u], hi = a.keyhi[u];
+    const float scale = __fdividef((float)T, (float)(uint32_t)(hi - lo + 1));
+    const uint64_t le = lanemask_le(lane);
+    int wrapped = 0;
+    int64_t q0 = v.it0;
+    int off0 = 0;
+
+    auto probe = [&](int j) -> int {
+        if (j == kDummyKey) return TX;
+        int h = (int)((float)(uint32_t)(j - lo) * scale);
+        h = h < T ? h : T - 1;
+        int old = atomicCAS(&keys[h], kEmpty, j);
+        while (old != kEmpty && old != j) {
+            if (++h == TX) {
+                h = 0;
+                wrapped = 1;
+            }
+            old = atomicCAS(&keys[h], kEmpty, j);
+        }
+        return h;
+    };
+    // products of one pass, applied item by item (ascending k)
+    auto apply = [&](const Pass<CL, true> &d, int h, int tf, int tl) {
+        for (int tt = tf; tt <= tl; ++tt) {
+            if (d.t != tt) continue;
+            if (CL) {
+                const uint32_t mt = (uint32_t)uniform((int)items[tt].x);
+                const int src = uniform((int)items[tt].y);
+                masks[h] |= mt;
+#pragma unroll
+                for (int l = 0; l < S; ++l) {
+                    if ((mt >> l) & 1u) {
+                        double *pv = &vals[l * VS + h];
+                        *pv = __fma_rn(aval[src * S + l], d.b, *pv);
+                    }
+                }
+            } else {
+                vals[h] = __fma_rn(d.a, d.b, vals[h]);
+            }
+        }
+    };
+
+    constexpr int kR = Depth<S>::R;
+    while (q0 < v.it1) {
+        const int E = load_round<CL, S, true>(a, v, q0, off0, items, sbits, aval);
+        const int npass = (E + 63) >> 6;
+        int cum = 0, p = 0;
+        for (; p + kR <= npass; p += kR) {
+            Pass<CL, true> d[kR];
+            int tf[kR], tl[kR];
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr) {
+                const uint64_t w = uniform64(sbits[p + rr]);
+                const int last = min(63, E - 1 - ((p + rr) << 6));
+                tf[rr] = cum + (int)(w & 1ull) - 1;
+                tl[rr] = cum + __popcll(w & lanemask_le(last)) - 1;
+                d[rr] = fetch_pass<CL, true>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                cum += __popcll(w);
+            }
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr) apply(d[rr], probe(d[rr].j), tf[rr], tl[rr]);
+        }
+        for (; p < npass; ++p) {
+            const uint64_t w = uniform64(sbits[p]);
+            const int last = min(63, E - 1 - (p << 6));
+            const int tf = cum + (int)(w & 1ull) - 1;
+            const int tl = cum + __popcll(w & lanemask_le(last)) - 1;
+            const Pass<CL, true> d = fetch_pass<CL, true>(a, items, w, cum, (p << 6) + lane, E, le);
+            cum += __popcll(w);
+            apply(d, probe(d.j), tf, tl);
+        }
+    }
+
+    // ---- rank every key; runs of occupied slots are ordered among themselves
+    wrapped = __ballot(wrapped) != 0ull;
+    const int nw = (TX + 63) >> 6;
+    int U = 0;
+    for (int c = 0; c < nw; ++c) {
+        const int sidx = (c << 6) + lane;
+        const uint64_t bal = __ballot(sidx < TX && keys[sidx] != kEmpty);
+        if (lane == 0) {
+            occw[c] = bal;
+            pre[c] = U;
+        }
+        U += __popcll(bal);
+    }
+    for (int c = 0; c < nw; ++c) {
+        const int sidx = (c << 6) + lane;
+        const uint64_t w = occw[c];
+        if (!((w >> lane) & 1ull)) continue;
+        const int key = keys[sidx];
+        int rank;
+        if (!wrapped) {
+            int rs;
+            const uint64_t fb = ~w & lanemask_lt(lane);
+            if (fb) {
+                rs = (c << 6) + 64 - __clzll((long long)fb);
+            } else {
+                int cc = c - 1;
+                while (cc >= 0 && occw[cc] == ~0ull) --cc;
+                rs = cc < 0 ? 0 : (cc << 6) + 64 - __clzll((long long)~occw[cc]);
+            }
+            int re;
+            const uint64_t fa = ~w & ~lanemask_le(lane);
+            if (fa) {
+                re = (c << 6) + __ffsll((unsigned long long)fa) - 1;
+            } else {
+                int cc = c + 1;
+                while (cc < nw && occw[cc] == ~0ull) ++cc;
+                re = cc >= nw ? TX : (cc << 6) + __ffsll((unsigned long long)~occw[cc]) - 1;
+                if (re > TX) re = TX;
+            }
+            int rk = 0;
+            for (int x = rs; x < re; ++x) rk += keys[x] < key;
+            const int rc = rs >> 6;
+            rank = pre[rc] + __popcll(occw[rc] & lanemask_lt(rs & 63)) + rk;
+        } else {
+            rank = 0;
+            for (int x = 0; x < TX; ++x) {
+                const int kx = keys[x];
+                rank += (kx != kEmpty) & (kx < key);
+            }
+        }
+        order[rank] = (uint16_t)sidx;
+    }
+
+    // ---- write each member row's entries in column order
+    if (!CL) {
+        const int64_t row = v.pos0;
+        const int64_t o0 = a.c_rp[row] - a.out_base;
+        const int64_t want = a.c_rp[row + 1] - a.c_rp[row];
+        for (int i = lane; i < U; i += 64) {
+            const int sl = order[i];
+            const int64_t dst = o0 + i;
+            if (dst >= 0 && dst < a.cap && i < want) {
+                a.c_col[dst] = keys[sl];
+                a.c_val[dst] = vals[sl];
+            } else {
+                atomicOr(a.err, kErrCapacity);
+            }
+        }
+        if (lane == 0 && U != want) atomicOr(a.err, kErrCount);
+        return;
+    }
+    int64_t my_off = 0, my_want = 0;
+    if (lane < v.s) {
+        const int64_t row = member_row<CL>(a, v, lane);
+        my_off = a.c_rp[row] - a.out_base;
+        my_want = a.c_rp[row + 1] - a.c_rp[row];
+    }
+    for (int l = 0; l < v.s; ++l) {
+        const int64_t roff = readlane_i64(my_off, l), rwant = readlane_i64(my_want, l);
+        int64_t w = 0;
+        for (int c0 = 0; c0 < U; c0 += 64) {
+            const int i = c0 + lane;
+            const int sl = i < U ? (int)order[i] : TX;
+            const bool has = (masks[sl] >> l) & 1u && i < U;
+            const uint64_t bal = __ballot(has);
+            if (has) {
+                const int64_t pos = w + __popcll(bal & lanemask_lt(lane));
+                const int64_t dst = roff + pos;
+                if (dst >= 0 && dst < a.cap && pos < rwant) {
+                    a.c_col[dst] = keys[sl];
+                    a.c_val[dst] = vals[l * VS + sl];
+                } else {
+                    atomicOr(a.err, kErrCapacity);
+                }
+            }
+            w += __popcll(bal);
+        }
+        if (lane == 0 && w != rwant) atomicOr(a.err, kErrCount);
+    }
+}
+
+// ================================================================ launchers
+template <int S, bool CL>
+static hipError_t go_sym(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sym<S, CL>), dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int S, bool CL>
+static hipError_t go_num(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_num<S, CL>), dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym(int sclass, bool cluster, const SpArgs &a, int blocks, int threads, size_t lds,
+                      hipStream_t s)
+{
+    if (!cluster) return go_sym<1, false>(a, blocks, threads, lds, s);
+    switch (sclass) {
+    case 0: return go_sym<1, true>(a, blocks, threads, lds, s);
+    case 1: return go_sym<2, true>(a, blocks, threads, lds, s);
+    case 2: return go_sym<4, true>(a, blocks, threads, lds, s);
+    case 3: return go_sym<8, true>(a, blocks, threads, lds, s);
+    default: return go_sym<16, true>(a, blocks, threads, lds, s);
+    }
+}
+
+hipError_t launch_num(int sclass, bool cluster, const SpArgs &a, int blocks, int threads, size_t lds,
+                      hipStream_t s)
+{
+    if (!cluster) return go_num<1, false>(a, blocks, threads, lds, s);
+    switch (sclass) {
+    case 0: return go_num<1, true>(a, blocks, threads, lds, s);
+    case 1: return go_num<2, true>(a, blocks, threads, lds, s);
+    case 2: return go_num<4, true>(a, blocks, threads, lds, s);
+    case 3: return go_num<8, true>(a, blocks, threads, lds, s);
+    default: return go_num<16, true>(a, blocks, threads, lds, s);
+    }
+}
+
+}  // namespace hcsp

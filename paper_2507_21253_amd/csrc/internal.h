@@ -38,7 +38,8 @@ constexpr int kSymBins = 2 + kSClasses * kSymT;   // + empty + global
 constexpr int kNumBins = 2 + kSClasses * kNumT;
 constexpr int kSymGlobal = kSymBins - 1;
 constexpr int kNumGlobal = kNumBins - 1;
-constexpr int kTail = 32;                    // numeric probe tail past the hashed range
+constexpr int kTail = 32;
+constexpr int kBinBlocks = 4096;            // blocks of the binning kernels                    // numeric probe tail past the hashed range
 static_assert(kSymBins <= HCSP_MAX_BINS && kNumBins <= HCSP_MAX_BINS, "bin count");
 
 __host__ __device__ inline int num_table(int t)
@@ -52,27 +53,13 @@ __host__ __device__ inline int sclass_of(int s)
     return s <= 1 ? 0 : s <= 2 ? 1 : s <= 4 ? 2 : s <= 8 ? 3 : 4;
 }
 
-// Shared-memory bytes of one group's tables.
-__host__ __device__ inline int64_t sym_group_bytes(bool cl, int T)
-{
-    return (int64_t)T * (cl ? 8 : 4);                           // key (+ row mask)
-}
-__host__ __device__ inline int64_t num_group_bytes(bool cl, int sclass, int T, int G)
-{
-    const int S = 1 << sclass;
-    const int64_t TX = (int64_t)T + kTail;
-    int64_t b = TX * 4;                                         // keys
-    if (cl) b += TX * 4;                                        // row masks
-    b = (b + 7) & ~7ll;
-    b += TX * 8 * S;                                            // values, one column per member row
-    b += (int64_t)G * S * 8;                                    // the current items' A values
-    b += TX * 2;                                                // sorted slot order
-    return (b + 15) & ~15ll;
-}
+// Shared-memory bytes of one wavefront's tables (layouts in hash.hip).
+int64_t sym_wave_bytes(bool cl, int T);
+int64_t num_wave_bytes(bool cl, int sclass, int T);
 
 // Tuning derived from hcsp_opts.
 struct Tune {
-    int G;               // lanes per group
+    int G;               // lanes per unit (one wavefront)
     int load_pct;        // numeric table fill target
     int sym_tmax_log2;   // largest symbolic table
     int num_tmax;        // largest numeric table
@@ -91,7 +78,7 @@ struct Workspace {
     // counters
     int64_t *sym_count;  // [HCSP_MAX_BINS]
     int64_t *num_count;
-    int64_t *cursor;     // [HCSP_MAX_BINS] scatter cursors
+    int32_t *bin_hist;   // [kBinBlocks][HCSP_MAX_BINS] per-block bin counts, then scatter offsets
     uint32_t *err;       // error flags
     int64_t *scan_tmp;   // block sums of the scan
     // dense path
@@ -126,7 +113,7 @@ struct SpArgs {
     // units of this launch
     const int32_t *order;
     int64_t bin_begin, count;
-    const int32_t *keylo, *keyhi;
+    int32_t *keylo, *keyhi;    // smallest / largest output column of each unit (symbolic writes)
     int32_t *ucount;
     // C
     int64_t *c_rp;
@@ -177,8 +164,9 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s);
 hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
-hipError_t launch_scatter(const uint8_t *bin, int64_t n, const int64_t *counts, int64_t *cursor, int nbins,
-                          int32_t *order, hipStream_t s);
+hipError_t launch_scatter(const uint8_t *bin, int64_t n, int32_t *hist, int nbins, int64_t *counts, int32_t *order,
+                          hipStream_t s);
+int bin_blocks(int64_t nunits);
 hipError_t launch_scan_exclusive(int64_t *data, int64_t n, int64_t *tmp, hipStream_t s);
 size_t scan_tmp_elems(int64_t n);
 hipError_t launch_csr_check(const hcsp_csr &A, uint32_t *flags, hipStream_t s);

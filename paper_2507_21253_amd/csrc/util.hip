@@ -1,6 +1,7 @@
 // Support kernels: fills, per-unit work estimate and binning, counting-sort
 // scatter of units into bins, a device-wide exclusive scan (int64), and CSR
 // validation.
+#include <algorithm>
 #include <climits>
 
 #include "device.h"
@@ -46,9 +47,21 @@ __device__ __forceinline__ int sym_bin(int sc, int64_t probes, int tmax_log2)
     return 1 + sc * kSymT + (l - kSymLog2Min);
 }
 
+// Units are split into kBinBlocks contiguous chunks, one per block.  Each
+// block counts its units per bin in shared memory and stores the counts as
+// one row of a [blocks x bins] matrix (no global atomics); k_binscan turns
+// the matrix into per-block starting offsets, and k_scatter places units so
+// that a bin lists the units of block 0 first, then block 1, and so on.
+__device__ __forceinline__ void chunk_of(int64_t n, int64_t *b, int64_t *e)
+{
+    const int64_t ch = (n + gridDim.x - 1) / gridDim.x;
+    *b = min(n, (int64_t)blockIdx.x * ch);
+    *e = min(n, *b + ch);
+}
+
 // One group of 16 lanes per unit: probes = sum of |B_k| over the unit's
-// columns k (an upper bound on its distinct output columns), the smallest
-// and largest output column it can reach, and its symbolic bin.  Units with
+// columns k (an upper bound on its distinct output columns) and its
+// symbolic bin.  Units with
 // no products get their zero row counts here.
 template <bool CL>
 __global__ void __launch_bounds__(256) k_work(BinArgs a)
@@ -57,8 +70,9 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
     for (int i = threadIdx.x; i < kSymBins; i += blockDim.x) hist[i] = 0;
     __syncthreads();
     const Group g = make_group(16);
-    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    if (u < a.nunits) {
+    int64_t cb, ce;
+    chunk_of(a.nunits, &cb, &ce);
+    for (int64_t u = cb + (threadIdx.x >> 4); u < ce; u += blockDim.x >> 4) {
         int64_t it0, it1, pos0 = u;
         int s = 1;
         if (CL) {
@@ -71,25 +85,14 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
             it1 = a.a_rp[u + 1];
         }
         int64_t probes = 0;
-        int lo = INT_MAX, hi = -1;
         for (int64_t q = it0 + g.gl; q < it1; q += 16) {
             const int k = CL ? a.cl_col[q] : a.a_col[q];
-            const int64_t bs = a.b_rp[k], be = a.b_rp[k + 1];
-            if (be > bs) {
-                probes += be - bs;
-                lo = min(lo, a.b_col[bs]);
-                hi = max(hi, a.b_col[be - 1]);
-            }
+            probes += a.b_rp[k + 1] - a.b_rp[k];
         }
         probes = gsum64(g, probes);
-        lo = gmin32(g, lo);
-        hi = gmax32(g, hi);
-        const int sc = sclass_of(s);
-        const int bin = probes == 0 ? kBinEmpty : sym_bin(sc, probes, CL ? a.sym_tmax_log2 - 1 : a.sym_tmax_log2);
+        const int bin = probes == 0 ? kBinEmpty : sym_bin(sclass_of(s), probes, a.sym_tmax_log2);
         if (g.gl == 0) {
             a.ws.probes[u] = probes;
-            a.ws.keylo[u] = lo;
-            a.ws.keyhi[u] = hi;
             a.ws.bin[u] = (uint8_t)bin;
             atomicAdd(&hist[bin], 1);
             if (bin == kBinEmpty) {
@@ -99,16 +102,21 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kSymBins; i += blockDim.x)
-        if (hist[i]) atomicAdd((unsigned long long *)&a.ws.sym_count[i], (unsigned long long)hist[i]);
+    for (int i = threadIdx.x; i < kSymBins; i += blockDim.x) a.ws.bin_hist[(int64_t)blockIdx.x * HCSP_MAX_BINS + i] = hist[i];
+}
+
+int bin_blocks(int64_t nunits)
+{
+    const int64_t b = (nunits + 255) / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kBinBlocks, b));
 }
 
 hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s)
 {
     if (a.nunits <= 0) return hipSuccess;
-    const int64_t blocks = (a.nunits * 16 + 255) / 256;
-    if (cluster) hipLaunchKernelGGL((k_work<true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_work<false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const int blocks = bin_blocks(a.nunits);
+    if (cluster) hipLaunchKernelGGL((k_work<true>), dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_work<false>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -120,8 +128,9 @@ __global__ void __launch_bounds__(256) k_numbin(BinArgs a)
     __shared__ int hist[kNumBins];
     for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < a.nunits) {
+    int64_t cb, ce;
+    chunk_of(a.nunits, &cb, &ce);
+    for (int64_t u = cb + threadIdx.x; u < ce; u += blockDim.x) {
         const int s = CL ? (int)(a.cl_row_ptr[u + 1] - a.cl_row_ptr[u]) : 1;
         const int sc = sclass_of(s);
         const int32_t U = a.ws.ucount[u];
@@ -146,59 +155,79 @@ __global__ void __launch_bounds__(256) k_numbin(BinArgs a)
         atomicAdd(&hist[bin], 1);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kNumBins; i += blockDim.x)
-        if (hist[i]) atomicAdd((unsigned long long *)&a.ws.num_count[i], (unsigned long long)hist[i]);
+    for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) a.ws.bin_hist[(int64_t)blockIdx.x * HCSP_MAX_BINS + i] = hist[i];
 }
 
 hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s)
 {
     if (a.nunits <= 0) return hipSuccess;
-    const int64_t blocks = (a.nunits + 255) / 256;
-    if (cluster) hipLaunchKernelGGL((k_numbin<true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_numbin<false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const int blocks = bin_blocks(a.nunits);
+    if (cluster) hipLaunchKernelGGL((k_numbin<true>), dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_numbin<false>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-// Counting-sort scatter: unit u goes to order[start(bin) + slot].  Each
-// block ranks its units per bin in shared memory and reserves one range per
-// bin with a single atomic, so units of one block stay adjacent.
-__global__ void __launch_bounds__(256) k_scatter(const uint8_t *bin, int64_t n, const int64_t *counts,
-                                                 int64_t *cursor, int nbins, int32_t *order)
+// Column b of the [blocks x bins] count matrix becomes its exclusive prefix
+// (the offset of each block inside bin b), and counts[b] its total.
+__global__ void __launch_bounds__(1024) k_bincol(int32_t *hist, int nblocks, int64_t *counts)
 {
-    __shared__ int64_t start[HCSP_MAX_BINS];
-    __shared__ int local[HCSP_MAX_BINS];
-    __shared__ int64_t base[HCSP_MAX_BINS];
+    __shared__ int wsum[16];
+    const int b = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int carry = 0;
+    for (int c0 = 0; c0 < nblocks; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nblocks ? hist[(int64_t)i * HCSP_MAX_BINS + b] : 0;
+        int inc = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        int wb = 0, tot = 0;
+        for (int x = 0; x < 16; ++x) {
+            if (x < w) wb += wsum[x];
+            tot += wsum[x];
+        }
+        if (i < nblocks) hist[(int64_t)i * HCSP_MAX_BINS + b] = carry + wb + inc - v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[b] = carry;
+}
+
+// Scatter: each block hands out positions from its own per-bin offsets
+// (bin start + the block's offset inside the bin).
+__global__ void __launch_bounds__(256) k_scatter(const uint8_t *bin, int64_t n, const int32_t *hist, int nbins,
+                                                 const int64_t *counts, int32_t *order)
+{
+    __shared__ int cursor[HCSP_MAX_BINS];
     if (threadIdx.x == 0) {
         int64_t acc = 0;
-        for (int b = 0; b < nbins; ++b) {
-            start[b] = acc;
-            acc += counts[b];
+        for (int x = 0; x < nbins; ++x) {
+            cursor[x] = (int)acc;
+            acc += counts[x];
         }
     }
-    for (int b = threadIdx.x; b < nbins; b += blockDim.x) local[b] = 0;
     __syncthreads();
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int b = -1, r = 0;
-    if (u < n) {
-        b = bin[u];
-        r = atomicAdd(&local[b], 1);
-    }
+    for (int x = threadIdx.x; x < nbins; x += blockDim.x) cursor[x] += hist[(int64_t)blockIdx.x * HCSP_MAX_BINS + x];
     __syncthreads();
-    for (int x = threadIdx.x; x < nbins; x += blockDim.x)
-        base[x] = local[x] ? (int64_t)atomicAdd((unsigned long long *)&cursor[x], (unsigned long long)local[x]) : 0;
-    __syncthreads();
-    if (u < n) {
-        const int64_t pos = start[b] + base[b] + r;
+    int64_t cb, ce;
+    chunk_of(n, &cb, &ce);
+    for (int64_t u = cb + threadIdx.x; u < ce; u += blockDim.x) {
+        const int b = bin[u];
+        const int pos = atomicAdd(&cursor[b], 1);
         if (pos >= 0 && pos < n) order[pos] = (int32_t)u;
     }
 }
 
-hipError_t launch_scatter(const uint8_t *bin, int64_t n, const int64_t *counts, int64_t *cursor, int nbins,
-                          int32_t *order, hipStream_t s)
+hipError_t launch_scatter(const uint8_t *bin, int64_t n, int32_t *hist, int nbins, int64_t *counts, int32_t *order,
+                          hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, bin, n, counts, cursor,
-                       nbins, order);
+    const int blocks = bin_blocks(n);
+    hipLaunchKernelGGL(k_bincol, dim3(nbins), dim3(1024), 0, s, hist, blocks, counts);
+    hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, s, bin, n, hist, nbins, counts, order);
     return hipGetLastError();
 }
 

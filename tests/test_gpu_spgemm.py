@@ -77,11 +77,25 @@ def test_relabelled_stencil_bitwise():
     assert_same(gpu_product(Md, Md), oracle.spgemm(M, M))
 
 
-@pytest.mark.parametrize("lanes", [8, 16, 32, 64])
-def test_lane_group_sizes(lanes):
+@pytest.mark.parametrize("d", [1, 3, 9, 40, 130])
+def test_row_length_mix(d):
+    # B rows from 1 to 130 entries: items shorter and longer than a 64-lane pass
     A = synth.uniform(700, 500, 9, 5)
-    B = synth.uniform(500, 900, 21, 6)
-    assert_same(gpu_product(to_dev(A), to_dev(B), hc.opts(lanes=lanes)), oracle.spgemm(A, B))
+    B = synth.uniform(500, 900, d, 6)
+    assert_same(gpu_product(to_dev(A), to_dev(B), hc.opts(lanes=64)), oracle.spgemm(A, B))
+
+
+def test_long_items_cross_rounds():
+    # rows whose products exceed one 4096-entry round, items cut across rounds
+    A = synth.uniform(40, 3000, 60, 7)
+    B = synth.uniform(3000, 5000, 150, 8)
+    assert_same(gpu_product(to_dev(A), to_dev(B)), oracle.spgemm(A, B))
+
+
+def test_bad_lanes_rejected():
+    A = to_dev(synth.uniform(10, 10, 2, 1))
+    with pytest.raises(hc.HcspError):
+        hc.spgemm(A, A, hc.opts(lanes=32))
 
 
 def plans_for(A):
