@@ -33,7 +33,7 @@ namespace hcsp {
 // per-member updates need more registers)
 template <int S>
 struct Depth {
-    static constexpr int R = S >= 8 ? 2 : (S >= 4 ? 4 : 8);
+    static constexpr int R = S >= 8 ? 2 : (S >= 4 ? 4 : 6);
 };
 constexpr int kRoundW = 4096;               // products per round
 constexpr int kRoundPasses = kRoundW / 64;  // == 64: one start-bit word per lane
@@ -99,22 +99,23 @@ __device__ __forceinline__ double ld_val(const double *base, uint32_t off)
 // ---------------------------------------------------------------- LDS layout
 // Slot counts include one reserved dummy slot at the end.
 struct SymLayout {
-    int keys, masks, items, sbits, bytes;
+    int keys, masks, mcnt, items, sbits, bytes;
     __host__ __device__ SymLayout(bool cl, int T)
     {
         keys = 0;
         masks = keys + 4 * (T + 1);
-        items = (masks + (cl ? 4 * (T + 1) : 0) + 15) & ~15;
+        mcnt = masks + (cl ? 4 * (T + 1) : 0);
+        items = (mcnt + (cl ? 4 * 16 : 0) + 15) & ~15;
         sbits = items + 16 * 64;
         bytes = (sbits + 8 * kRoundPasses + 15) & ~15;
     }
 };
 
 struct NumLayout {
-    int keys, masks, vals, aval, order, items, sbits, occw, pre, bytes;
+    int keys, masks, vals, aval, order, items, sbits, hcnt, hpre, bytes;
     __host__ __device__ NumLayout(bool cl, int S, int TX)
     {
-        const int nw = (TX + 63) / 64;
+        const int T = TX - kTail;
         keys = 0;
         masks = keys + 4 * (TX + 1);
         vals = (masks + (cl ? 4 * (TX + 1) : 0) + 15) & ~15;
@@ -122,9 +123,9 @@ struct NumLayout {
         order = aval + (cl ? 8 * S * 64 : 0);
         items = (order + 2 * TX + 15) & ~15;
         sbits = items + 16 * 64;
-        occw = sbits + 8 * kRoundPasses;
-        pre = occw + 8 * nw;
-        bytes = (pre + 4 * nw + 15) & ~15;
+        hcnt = sbits + 8 * kRoundPasses;
+        hpre = hcnt + 4 * T;
+        bytes = (hpre + 4 * T + 15) & ~15;
     }
 };
 
@@ -245,7 +246,8 @@ __device__ __forceinline__ Pass<CL, NUM> fetch_pass(const SpArgs &a, const ItemR
 // into a power-of-two open-addressing table with a multiplicative hash; the
 // table has at least as many slots as the unit has products, so it never
 // fills.  For clusters each key carries the OR of the masks of the columns k
-// that reached it: row l's count is the number of keys with bit l set.
+// that reached it: row l's count is the number of keys whose bit l got set,
+// counted when the bit first appears.
 template <int S, bool CL>
 __global__ void __launch_bounds__(256) k_sym(SpArgs a)
 {
@@ -260,12 +262,14 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
     unsigned char *base = smem + (size_t)wib * a.group_bytes;
     int *keys = (int *)(base + L.keys);
     uint32_t *masks = (uint32_t *)(base + L.masks);
+    int *mcnt = (int *)(base + L.mcnt);
     ItemRec *items = (ItemRec *)(base + L.items);
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
     for (int i = lane; i <= T; i += 64) {
         keys[i] = i == T ? kDummyKey : kEmpty;
         if (CL) masks[i] = 0u;
     }
+    if (CL && lane < 16) mcnt[lane] = 0;
     const UnitView v = unit_view<CL>(a, u);
     const uint32_t hmask = (uint32_t)T - 1u;
     const int hshift = 32 - a.log2T;
@@ -285,7 +289,15 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
             old = atomicCAS(&keys[h], kEmpty, d.j);
         }
         inserted += old == kEmpty;
-        if (CL) atomicOr(&masks[h], d.m);
+        if (CL) {
+            // member rows that see this column for the first time
+            uint32_t fresh = d.m & ~atomicOr(&masks[h], d.m);
+            if (h == (uint32_t)T) fresh = 0u;
+            while (fresh) {
+                atomicAdd(&mcnt[__ffs(fresh) - 1], 1);
+                fresh &= fresh - 1u;
+            }
+        }
     };
 
     constexpr int kR = 8;
@@ -338,23 +350,7 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
         }
         return;
     }
-    int cnt[S];
-#pragma unroll
-    for (int l = 0; l < S; ++l) cnt[l] = 0;
-    for (int c0 = 0; c0 < T; c0 += 64) {
-        const int sidx = c0 + lane;
-        const bool occ = sidx < T && keys[sidx] != kEmpty;
-        const uint32_t mm = occ ? masks[sidx] : 0u;
-#pragma unroll
-        for (int l = 0; l < S; ++l) cnt[l] += __popcll(__ballot((mm >> l) & 1u));
-    }
-    if (lane < v.s && lane < S) {
-        int c = 0;
-#pragma unroll
-        for (int l = 0; l < S; ++l)
-            if (l == lane) c = cnt[l];
-        a.c_rp[member_row<CL>(a, v, lane)] = c;
-    }
+    if (lane < v.s) a.c_rp[member_row<CL>(a, v, lane)] = mcnt[lane];
     if (lane == 0) a.ucount[u] = U;
 }
 
@@ -362,12 +358,11 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
 // Keys go into a table of T slots plus a short tail, placed by an
 // order-preserving hash h(j) = floor((j - lo) * T / (hi - lo + 1)) (lo/hi:
 // the unit's smallest and largest output column) with linear probing.
-// Because h never decreases with j and probing only moves forward, the
-// occupied slots form runs whose keys are all smaller than the keys of any
-// later run: a key x stored past an empty slot e must have h(x) > e, which
-// bounds every key stored before e.  Sorting a row therefore only needs each
-// key's rank inside its run.  If a probe ever wraps past the tail that order
-// is lost and ranks are computed by full comparison instead.
+// Because h never decreases with j, a key's rank among the unit's keys is
+// the number of keys whose home slot is lower (a prefix sum of per-home
+// counts kept while inserting) plus the smaller keys with the same home,
+// which all lie on the probe path from that home; no sort is needed, and a
+// CSR row's entries are written straight to their final positions.
 template <int S, bool CL>
 __global__ void __launch_bounds__(256) k_num(SpArgs a)
 {
@@ -389,13 +384,14 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
     uint16_t *order = (uint16_t *)(base + L.order);
     ItemRec *items = (ItemRec *)(base + L.items);
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
-    uint64_t *occw = (uint64_t *)(base + L.occw);
-    int *pre = (int *)(base + L.pre);
-    const int VS = TX + 1;  // value column stride (slots incl. the dummy)
+    int *hcnt = (int *)(base + L.hcnt);
+    int *hpre = (int *)(base + L.hpre);
 
+    const int VS = TX + 1;  // value column stride (slots incl. the dummy)
     const UnitView v = unit_view<CL>(a, u);
     for (int i = lane; i <= TX; i += 64) {
         keys[i] = i == TX ? kDummyKey : kEmpty;
+        if (i < T) hcnt[i] = 0;
         if (CL) masks[i] = 0u;
 #pragma unroll
         for (int l = 0; l < S; ++l)
@@ -404,22 +400,23 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
     const int lo = a.keylo[u], hi = a.keyhi[u];
     const float scale = __fdividef((float)T, (float)(uint32_t)(hi - lo + 1));
     const uint64_t le = lanemask_le(lane);
-    int wrapped = 0;
     int64_t q0 = v.it0;
     int off0 = 0;
 
+    auto home = [&](int j) -> int {
+        const int h = (int)((float)(uint32_t)(j - lo) * scale);
+        return h < T ? h : T - 1;
+    };
     auto probe = [&](int j) -> int {
         if (j == kDummyKey) return TX;
-        int h = (int)((float)(uint32_t)(j - lo) * scale);
-        h = h < T ? h : T - 1;
+        const int h0 = home(j);
+        int h = h0;
         int old = atomicCAS(&keys[h], kEmpty, j);
         while (old != kEmpty && old != j) {
-            if (++h == TX) {
-                h = 0;
-                wrapped = 1;
-            }
+            if (++h == TX) h = 0;
             old = atomicCAS(&keys[h], kEmpty, j);
         }
+        if (old == kEmpty) atomicAdd(&hcnt[h0], 1);
         return h;
     };
     // products of one pass, applied item by item (ascending k)
@@ -474,77 +471,54 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
         }
     }
 
-    // ---- rank every key; runs of occupied slots are ordered among themselves
-    wrapped = __ballot(wrapped) != 0ull;
-    const int nw = (TX + 63) >> 6;
+    // ---- rank every key.  h never decreases with j, so the keys smaller than
+    // x are exactly those with a lower home slot plus the smaller ones sharing
+    // x's home; the latter sit on x's probe path from that home on.
     int U = 0;
-    for (int c = 0; c < nw; ++c) {
-        const int sidx = (c << 6) + lane;
-        const uint64_t bal = __ballot(sidx < TX && keys[sidx] != kEmpty);
-        if (lane == 0) {
-            occw[c] = bal;
-            pre[c] = U;
-        }
-        U += __popcll(bal);
+    for (int c0 = 0; c0 < T; c0 += 64) {
+        const int i = c0 + lane;
+        const int cnt = i < T ? hcnt[i] : 0;
+        const int incl = wave_incl_scan(cnt);
+        if (i < T) hpre[i] = U + incl - cnt;
+        U += __shfl(incl, 63);
     }
-    for (int c = 0; c < nw; ++c) {
-        const int sidx = (c << 6) + lane;
-        const uint64_t w = occw[c];
-        if (!((w >> lane) & 1ull)) continue;
-        const int key = keys[sidx];
-        int rank;
-        if (!wrapped) {
-            int rs;
-            const uint64_t fb = ~w & lanemask_lt(lane);
-            if (fb) {
-                rs = (c << 6) + 64 - __clzll((long long)fb);
-            } else {
-                int cc = c - 1;
-                while (cc >= 0 && occw[cc] == ~0ull) --cc;
-                rs = cc < 0 ? 0 : (cc << 6) + 64 - __clzll((long long)~occw[cc]);
-            }
-            int re;
-            const uint64_t fa = ~w & ~lanemask_le(lane);
-            if (fa) {
-                re = (c << 6) + __ffsll((unsigned long long)fa) - 1;
-            } else {
-                int cc = c + 1;
-                while (cc < nw && occw[cc] == ~0ull) ++cc;
-                re = cc >= nw ? TX : (cc << 6) + __ffsll((unsigned long long)~occw[cc]) - 1;
-                if (re > TX) re = TX;
-            }
-            int rk = 0;
-            for (int x = rs; x < re; ++x) rk += keys[x] < key;
-            const int rc = rs >> 6;
-            rank = pre[rc] + __popcll(occw[rc] & lanemask_lt(rs & 63)) + rk;
-        } else {
-            rank = 0;
-            for (int x = 0; x < TX; ++x) {
-                const int kx = keys[x];
-                rank += (kx != kEmpty) & (kx < key);
-            }
-        }
-        order[rank] = (uint16_t)sidx;
-    }
-
-    // ---- write each member row's entries in column order
+    int64_t o0 = 0, want = 0;
     if (!CL) {
-        const int64_t row = v.pos0;
-        const int64_t o0 = a.c_rp[row] - a.out_base;
-        const int64_t want = a.c_rp[row + 1] - a.c_rp[row];
-        for (int i = lane; i < U; i += 64) {
-            const int sl = order[i];
-            const int64_t dst = o0 + i;
-            if (dst >= 0 && dst < a.cap && i < want) {
-                a.c_col[dst] = keys[sl];
-                a.c_val[dst] = vals[sl];
+        o0 = a.c_rp[v.pos0] - a.out_base;
+        want = a.c_rp[v.pos0 + 1] - a.c_rp[v.pos0];
+    }
+    for (int c0 = 0; c0 < TX; c0 += 64) {
+        const int sidx = c0 + lane;
+        const int key = sidx < TX ? keys[sidx] : kEmpty;
+        if (key == kEmpty) continue;
+        const int hx = home(key);
+        int rank = hpre[hx];
+        if (hcnt[hx] > 1) {
+            for (int x = hx;; x = x + 1 == TX ? 0 : x + 1) {
+                const int kx = keys[x];
+                if (kx == kEmpty) break;
+                rank += kx < key && home(kx) == hx;
+            }
+        }
+        if (CL) {
+            order[rank] = (uint16_t)sidx;
+        } else {
+            // a CSR row goes straight to its place in C
+            const int64_t dst = o0 + rank;
+            if (dst >= 0 && dst < a.cap && rank < want) {
+                a.c_col[dst] = key;
+                a.c_val[dst] = vals[sidx];
             } else {
                 atomicOr(a.err, kErrCapacity);
             }
         }
+    }
+    if (!CL) {
         if (lane == 0 && U != want) atomicOr(a.err, kErrCount);
         return;
     }
+
+    // ---- each member row's entries, in column order
     int64_t my_off = 0, my_want = 0;
     if (lane < v.s) {
         const int64_t row = member_row<CL>(a, v, lane);
