@@ -4,8 +4,9 @@
 Workload (default): C = M*M for M the 27-point stencil on a 100^3 grid with
 values U(-1,1), symmetrically relabelled by a seeded random permutation so
 the natural locality is gone.  Hierarchical clustering (Alg. 3, jacc_th 0.3,
-max cluster 8) then regroups similar rows into CSR_Cluster and the product
-runs cluster-wise (Alg. 1).  One step = symbolic phase (binning, counts,
+max cluster 2 by default, the fastest measured; the paper uses 8) then
+regroups similar rows into CSR_Cluster and the product runs cluster-wise
+(Alg. 1).  One step = symbolic phase (binning, counts,
 scan), the nnz read-back, and the numeric phase of the clustered product;
 the plain-CSR product of the same matrix is timed the same way for the
 comparison.  Clustering itself (host plan + device CSR_Cluster build) is
@@ -17,8 +18,10 @@ size (the calibration run for hardware byte counters).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -44,14 +47,34 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--m", type=int, default=100, help="stencil grid side")
-    p.add_argument("--max-cluster", type=int, default=8)
+    p.add_argument("--max-cluster", type=int, default=2)
     p.add_argument("--sim", choices=["root", "union"], default="root")
     p.add_argument("--lanes", type=int, default=0)
     p.add_argument("--mode", choices=["bench", "copy"], default="bench")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-threads", type=int, default=0)
-    p.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per numeric launch")
     return p.parse_args()
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_num_stencil27_100_relabelled.md")
+KERNEL_SOURCES = ["paper_2507_21253_amd/csrc/hash.hip", "paper_2507_21253_amd/csrc/dense.hip"]
+
+
+def numeric_traffic(key: str, config: str):
+    """HBM bytes of one numeric phase from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the copy-kernel calibration), or None when the numeric kernels' sources
+    changed since the counters were taken or they were taken on another configuration."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    m = re.search(r"traffic: clustered_numeric_bytes=(\d+) plain_numeric_bytes=(\d+) kernel_source=(\w+) "
+                  r"config=(\S+)", open(TRAFFIC_PROFILE).read())
+    if not m or m.group(3) != h.hexdigest()[:16] or m.group(4) != config:
+        return None
+    return int(m.group(1) if key == "clustered" else m.group(2))
 
 
 def copy_mode(args):
@@ -156,10 +179,7 @@ def main():
     gflops_pl = flop / (wall_pl * 1e-3) / 1e9
     # dominant kernel family: the numeric launches; its algorithmic bytes are A (clustered), B and C
     ach = comp_cl / (num_cl * 1e-3) / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        tr = json.load(open(args.traffic))
-        traffic = tr.get("numeric_hbm_bytes")
+    traffic = numeric_traffic("clustered", "m%d_mc%d_%s" % (m, args.max_cluster, args.sim))
 
     cpu = None
     if not args.no_cpu:

@@ -217,12 +217,20 @@ static BinArgs bin_args(const hcsp_operand *A, const hcsp_csr *B, const Workspac
     return b;
 }
 
-// Launch geometry for one bin: one wavefront per unit, up to four per block
-// as the block's shared-memory target allows.
+// Launch geometry for one bin: one wavefront per unit, one to four per block,
+// whichever lets the most wavefronts share a compute unit's 160 KiB of LDS
+// (ties go to the larger block).
 static void geometry(int64_t wave_bytes, int64_t count, int *blocks, int *threads, size_t *lds)
 {
-    const int64_t target = 64 * 1024;
-    const int64_t wpb = std::max<int64_t>(1, std::min<int64_t>(4, target / std::max<int64_t>(wave_bytes, 1)));
+    const int64_t cu_lds = 160 * 1024, wb = std::max<int64_t>(wave_bytes, 1);
+    int64_t wpb = 1, best = -1;
+    for (int64_t w = 4; w >= 1; w >>= 1) {
+        const int64_t resident = std::min<int64_t>(32, cu_lds / (w * wb) * w);
+        if (w * wb <= cu_lds && resident > best) {
+            best = resident;
+            wpb = w;
+        }
+    }
     *threads = (int)(wpb * 64);
     *lds = (size_t)(wpb * wave_bytes);
     *blocks = (int)((count + wpb - 1) / wpb);
@@ -397,7 +405,7 @@ int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
                 const int l2 = (b - 1) % kSymT + kSymLog2Min;
                 a.T = 1 << l2;
                 a.log2T = l2;
-                const int64_t gb = sym_wave_bytes(v.cluster, a.T);
+                const int64_t gb = sym_wave_bytes(v.cluster && sc > 0, a.T);
                 a.group_bytes = (int)gb;
                 int blocks, threads;
                 size_t lds;

@@ -39,6 +39,11 @@ constexpr int kRoundW = 4096;               // products per round
 constexpr int kRoundPasses = kRoundW / 64;  // == 64: one start-bit word per lane
 constexpr int kDummyKey = INT_MAX;          // key of the reserved slot used by idle lanes
 
+// Narrow clusters keep each item's member values of A in the registers of the
+// lane that loaded the item (read back by lane broadcast); wider ones stage
+// them in shared memory.
+__host__ __device__ constexpr bool a_in_regs(int S) { return S <= 4; }
+
 // 16-byte item record: one column k of the unit inside the current round.
 struct __align__(16) ItemRec {
     uint32_t bs;  // offset in B of the item's first product in this round
@@ -99,49 +104,48 @@ __device__ __forceinline__ double ld_val(const double *base, uint32_t off)
 // ---------------------------------------------------------------- LDS layout
 // Slot counts include one reserved dummy slot at the end.
 struct SymLayout {
-    int keys, masks, mcnt, items, sbits, bytes;
+    int keys, masks, items, sbits, bytes;
     __host__ __device__ SymLayout(bool cl, int T)
     {
         keys = 0;
         masks = keys + 4 * (T + 1);
-        mcnt = masks + (cl ? 4 * (T + 1) : 0);
-        items = (mcnt + (cl ? 4 * 16 : 0) + 15) & ~15;
+        items = (masks + (cl ? 4 * (T + 1) : 0) + 15) & ~15;
         sbits = items + 16 * 64;
         bytes = (sbits + 8 * kRoundPasses + 15) & ~15;
     }
 };
 
 struct NumLayout {
-    int keys, masks, vals, aval, order, items, sbits, hcnt, hpre, bytes;
+    int keys, masks, vals, aval, order, items, sbits, hcnt, bytes;
     __host__ __device__ NumLayout(bool cl, int S, int TX)
     {
         const int T = TX - kTail;
         keys = 0;
         masks = keys + 4 * (TX + 1);
+        cl = cl && S > 1;
         vals = (masks + (cl ? 4 * (TX + 1) : 0) + 15) & ~15;
         aval = vals + 8 * S * (TX + 1);
-        order = aval + (cl ? 8 * S * 64 : 0);
-        items = (order + 2 * TX + 15) & ~15;
+        order = aval + (cl && !a_in_regs(S) ? 8 * S * 64 : 0);
+        items = (order + (cl ? 2 * TX : 0) + 15) & ~15;
         sbits = items + 16 * 64;
         hcnt = sbits + 8 * kRoundPasses;
-        hpre = hcnt + 4 * T;
-        bytes = (hpre + 4 * T + 15) & ~15;
+        bytes = (hcnt + 4 * (T + 1) + 15) & ~15;
     }
 };
 
-int64_t sym_wave_bytes(bool cl, int T) { return SymLayout(cl, T).bytes; }
+int64_t sym_wave_bytes(bool multi, int T) { return SymLayout(multi, T).bytes; }
 int64_t num_wave_bytes(bool cl, int sclass, int T) { return NumLayout(cl, 1 << sclass, T + kTail).bytes; }
 
 // ---------------------------------------------------------------- rounds
 // Loads the next round of items into LDS: lane i takes column q0+i of the
 // unit; the non-empty ones are compacted, their products laid out back to
 // back (positions P), and a start bit set at each P.  For a cluster's numeric
-// phase lane i also stages the column's member values in aval[i*S ..].  An item longer than
+// phase lane i also keeps the column's member values (areg, or aval[i*S ..]).  An item longer than
 // what fits is cut and resumed in the next round (q0, off0 advance).
 // Returns the number of products in the round.
 template <bool CL, int S, bool NUM>
 __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, int64_t &q0, int &off0,
-                                          ItemRec *items, uint64_t *sbits, double *aval)
+                                          ItemRec *items, uint64_t *sbits, double *aval, double *areg)
 {
     const int lane = (int)__lane_id();
     sbits[lane] = 0ull;
@@ -152,17 +156,22 @@ __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, in
     double a1 = 0.0;
     if (q < v.it1) {
         const int k = CL ? a.cl_col[q] : a.a_col[q];
-        if (CL) m = a.cl_mask[q];
+        if (CL && S > 1) m = a.cl_mask[q];
         bs = a.b_rp[k];
         bl = (int)(a.b_rp[k + 1] - bs);
         if (NUM) {
-            if (CL) {
+            if (CL && S > 1) {
                 const double *src = a.cl_val + v.vbase + (q - v.it0) * v.s;
 #pragma unroll
-                for (int l = 0; l < S; ++l)
-                    if (l < v.s) aval[lane * S + l] = src[l];
+                for (int l = 0; l < S; ++l) {
+                    if (a_in_regs(S))
+                        areg[l] = l < v.s ? src[l] : 0.0;
+                    else if (l < v.s)
+                        aval[lane * S + l] = src[l];
+                }
             } else {
-                a1 = a.a_val[q];
+                // a CSR row, or a one-row cluster (its values are contiguous)
+                a1 = CL ? a.cl_val[v.vbase + (q - v.it0)] : a.a_val[q];
             }
         }
     }
@@ -180,7 +189,7 @@ __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, in
         ItemRec r;
         r.bs = (uint32_t)bs;
         r.P = P;
-        if (CL) {
+        if (CL && S > 1) {
             r.x = m;
             r.y = (uint32_t)lane;
         } else {
@@ -211,7 +220,7 @@ __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, in
 
 // One lane's share of one pass: its entry of the flattened product list.
 // Lanes past the end get the dummy key and read B at offset 0.
-template <bool CL, bool NUM>
+template <bool MS, bool NUM>
 struct Pass {
     int j;
     int t;        // item index (lanes past the end: the last item)
@@ -219,22 +228,22 @@ struct Pass {
     double b, a;
 };
 
-template <bool CL, bool NUM>
-__device__ __forceinline__ Pass<CL, NUM> fetch_pass(const SpArgs &a, const ItemRec *items, uint64_t w, int cum,
+template <bool MS, bool NUM>
+__device__ __forceinline__ Pass<MS, NUM> fetch_pass(const SpArgs &a, const ItemRec *items, uint64_t w, int cum,
                                                     int e, int E, uint64_t le)
 {
-    Pass<CL, NUM> d;
+    Pass<MS, NUM> d;
     d.t = cum + __popcll(w & le) - 1;
     const ItemRec it = items[d.t];
     const bool ok = e < E;
     const uint32_t off = ok ? it.bs + (uint32_t)(e - it.P) : 0u;
     const int j = ld_col(a.b_col, off);
     d.j = ok ? j : kDummyKey;
-    d.m = CL ? it.x : 1u;
+    d.m = MS ? it.x : 1u;
     if (NUM) {
         const double b = ld_val(a.b_val, off);
         d.b = ok ? b : 0.0;
-        d.a = CL ? 0.0 : __longlong_as_double(((long long)it.y << 32) | it.x);
+        d.a = MS ? 0.0 : __longlong_as_double(((long long)it.y << 32) | it.x);
     }
     return d;
 }
@@ -247,10 +256,11 @@ __device__ __forceinline__ Pass<CL, NUM> fetch_pass(const SpArgs &a, const ItemR
 // table has at least as many slots as the unit has products, so it never
 // fills.  For clusters each key carries the OR of the masks of the columns k
 // that reached it: row l's count is the number of keys whose bit l got set,
-// counted when the bit first appears.
+// counted (by ballot) when the bit first appears.
 template <int S, bool CL>
 __global__ void __launch_bounds__(256) k_sym(SpArgs a)
 {
+    constexpr bool MS = CL && S > 1;  // several member rows (masks needed)
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = (int)__lane_id();
     const int wib = threadIdx.x >> 6;
@@ -258,18 +268,19 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
     if (ui >= a.count) return;
     const int u = a.order[a.bin_begin + ui];
     const int T = a.T;
-    const SymLayout L(CL, T);
+    const SymLayout L(MS, T);
     unsigned char *base = smem + (size_t)wib * a.group_bytes;
     int *keys = (int *)(base + L.keys);
     uint32_t *masks = (uint32_t *)(base + L.masks);
-    int *mcnt = (int *)(base + L.mcnt);
     ItemRec *items = (ItemRec *)(base + L.items);
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
     for (int i = lane; i <= T; i += 64) {
         keys[i] = i == T ? kDummyKey : kEmpty;
-        if (CL) masks[i] = 0u;
+        if (MS) masks[i] = 0u;
     }
-    if (CL && lane < 16) mcnt[lane] = 0;
+    int mcnt[S];  // wave-uniform per-member counts
+#pragma unroll
+    for (int l = 0; l < S; ++l) mcnt[l] = 0;
     const UnitView v = unit_view<CL>(a, u);
     const uint32_t hmask = (uint32_t)T - 1u;
     const int hshift = 32 - a.log2T;
@@ -281,7 +292,7 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
 
     // one compare-and-swap takes an empty slot or confirms the key already
     // there; only collisions walk on
-    auto probe = [&](const Pass<CL, false> &d) {
+    auto probe = [&](const Pass<MS, false> &d) {
         uint32_t h = d.j == kDummyKey ? (uint32_t)T : ((uint32_t)d.j * 2654435761u) >> hshift;
         int old = atomicCAS(&keys[h], kEmpty, d.j);
         while (old != kEmpty && old != d.j) {
@@ -289,28 +300,28 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
             old = atomicCAS(&keys[h], kEmpty, d.j);
         }
         inserted += old == kEmpty;
-        if (CL) {
+        if (MS) {
             // member rows that see this column for the first time
             uint32_t fresh = d.m & ~atomicOr(&masks[h], d.m);
             if (h == (uint32_t)T) fresh = 0u;
-            while (fresh) {
-                atomicAdd(&mcnt[__ffs(fresh) - 1], 1);
-                fresh &= fresh - 1u;
+            if (__ballot(fresh != 0u)) {
+#pragma unroll
+                for (int l = 0; l < S; ++l) mcnt[l] += __popcll(__ballot((fresh >> l) & 1u));
             }
         }
     };
 
     constexpr int kR = 8;
     while (q0 < v.it1) {
-        const int E = load_round<CL, S, false>(a, v, q0, off0, items, sbits, nullptr);
+        const int E = load_round<CL, S, false>(a, v, q0, off0, items, sbits, nullptr, nullptr);
         const int npass = (E + 63) >> 6;
         int cum = 0, p = 0;
         for (; p + kR <= npass; p += kR) {
-            Pass<CL, false> d[kR];
+            Pass<MS, false> d[kR];
 #pragma unroll
             for (int rr = 0; rr < kR; ++rr) {
                 const uint64_t w = uniform64(sbits[p + rr]);
-                d[rr] = fetch_pass<CL, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                d[rr] = fetch_pass<MS, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
                 cum += __popcll(w);
             }
 #pragma unroll
@@ -324,7 +335,7 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
         }
         for (; p < npass; ++p) {
             const uint64_t w = uniform64(sbits[p]);
-            const Pass<CL, false> d = fetch_pass<CL, false>(a, items, w, cum, (p << 6) + lane, E, le);
+            const Pass<MS, false> d = fetch_pass<MS, false>(a, items, w, cum, (p << 6) + lane, E, le);
             cum += __popcll(w);
             if (d.j != kDummyKey) {
                 kmin = min(kmin, d.j);
@@ -343,14 +354,18 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
         a.keylo[u] = kmin;
         a.keyhi[u] = kmax;
     }
-    if (!CL) {
+    if (!MS) {
         if (lane == 0) {
-            a.c_rp[u] = U;
+            a.c_rp[member_row<CL>(a, v, 0)] = U;
             a.ucount[u] = U;
         }
         return;
     }
-    if (lane < v.s) a.c_rp[member_row<CL>(a, v, lane)] = mcnt[lane];
+    int mine = 0;
+#pragma unroll
+    for (int l = 0; l < S; ++l)
+        if (l == lane) mine = mcnt[l];
+    if (lane < v.s) a.c_rp[member_row<CL>(a, v, lane)] = mine;
     if (lane == 0) a.ucount[u] = U;
 }
 
@@ -366,6 +381,7 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
 template <int S, bool CL>
 __global__ void __launch_bounds__(256) k_num(SpArgs a)
 {
+    constexpr bool MS = CL && S > 1;  // several member rows (masks needed)
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = (int)__lane_id();
     const int wib = threadIdx.x >> 6;
@@ -375,7 +391,7 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
     if (u < a.unit_lo || u >= a.unit_hi) return;
 
     const int T = a.T, TX = a.T + kTail;
-    const NumLayout L(CL, S, TX);
+    const NumLayout L(MS, S, TX);
     unsigned char *base = smem + (size_t)wib * a.group_bytes;
     int *keys = (int *)(base + L.keys);
     uint32_t *masks = (uint32_t *)(base + L.masks);
@@ -384,15 +400,14 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
     uint16_t *order = (uint16_t *)(base + L.order);
     ItemRec *items = (ItemRec *)(base + L.items);
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
-    int *hcnt = (int *)(base + L.hcnt);
-    int *hpre = (int *)(base + L.hpre);
+    int *hcnt = (int *)(base + L.hcnt);  // per-home key counts, then their exclusive prefix
 
     const int VS = TX + 1;  // value column stride (slots incl. the dummy)
     const UnitView v = unit_view<CL>(a, u);
     for (int i = lane; i <= TX; i += 64) {
         keys[i] = i == TX ? kDummyKey : kEmpty;
         if (i < T) hcnt[i] = 0;
-        if (CL) masks[i] = 0u;
+        if (MS) masks[i] = 0u;
 #pragma unroll
         for (int l = 0; l < S; ++l)
             if (l < v.s) vals[l * VS + i] = 0.0;
@@ -402,6 +417,9 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
     const uint64_t le = lanemask_le(lane);
     int64_t q0 = v.it0;
     int off0 = 0;
+    double areg[S];  // this lane's item: member values of A (narrow clusters)
+#pragma unroll
+    for (int l = 0; l < S; ++l) areg[l] = 0.0;
 
     auto home = [&](int j) -> int {
         const int h = (int)((float)(uint32_t)(j - lo) * scale);
@@ -420,18 +438,19 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
         return h;
     };
     // products of one pass, applied item by item (ascending k)
-    auto apply = [&](const Pass<CL, true> &d, int h, int tf, int tl) {
+    auto apply = [&](const Pass<MS, true> &d, int h, int tf, int tl) {
         for (int tt = tf; tt <= tl; ++tt) {
             if (d.t != tt) continue;
-            if (CL) {
+            if (MS) {
                 const uint32_t mt = (uint32_t)uniform((int)items[tt].x);
                 const int src = uniform((int)items[tt].y);
-                masks[h] |= mt;
+                atomicOr(&masks[h], mt);  // lanes of one sub-step hold distinct slots
 #pragma unroll
                 for (int l = 0; l < S; ++l) {
                     if ((mt >> l) & 1u) {
+                        const double av = a_in_regs(S) ? readlane_f64(areg[l], src) : aval[src * S + l];
                         double *pv = &vals[l * VS + h];
-                        *pv = __fma_rn(aval[src * S + l], d.b, *pv);
+                        *pv = __fma_rn(av, d.b, *pv);
                     }
                 }
             } else {
@@ -442,11 +461,11 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
 
     constexpr int kR = Depth<S>::R;
     while (q0 < v.it1) {
-        const int E = load_round<CL, S, true>(a, v, q0, off0, items, sbits, aval);
+        const int E = load_round<CL, S, true>(a, v, q0, off0, items, sbits, aval, areg);
         const int npass = (E + 63) >> 6;
         int cum = 0, p = 0;
         for (; p + kR <= npass; p += kR) {
-            Pass<CL, true> d[kR];
+            Pass<MS, true> d[kR];
             int tf[kR], tl[kR];
 #pragma unroll
             for (int rr = 0; rr < kR; ++rr) {
@@ -454,7 +473,7 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
                 const int last = min(63, E - 1 - ((p + rr) << 6));
                 tf[rr] = cum + (int)(w & 1ull) - 1;
                 tl[rr] = cum + __popcll(w & lanemask_le(last)) - 1;
-                d[rr] = fetch_pass<CL, true>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                d[rr] = fetch_pass<MS, true>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
                 cum += __popcll(w);
             }
 #pragma unroll
@@ -465,7 +484,7 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
             const int last = min(63, E - 1 - (p << 6));
             const int tf = cum + (int)(w & 1ull) - 1;
             const int tl = cum + __popcll(w & lanemask_le(last)) - 1;
-            const Pass<CL, true> d = fetch_pass<CL, true>(a, items, w, cum, (p << 6) + lane, E, le);
+            const Pass<MS, true> d = fetch_pass<MS, true>(a, items, w, cum, (p << 6) + lane, E, le);
             cum += __popcll(w);
             apply(d, probe(d.j), tf, tl);
         }
@@ -479,28 +498,30 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
         const int i = c0 + lane;
         const int cnt = i < T ? hcnt[i] : 0;
         const int incl = wave_incl_scan(cnt);
-        if (i < T) hpre[i] = U + incl - cnt;
+        if (i < T) hcnt[i] = U + incl - cnt;
         U += __shfl(incl, 63);
     }
+    if (lane == 0) hcnt[T] = U;
     int64_t o0 = 0, want = 0;
-    if (!CL) {
-        o0 = a.c_rp[v.pos0] - a.out_base;
-        want = a.c_rp[v.pos0 + 1] - a.c_rp[v.pos0];
+    if (!MS) {
+        const int64_t row = member_row<CL>(a, v, 0);
+        o0 = a.c_rp[row] - a.out_base;
+        want = a.c_rp[row + 1] - a.c_rp[row];
     }
     for (int c0 = 0; c0 < TX; c0 += 64) {
         const int sidx = c0 + lane;
         const int key = sidx < TX ? keys[sidx] : kEmpty;
         if (key == kEmpty) continue;
         const int hx = home(key);
-        int rank = hpre[hx];
-        if (hcnt[hx] > 1) {
+        int rank = hcnt[hx];
+        if (hcnt[hx + 1] - rank > 1) {
             for (int x = hx;; x = x + 1 == TX ? 0 : x + 1) {
                 const int kx = keys[x];
                 if (kx == kEmpty) break;
                 rank += kx < key && home(kx) == hx;
             }
         }
-        if (CL) {
+        if (MS) {
             order[rank] = (uint16_t)sidx;
         } else {
             // a CSR row goes straight to its place in C
@@ -513,7 +534,7 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
             }
         }
     }
-    if (!CL) {
+    if (!MS) {
         if (lane == 0 && U != want) atomicOr(a.err, kErrCount);
         return;
     }

@@ -54,7 +54,7 @@ __host__ __device__ inline int sclass_of(int s)
 }
 
 // Shared-memory bytes of one wavefront's tables (layouts in hash.hip).
-int64_t sym_wave_bytes(bool cl, int T);
+int64_t sym_wave_bytes(bool multi, int T);  // multi: units of several rows (masks kept)
 int64_t num_wave_bytes(bool cl, int sclass, int T);
 
 // Tuning derived from hcsp_opts.
