@@ -242,6 +242,71 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                         double *C_val_d, int64_t capacity, void *ws_d, size_t ws_bytes,
                         void *stream);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent products C_p = A_p x B_p of uneven sizes in one fixed
+ * sequence of launches: the units (rows or clusters) of all products are
+ * numbered consecutively, binned together, and every bin is processed by
+ * one persistent launch whose wavefronts take slices of the bin.  Bin sizes
+ * stay in device memory, so hcsp_spgemm_batched never synchronizes, copies
+ * or allocates: it can be captured into a HIP graph and replayed.  (The
+ * paper's row-wise product, Background "SpGEMM Kernel"; the batching is this
+ * library's own.)
+ *
+ * Outputs are flat: product p's row offsets are the nrows_p + 1 entries of
+ * C_row_ptr_d starting at seg_offset[p] (= sum over q < p of nrows_q + 1),
+ * local to the product (starting at 0); its columns and values start at
+ * out_offset[p] of C_col_d / C_val_d, where out_offset is the prefix sum of
+ * the per-product upper bounds sum_i sum_{k in A_i} |B_k|, so they never
+ * overflow.
+ *
+ * Use: hcsp_batch_plan_init (host only: sizes) -> allocate plan->ws_bytes
+ * -> hcsp_batch_prepare (uploads the descriptors, computes the bounds;
+ * synchronizes) -> allocate plan->out_capacity entries for C_col_d / C_val_d
+ * and plan->row_ptr_len for C_row_ptr_d -> hcsp_spgemm_batched, any number
+ * of times (capturable) -> hcsp_batch_status (per-product nnz and errors;
+ * synchronizes).  The items' device arrays must stay valid and keep their
+ * structure between prepare and the last batched call.
+ */
+typedef struct hcsp_batch_item {
+    hcsp_operand A; /* device arrays; all items of a batch have the same kind */
+    hcsp_csr B;     /* device arrays */
+} hcsp_batch_item;
+
+typedef struct hcsp_batch_plan {
+    int32_t count;        /* products */
+    int32_t kind;         /* HCSP_OP_CSR or HCSP_OP_CLUSTER */
+    int64_t units;        /* rows (CSR) or clusters, over all products */
+    int64_t rows;         /* rows of A over all products */
+    int64_t row_ptr_len;  /* rows + count: entries of C_row_ptr_d */
+    int64_t max_ncols;    /* widest B */
+    int32_t max_class;    /* member-count class of the widest cluster (0 for CSR) */
+    int32_t prepared;     /* set by hcsp_batch_prepare */
+    int64_t max_probes;   /* largest per-unit product count (prepare) */
+    int64_t out_capacity; /* entries of C_col_d / C_val_d (prepare) */
+    size_t ws_bytes;      /* workspace bytes (plan_init) */
+    hcsp_opts opts;       /* options the plan was made with */
+} hcsp_batch_plan;
+
+/* Host only: checks the items (host copies of the descriptors, device
+ * arrays inside) and fills count, kind, units, rows, row_ptr_len,
+ * max_ncols, max_class and ws_bytes.  opts may be NULL. */
+int hcsp_batch_plan_init(int32_t count, const hcsp_batch_item *items_h, const hcsp_opts *opts,
+                         hcsp_batch_plan *plan);
+/* Uploads the descriptors into the workspace and computes every product's
+ * output bound; fills plan->max_probes, plan->out_capacity and, when not
+ * NULL, out_offset_h[count+1] and seg_offset_h[count+1].  Synchronizes. */
+int hcsp_batch_prepare(hcsp_batch_plan *plan, const hcsp_batch_item *items_h, void *ws_d, size_t ws_bytes,
+                       int64_t *out_offset_h, int64_t *seg_offset_h, void *stream);
+/* Symbolic and numeric phases of every product.  Never synchronizes,
+ * copies from the host or allocates (capture-safe).  Errors are recorded
+ * per product in the workspace and reported by hcsp_batch_status. */
+int hcsp_spgemm_batched(const hcsp_batch_plan *plan, int64_t *C_row_ptr_d, int32_t *C_col_d, double *C_val_d,
+                        void *ws_d, size_t ws_bytes, void *stream);
+/* nnz_h[count] (nullable) receives nnz(C_p); returns HCSP_E_CAPACITY or
+ * HCSP_E_INVALID if a product of the last batched call flagged an error.
+ * Synchronizes. */
+int hcsp_batch_status(const hcsp_batch_plan *plan, void *ws_d, size_t ws_bytes, int64_t *nnz_h, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,16 @@ class c_sym_info(ctypes.Structure):
                 ("num_bin_count", i64 * MAX_BINS), ("lanes", i32), ("valid", i32)]
 
 
+class c_batch_item(ctypes.Structure):
+    _fields_ = [("A", c_operand), ("B", c_csr)]
+
+
+class c_batch_plan(ctypes.Structure):
+    _fields_ = [("count", i32), ("kind", i32), ("units", i64), ("rows", i64), ("row_ptr_len", i64),
+                ("max_ncols", i64), ("max_class", i32), ("prepared", i32), ("max_probes", i64),
+                ("out_capacity", i64), ("ws_bytes", ctypes.c_size_t), ("opts", c_opts)]
+
+
 # every symbol include/hcsp.h declares, with its ctypes signature
 _SIGS = {
     "hcsp_version": ([], ctypes.c_char_p),
@@ -84,6 +94,12 @@ _SIGS = {
                               ctypes.POINTER(c_sym_info), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "hcsp_spgemm_numeric": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
                              ctypes.POINTER(c_sym_info), vp, vp, vp, i64, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_batch_plan_init": ([i32, ctypes.POINTER(c_batch_item), ctypes.POINTER(c_opts),
+                              ctypes.POINTER(c_batch_plan)], ctypes.c_int),
+    "hcsp_batch_prepare": ([ctypes.POINTER(c_batch_plan), ctypes.POINTER(c_batch_item), vp, ctypes.c_size_t, vp, vp,
+                            vp], ctypes.c_int),
+    "hcsp_spgemm_batched": ([ctypes.POINTER(c_batch_plan), vp, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_batch_status": ([ctypes.POINTER(c_batch_plan), vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
 }
 
 _lib = None
@@ -398,3 +414,71 @@ class Product:
 def spgemm(A, B: DeviceCSR, o: c_opts | None = None, stream=None) -> DeviceCSR:
     """C = A x B (A: DeviceCSR or DeviceCluster) with C in A's original row order."""
     return Product(A, B, o).run(stream)
+
+
+# ------------------------------------------------------------------ batches
+
+def batch_plan_init(items, o: c_opts | None = None) -> c_batch_plan:
+    plan = c_batch_plan()
+    o = o or c_opts()
+    _check(lib().hcsp_batch_plan_init(len(items), items, ctypes.byref(o), ctypes.byref(plan)), "batch_plan_init")
+    return plan
+
+
+def batch_prepare(plan: c_batch_plan, items, ws, stream=None):
+    """Returns (out_offset, seg_offset), numpy int64 arrays of count+1 entries."""
+    n = plan.count
+    out_off = np.zeros(n + 1, np.int64)
+    seg_off = np.zeros(n + 1, np.int64)
+    _check(lib().hcsp_batch_prepare(ctypes.byref(plan), items, _tp(ws), ws.numel(), _np(out_off), _np(seg_off),
+                                    _stream(stream)), "batch_prepare")
+    return out_off, seg_off
+
+
+def spgemm_batched(plan: c_batch_plan, C_row_ptr, C_col, C_val, ws, stream=None):
+    _check(lib().hcsp_spgemm_batched(ctypes.byref(plan), _tp(C_row_ptr), _tp(C_col), _tp(C_val), _tp(ws), ws.numel(),
+                                     _stream(stream)), "spgemm_batched")
+
+
+def batch_status(plan: c_batch_plan, ws, stream=None) -> np.ndarray:
+    nnz = np.zeros(max(plan.count, 1), np.int64)
+    _check(lib().hcsp_batch_status(ctypes.byref(plan), _tp(ws), ws.numel(), _np(nnz), _stream(stream)),
+           "batch_status")
+    return nnz[:plan.count]
+
+
+class Batch:
+    """Many independent products C_p = A_p x B_p computed by one fixed launch sequence (capturable into a
+    graph).  ``run()`` enqueues both phases for every product; ``status()`` synchronizes and returns each
+    product's nnz; ``result(p)`` is product p's C as a DeviceCSR view of the flat outputs."""
+
+    def __init__(self, pairs, o: c_opts | None = None, stream=None):
+        import torch
+        self.pairs = list(pairs)
+        n = len(self.pairs)
+        self.items = (c_batch_item * max(n, 1))()
+        for p, (A, B) in enumerate(self.pairs):
+            self.items[p].A = operand(A)
+            self.items[p].B = B.c()
+        self.plan = batch_plan_init(self.items, o)
+        dev = self.pairs[0][1].row_ptr.device if n else torch.device("cuda")
+        self.ws = torch.empty(max(self.plan.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        self.out_off, self.seg_off = batch_prepare(self.plan, self.items, self.ws, stream)
+        self.C_row_ptr = torch.empty(max(self.plan.row_ptr_len, 1), dtype=torch.int64, device=dev)
+        self.C_col = torch.empty(max(self.plan.out_capacity, 1), dtype=torch.int32, device=dev)
+        self.C_val = torch.empty(max(self.plan.out_capacity, 1), dtype=torch.float64, device=dev)
+
+    def run(self, stream=None):
+        spgemm_batched(self.plan, self.C_row_ptr, self.C_col, self.C_val, self.ws, stream)
+
+    def status(self, stream=None) -> np.ndarray:
+        return batch_status(self.plan, self.ws, stream)
+
+    def result(self, p: int, nnz: int | None = None) -> DeviceCSR:
+        A, B = self.pairs[p]
+        s0 = int(self.seg_off[p])
+        rp = self.C_row_ptr[s0:s0 + A.nrows + 1]
+        if nnz is None:
+            nnz = int(rp[-1].item())
+        o0 = int(self.out_off[p])
+        return DeviceCSR(rp, self.C_col[o0:o0 + nnz], self.C_val[o0:o0 + nnz], A.nrows, B.ncols)

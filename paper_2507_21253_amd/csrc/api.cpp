@@ -53,6 +53,22 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     return ws->bytes;
 }
 
+// Compute units of the current device (queried once per device).
+static int cu_count()
+{
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
 // Shared memory per workgroup the bins may plan for (queried once per device).
 static int64_t lds_limit()
 {
@@ -242,6 +258,59 @@ static int ensure_lds(size_t lds, int64_t budget)
     return HCSP_OK;
 }
 
+// Batch workspace: descriptors and per-product data, then the same per-unit
+// arrays and counters as a single product (over the batch's units).
+struct BatchWs {
+    BatchProb *probs;
+    int64_t *units, *segs;     // [count+1] unit and row-offset segment bases
+    int64_t *ub, *nnz, *seg_base, *maxp;
+    uint32_t *errs;
+    int64_t *sym_begin, *num_begin;
+    Workspace w;
+};
+
+static size_t layout_batch(int32_t count, int64_t units, int64_t row_ptr_len, int64_t max_ncols, int dense_slots,
+                           char *base, BatchWs *b)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        off = align_up(off, 256);
+        void *p = base ? (void *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t n = (size_t)std::max(count, 1);
+    b->probs = (BatchProb *)take(sizeof(BatchProb) * n);
+    b->units = (int64_t *)take(8 * (n + 1));
+    b->segs = (int64_t *)take(8 * (n + 1));
+    b->ub = (int64_t *)take(8 * n);
+    b->nnz = (int64_t *)take(8 * n);
+    b->seg_base = (int64_t *)take(8 * n);
+    b->maxp = (int64_t *)take(8);
+    b->errs = (uint32_t *)take(4 * n);
+    b->sym_begin = (int64_t *)take(8 * HCSP_MAX_BINS);
+    b->num_begin = (int64_t *)take(8 * HCSP_MAX_BINS);
+    off = align_up(off, 256);
+    const size_t rest = layout_workspace(units, row_ptr_len, max_ncols, dense_slots, base ? base + off : nullptr, &b->w);
+    return off + rest;
+}
+
+static BinArgs batch_bin_args(const hcsp_batch_plan &plan, const BatchWs &ws, const Tune &tu, int64_t *c_rp)
+{
+    BinArgs b;
+    std::memset(&b, 0, sizeof b);
+    b.nunits = plan.units;
+    b.ws = ws.w;
+    b.c_rp = c_rp;
+    b.sym_tmax_log2 = tu.sym_tmax_log2;
+    num_tmax_classes(tu, plan.kind == HCSP_OP_CLUSTER, b.num_tmax_by_class);
+    b.load_pct = tu.load_pct;
+    b.batch = ws.probs;
+    b.batch_units = ws.units;
+    b.nprob = plan.count;
+    return b;
+}
+
 }  // namespace hcsp
 
 using namespace hcsp;
@@ -399,7 +468,7 @@ int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
             if (b == kSymGlobal) {
                 const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
                 HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, s));
-                HCSP_HIP(launch_sym_dense(v.cluster, a, waves / 4, s));
+                HCSP_HIP(launch_sym_dense(v.cluster, false, a, waves / 4, s));
             } else {
                 const int sc = (b - 1) / kSymT;
                 const int l2 = (b - 1) % kSymT + kSymLog2Min;
@@ -412,7 +481,7 @@ int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
                 geometry(gb, c, &blocks, &threads, &lds);
                 rc = ensure_lds(lds, tu.lds_budget);
                 if (rc) return rc;
-                HCSP_HIP(launch_sym(sc, v.cluster, a, blocks, threads, lds, s));
+                HCSP_HIP(launch_sym(sc, v.cluster, false, a, blocks, threads, lds, s));
             }
         }
         start += c;
@@ -475,7 +544,7 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
             if (b == kNumGlobal) {
                 const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
                 HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, s));
-                HCSP_HIP(launch_num_dense(v.cluster, a, waves / 4, s));
+                HCSP_HIP(launch_num_dense(v.cluster, false, a, waves / 4, s));
             } else {
                 const int sc = (b - 1) / kNumT;
                 const int t = (b - 1) % kNumT;
@@ -487,7 +556,7 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                 geometry(gb, c, &blocks, &threads, &lds);
                 rc = ensure_lds(lds, tu.lds_budget);
                 if (rc) return rc;
-                HCSP_HIP(launch_num(sc, v.cluster, a, blocks, threads, lds, s));
+                HCSP_HIP(launch_num(sc, v.cluster, false, a, blocks, threads, lds, s));
             }
         }
         start += c;
@@ -498,6 +567,299 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
         HCSP_HIP(hipStreamSynchronize(s));
         if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "output capacity too small for the requested units");
         if (e & kErrCount) return fail(HCSP_E_INVALID, "row counts differ from the symbolic phase (inputs changed?)");
+    }
+    return HCSP_OK;
+}
+
+// ================================================================ batches
+
+int hcsp_batch_plan_init(int32_t count, const hcsp_batch_item *items, const hcsp_opts *opts, hcsp_batch_plan *plan)
+{
+    clear_error();
+    if (!plan || count < 0 || (count > 0 && !items)) return fail(HCSP_E_INVALID, "bad arguments");
+    std::memset(plan, 0, sizeof *plan);
+    if (opts) plan->opts = *opts;
+    plan->count = count;
+    plan->kind = count > 0 ? items[0].A.kind : HCSP_OP_CSR;
+    int maxs = 1;
+    for (int32_t p = 0; p < count; ++p) {
+        OpView v;
+        int rc = check_operands(&items[p].A, &items[p].B, &v);
+        if (rc) return fail(rc, "batch item " + std::to_string(p) + ": " + g_err);
+        if (items[p].A.kind != plan->kind) return fail(HCSP_E_INVALID, "all items of a batch must have the same kind");
+        if (v.cluster) maxs = std::max(maxs, (int)std::max<int64_t>(1, items[p].A.cl.max_cluster));
+        plan->units += v.nunits;
+        plan->rows += v.nrows;
+        plan->max_ncols = std::max(plan->max_ncols, items[p].B.ncols);
+    }
+    if (plan->units >= INT32_MAX) return fail(HCSP_E_OVERFLOW, "a batch holds fewer than 2^31 units");
+    plan->row_ptr_len = plan->rows + count;
+    plan->max_class = sclass_of(maxs);
+    Tune tu;
+    hcsp_csr widest;
+    std::memset(&widest, 0, sizeof widest);
+    widest.ncols = plan->max_ncols;
+    int rc = make_tune(&plan->opts, &widest, false, &tu);
+    if (rc) return rc;
+    BatchWs ws;
+    plan->ws_bytes = layout_batch(count, plan->units, plan->row_ptr_len, plan->max_ncols, tu.dense_slots, nullptr, &ws);
+    return HCSP_OK;
+}
+
+int hcsp_batch_prepare(hcsp_batch_plan *plan, const hcsp_batch_item *items, void *ws_d, size_t ws_bytes,
+                       int64_t *out_offset_h, int64_t *seg_offset_h, void *stream)
+{
+    clear_error();
+    if (!plan || (plan->count > 0 && !items)) return fail(HCSP_E_INVALID, "bad arguments");
+    hcsp_batch_plan chk;
+    int rc = hcsp_batch_plan_init(plan->count, items, &plan->opts, &chk);
+    if (rc) return rc;
+    if (chk.units != plan->units || chk.rows != plan->rows || chk.ws_bytes != plan->ws_bytes)
+        return fail(HCSP_E_INVALID, "items differ from the ones the plan was made for");
+    if (!ws_d || ws_bytes < plan->ws_bytes) return fail(HCSP_E_CAPACITY, "batch workspace too small");
+    Tune tu;
+    hcsp_csr widest;
+    std::memset(&widest, 0, sizeof widest);
+    widest.ncols = plan->max_ncols;
+    rc = make_tune(&plan->opts, &widest, true, &tu);
+    if (rc) return rc;
+    BatchWs ws;
+    layout_batch(plan->count, plan->units, plan->row_ptr_len, plan->max_ncols, tu.dense_slots, (char *)ws_d, &ws);
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t n = plan->count;
+    const bool cl = plan->kind == HCSP_OP_CLUSTER;
+
+    // descriptors with unit / segment bases; capacities follow from the bounds
+    std::vector<BatchProb> bp((size_t)std::max(n, 1));
+    std::vector<int64_t> ubase((size_t)n + 1), segs((size_t)n + 1);
+    int64_t u0 = 0, s0 = 0;
+    for (int32_t p = 0; p < n; ++p) {
+        BatchProb &d = bp[(size_t)p];
+        std::memset(&d, 0, sizeof d);
+        const hcsp_operand &A = items[p].A;
+        const hcsp_csr &B = items[p].B;
+        if (cl) {
+            d.cl_row_ptr = A.cl.cl_row_ptr;
+            d.perm = A.cl.perm;
+            d.cl_col_ptr = A.cl.cl_col_ptr;
+            d.cl_col = A.cl.cl_col;
+            d.cl_mask = A.cl.cl_mask;
+            d.cl_val_ptr = A.cl.cl_val_ptr;
+            d.cl_val = A.cl.cl_val;
+            d.nunits = A.cl.nclusters;
+            d.nrows = A.cl.nrows;
+        } else {
+            d.a_rp = A.csr.row_ptr;
+            d.a_col = A.csr.col;
+            d.a_val = A.csr.val;
+            d.nunits = A.csr.nrows;
+            d.nrows = A.csr.nrows;
+        }
+        d.b_rp = B.row_ptr;
+        d.b_col = B.col;
+        d.b_val = B.val;
+        d.ncols = B.ncols;
+        d.unit_base = u0;
+        d.seg_base = s0;
+        ubase[(size_t)p] = u0;
+        segs[(size_t)p] = s0;
+        u0 += d.nunits;
+        s0 += d.nrows + 1;
+    }
+    ubase[(size_t)n] = u0;
+    segs[(size_t)n] = s0;
+    HCSP_HIP(hipMemcpyAsync(ws.units, ubase.data(), 8 * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+    HCSP_HIP(hipMemcpyAsync(ws.segs, segs.data(), 8 * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+    HCSP_HIP(hipMemcpyAsync(ws.probs, bp.data(), sizeof(BatchProb) * (size_t)n, hipMemcpyHostToDevice, s));
+    HCSP_HIP(launch_fill_i64(ws.ub, n, 0, s));
+    HCSP_HIP(launch_batch_bound(ws.probs, n, cl, ws.ub, s));
+    // the largest unit bounds which bins a batched call can reach
+    BinArgs ba = batch_bin_args(*plan, ws, tu, nullptr);
+    HCSP_HIP(launch_fill_i64(ws.maxp, 1, 0, s));
+    HCSP_HIP(launch_work(cl, ba, s));
+    HCSP_HIP(launch_max_i64(ws.w.probes, plan->units, ws.maxp, s));
+    std::vector<int64_t> ub((size_t)std::max(n, 1));
+    int64_t maxp = 0;
+    HCSP_HIP(hipMemcpyAsync(ub.data(), ws.ub, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipMemcpyAsync(&maxp, ws.maxp, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    int64_t off = 0;
+    for (int32_t p = 0; p < n; ++p) {
+        bp[(size_t)p].out_base = off;
+        bp[(size_t)p].cap = ub[(size_t)p];
+        if (out_offset_h) out_offset_h[p] = off;
+        off += ub[(size_t)p];
+    }
+    if (out_offset_h) out_offset_h[n] = off;
+    if (seg_offset_h)
+        for (int32_t p = 0; p <= n; ++p) seg_offset_h[p] = segs[(size_t)p];
+    HCSP_HIP(hipMemcpyAsync(ws.probs, bp.data(), sizeof(BatchProb) * (size_t)n, hipMemcpyHostToDevice, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    plan->max_probes = maxp;
+    plan->out_capacity = off;
+    plan->prepared = 1;
+    return HCSP_OK;
+}
+
+int hcsp_spgemm_batched(const hcsp_batch_plan *plan, int64_t *C_row_ptr_d, int32_t *C_col_d, double *C_val_d,
+                        void *ws_d, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (!plan || !plan->prepared) return fail(HCSP_E_INVALID, "the plan was not prepared");
+    if (!ws_d || ws_bytes < plan->ws_bytes) return fail(HCSP_E_CAPACITY, "batch workspace too small");
+    if (plan->count == 0) return HCSP_OK;
+    if (!C_row_ptr_d || (plan->out_capacity > 0 && (!C_col_d || !C_val_d)))
+        return fail(HCSP_E_INVALID, "null output array");
+    Tune tu;
+    hcsp_csr widest;
+    std::memset(&widest, 0, sizeof widest);
+    widest.ncols = plan->max_ncols;
+    int rc = make_tune(&plan->opts, &widest, true, &tu);
+    if (rc) return rc;
+    BatchWs ws;
+    layout_batch(plan->count, plan->units, plan->row_ptr_len, plan->max_ncols, tu.dense_slots, (char *)ws_d, &ws);
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t n = plan->count;
+    const bool cl = plan->kind == HCSP_OP_CLUSTER;
+    const int ncu = cu_count();
+
+    HCSP_HIP(launch_fill_i64(ws.w.sym_count, HCSP_MAX_BINS, 0, s));
+    HCSP_HIP(launch_fill_i64(ws.w.num_count, HCSP_MAX_BINS, 0, s));
+    HCSP_HIP(launch_fill_u32(ws.errs, n, 0u, s));
+
+    SpArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.keylo = ws.w.keylo;
+    a.keyhi = ws.w.keyhi;
+    a.ucount = ws.w.ucount;
+    a.c_rp = C_row_ptr_d;
+    a.G = tu.G;
+    a.dense_bits = ws.w.dense_bits;
+    a.dense_vals = ws.w.dense_vals;
+    a.dense_words = ws.w.dense_words;
+    a.ncols = plan->max_ncols;
+    a.unit_lo = 0;
+    a.unit_hi = INT64_MAX;
+    a.batch = ws.probs;
+    a.batch_units = ws.units;
+    a.nprob = n;
+    a.errs = ws.errs;
+    a.err = ws.errs;
+
+    // persistent launch of one bin: enough wavefronts to fill every compute
+    // unit the bin's shared memory allows, never more than the batch's units
+    auto persistent = [&](int64_t wave_bytes, int *blocks, int *threads, size_t *lds) {
+        int b0;
+        geometry(wave_bytes, 1, &b0, threads, lds);
+        const int wpb = *threads / 64;
+        const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(32 / wpb, (160 * 1024) / (int64_t)*lds));
+        *blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, (plan->units + wpb - 1) / wpb));
+    };
+
+    // ---- symbolic
+    BinArgs ba = batch_bin_args(*plan, ws, tu, C_row_ptr_d);
+    HCSP_HIP(launch_work(cl, ba, s));
+    HCSP_HIP(launch_scatter(ws.w.bin, plan->units, ws.w.bin_hist, kSymBins, ws.w.sym_count, ws.w.order_sym, s));
+    HCSP_HIP(launch_bin_begin(ws.w.sym_count, kSymBins, ws.sym_begin, s));
+    a.order = ws.w.order_sym;
+    a.dcount = ws.w.sym_count;
+    a.dbegin = ws.sym_begin;
+    int sym_l2 = kSymLog2Min;
+    while (sym_l2 < tu.sym_tmax_log2 && ((int64_t)1 << sym_l2) < plan->max_probes) ++sym_l2;
+    for (int sc = 0; sc <= (cl ? plan->max_class : 0); ++sc) {
+        for (int l2 = kSymLog2Min; l2 <= sym_l2; ++l2) {
+            a.bin = 1 + sc * kSymT + (l2 - kSymLog2Min);
+            a.T = 1 << l2;
+            a.log2T = l2;
+            const int64_t gb = sym_wave_bytes(cl && sc > 0, a.T);
+            a.group_bytes = (int)gb;
+            int blocks, threads;
+            size_t lds;
+            persistent(gb, &blocks, &threads, &lds);
+            rc = ensure_lds(lds, tu.lds_budget);
+            if (rc) return rc;
+            HCSP_HIP(launch_sym(sc, cl, true, a, blocks, threads, lds, s));
+        }
+    }
+    const bool dense = plan->max_probes > ((int64_t)1 << tu.sym_tmax_log2);
+    if (dense) {
+        a.bin = kSymGlobal;
+        HCSP_HIP(launch_fill_u32(ws.w.dense_bits, (int64_t)tu.dense_slots * ws.w.dense_words, 0u, s));
+        HCSP_HIP(launch_sym_dense(cl, true, a, tu.dense_slots / 4, s));
+    }
+    // ---- per-product row offsets
+    HCSP_HIP(launch_batch_seg_tail(ws.probs, n, C_row_ptr_d, s));
+    HCSP_HIP(launch_scan_exclusive(C_row_ptr_d, plan->row_ptr_len, ws.w.scan_tmp, s));
+    HCSP_HIP(launch_batch_seg_rebase(ws.probs, ws.segs, n, C_row_ptr_d, plan->row_ptr_len, ws.seg_base, ws.nnz, s));
+    // ---- numeric
+    HCSP_HIP(launch_numbin(cl, ba, s));
+    HCSP_HIP(launch_scatter(ws.w.bin, plan->units, ws.w.bin_hist, kNumBins, ws.w.num_count, ws.w.order_num, s));
+    HCSP_HIP(launch_bin_begin(ws.w.num_count, kNumBins, ws.num_begin, s));
+    a.order = ws.w.order_num;
+    a.dcount = ws.w.num_count;
+    a.dbegin = ws.num_begin;
+    a.c_col = C_col_d;
+    a.c_val = C_val_d;
+    int tmax[kSClasses];
+    num_tmax_classes(tu, cl, tmax);
+    const int64_t need = (plan->max_probes * 100 + tu.load_pct - 1) / tu.load_pct;
+    bool num_dense = dense;
+    for (int sc = 0; sc <= (cl ? plan->max_class : 0); ++sc) {
+        for (int t = 0; t < kNumT; ++t) {
+            const int T = num_table(t);
+            if (T > tmax[sc]) {
+                num_dense = true;
+                break;
+            }
+            a.bin = 1 + sc * kNumT + t;
+            a.T = T;
+            const int64_t gb = num_wave_bytes(cl, sc, T);
+            a.group_bytes = (int)gb;
+            int blocks, threads;
+            size_t lds;
+            persistent(gb, &blocks, &threads, &lds);
+            rc = ensure_lds(lds, tu.lds_budget);
+            if (rc) return rc;
+            HCSP_HIP(launch_num(sc, cl, true, a, blocks, threads, lds, s));
+            if (T >= need) break;
+        }
+    }
+    if (num_dense) {
+        a.bin = kNumGlobal;
+        HCSP_HIP(launch_fill_u32(ws.w.dense_bits, (int64_t)tu.dense_slots * ws.w.dense_words, 0u, s));
+        HCSP_HIP(launch_num_dense(cl, true, a, tu.dense_slots / 4, s));
+    }
+    return HCSP_OK;
+}
+
+int hcsp_batch_status(const hcsp_batch_plan *plan, void *ws_d, size_t ws_bytes, int64_t *nnz_h, void *stream)
+{
+    clear_error();
+    if (!plan || !plan->prepared) return fail(HCSP_E_INVALID, "the plan was not prepared");
+    if (!ws_d || ws_bytes < plan->ws_bytes) return fail(HCSP_E_CAPACITY, "batch workspace too small");
+    Tune tu;
+    hcsp_csr widest;
+    std::memset(&widest, 0, sizeof widest);
+    widest.ncols = plan->max_ncols;
+    int rc = make_tune(&plan->opts, &widest, false, &tu);
+    if (rc) return rc;
+    BatchWs ws;
+    layout_batch(plan->count, plan->units, plan->row_ptr_len, plan->max_ncols, tu.dense_slots, (char *)ws_d, &ws);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)plan->count;
+    std::vector<uint32_t> e(std::max<size_t>(n, 1));
+    std::vector<int64_t> z(std::max<size_t>(n, 1));
+    if (n) {
+        HCSP_HIP(hipMemcpyAsync(e.data(), ws.errs, 4 * n, hipMemcpyDeviceToHost, s));
+        HCSP_HIP(hipMemcpyAsync(z.data(), ws.nnz, 8 * n, hipMemcpyDeviceToHost, s));
+    }
+    HCSP_HIP(hipStreamSynchronize(s));
+    if (nnz_h)
+        for (size_t p = 0; p < n; ++p) nnz_h[p] = z[p];
+    for (size_t p = 0; p < n; ++p) {
+        if (e[p] & kErrCapacity) return fail(HCSP_E_CAPACITY, "product " + std::to_string(p) + ": output bound exceeded");
+        if (e[p] & kErrCount)
+            return fail(HCSP_E_INVALID, "product " + std::to_string(p) + ": row counts differ between the phases");
     }
     return HCSP_OK;
 }

@@ -6,6 +6,22 @@
 
 namespace hcsp {
 
+// The dense bin's units as (count, first) for this launch; in a batch they
+// are read from device memory and each unit is resolved to its product.
+template <bool BATCH>
+__device__ __forceinline__ void dense_range(const SpArgs &a, int64_t *count, int64_t *begin)
+{
+    *count = BATCH ? a.dcount[a.bin] : a.count;
+    *begin = BATCH ? a.dbegin[a.bin] : a.bin_begin;
+}
+
+template <bool BATCH>
+__device__ __forceinline__ int dense_unit(SpArgs &a, const SpArgs &a0, int64_t i)
+{
+    a = a0;
+    return BATCH ? batch_resolve(a, a0.order[i]) : a0.order[i];
+}
+
 // ============================================================== dense path
 // Units whose tables do not fit in shared memory.  One wavefront per unit,
 // each with a private bitmap (and, for the numeric phase, a value array)
@@ -15,15 +31,18 @@ namespace hcsp {
 // Symbolic: lanes take different columns k of the row (no order needed to
 // count distinct columns), set bits with atomic OR and count the bits they
 // were first to set; a second walk clears the bits it set.
-template <bool CL>
-__global__ void __launch_bounds__(256) k_sym_dense(SpArgs a)
+template <bool CL, bool BATCH>
+__global__ void __launch_bounds__(256) k_sym_dense(SpArgs a0)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    uint32_t *bm = a.dense_bits + wv * a.dense_words;
-    for (int64_t ti = wv; ti < a.count; ti += nw) {
-        const int u = a.order[a.bin_begin + ti];
+    uint32_t *bm = a0.dense_bits + wv * a0.dense_words;
+    int64_t count, begin;
+    dense_range<BATCH>(a0, &count, &begin);
+    for (int64_t ti = wv; ti < count; ti += nw) {
+        SpArgs a;
+        const int u = dense_unit<BATCH>(a, a0, begin + ti);
         const UnitView v = unit_view<CL>(a, u);
         for (int l = 0; l < v.s; ++l) {
             int64_t cnt = 0;
@@ -56,16 +75,19 @@ __global__ void __launch_bounds__(256) k_sym_dense(SpArgs a)
 // split row k of B, so each c_j still sees its products in ascending k; the
 // accumulator lives in global memory, so every step waits for its stores
 // before the next step reads.  Output: scan the bitmap in column order.
-template <bool CL>
-__global__ void __launch_bounds__(256) k_num_dense(SpArgs a)
+template <bool CL, bool BATCH>
+__global__ void __launch_bounds__(256) k_num_dense(SpArgs a0)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    uint32_t *bm = a.dense_bits + wv * a.dense_words;
-    double *acc = a.dense_vals + wv * a.ncols;
-    for (int64_t ti = wv; ti < a.count; ti += nw) {
-        const int u = a.order[a.bin_begin + ti];
+    uint32_t *bm = a0.dense_bits + wv * a0.dense_words;
+    double *acc = a0.dense_vals + wv * a0.ncols;  // stride: the widest B of the launch
+    int64_t count, begin;
+    dense_range<BATCH>(a0, &count, &begin);
+    for (int64_t ti = wv; ti < count; ti += nw) {
+        SpArgs a;
+        const int u = dense_unit<BATCH>(a, a0, begin + ti);
         if (u < a.unit_lo || u >= a.unit_hi) continue;
         const UnitView v = unit_view<CL>(a, u);
         for (int l = 0; l < v.s; ++l) {
@@ -122,17 +144,21 @@ __global__ void __launch_bounds__(256) k_num_dense(SpArgs a)
     }
 }
 
-hipError_t launch_sym_dense(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
+hipError_t launch_sym_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s)
 {
-    if (cluster) hipLaunchKernelGGL((k_sym_dense<true>), dim3(blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_sym_dense<false>), dim3(blocks), dim3(256), 0, s, a);
+    if (cluster && batch) hipLaunchKernelGGL((k_sym_dense<true, true>), dim3(blocks), dim3(256), 0, s, a);
+    else if (cluster) hipLaunchKernelGGL((k_sym_dense<true, false>), dim3(blocks), dim3(256), 0, s, a);
+    else if (batch) hipLaunchKernelGGL((k_sym_dense<false, true>), dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_sym_dense<false, false>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_num_dense(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
+hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s)
 {
-    if (cluster) hipLaunchKernelGGL((k_num_dense<true>), dim3(blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_num_dense<false>), dim3(blocks), dim3(256), 0, s, a);
+    if (cluster && batch) hipLaunchKernelGGL((k_num_dense<true, true>), dim3(blocks), dim3(256), 0, s, a);
+    else if (cluster) hipLaunchKernelGGL((k_num_dense<true, false>), dim3(blocks), dim3(256), 0, s, a);
+    else if (batch) hipLaunchKernelGGL((k_num_dense<false, true>), dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_num_dense<false, false>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -258,18 +258,12 @@ __device__ __forceinline__ Pass<MS, NUM> fetch_pass(const SpArgs &a, const ItemR
 // that reached it: row l's count is the number of keys whose bit l got set,
 // counted (by ballot) when the bit first appears.
 template <int S, bool CL>
-__global__ void __launch_bounds__(256) k_sym(SpArgs a)
+__device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned char *base)
 {
     constexpr bool MS = CL && S > 1;  // several member rows (masks needed)
-    extern __shared__ __align__(16) unsigned char smem[];
     const int lane = (int)__lane_id();
-    const int wib = threadIdx.x >> 6;
-    const int64_t ui = xcd_block() * (blockDim.x >> 6) + wib;
-    if (ui >= a.count) return;
-    const int u = a.order[a.bin_begin + ui];
     const int T = a.T;
     const SymLayout L(MS, T);
-    unsigned char *base = smem + (size_t)wib * a.group_bytes;
     int *keys = (int *)(base + L.keys);
     uint32_t *masks = (uint32_t *)(base + L.masks);
     ItemRec *items = (ItemRec *)(base + L.items);
@@ -379,20 +373,14 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a)
 // which all lie on the probe path from that home; no sort is needed, and a
 // CSR row's entries are written straight to their final positions.
 template <int S, bool CL>
-__global__ void __launch_bounds__(256) k_num(SpArgs a)
+__device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned char *base)
 {
     constexpr bool MS = CL && S > 1;  // several member rows (masks needed)
-    extern __shared__ __align__(16) unsigned char smem[];
     const int lane = (int)__lane_id();
-    const int wib = threadIdx.x >> 6;
-    const int64_t ui = xcd_block() * (blockDim.x >> 6) + wib;
-    if (ui >= a.count) return;
-    const int u = a.order[a.bin_begin + ui];
     if (u < a.unit_lo || u >= a.unit_hi) return;
 
     const int T = a.T, TX = a.T + kTail;
     const NumLayout L(MS, S, TX);
-    unsigned char *base = smem + (size_t)wib * a.group_bytes;
     int *keys = (int *)(base + L.keys);
     uint32_t *masks = (uint32_t *)(base + L.masks);
     double *vals = (double *)(base + L.vals);
@@ -570,44 +558,83 @@ __global__ void __launch_bounds__(256) k_num(SpArgs a)
     }
 }
 
-// ================================================================ launchers
-template <int S, bool CL>
-static hipError_t go_sym(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
+// ================================================================ kernels
+// A bin's units: one per wavefront with the grid sized to the bin, or, for a
+// batch (BATCH), a persistent grid whose wavefronts each take one contiguous
+// slice of the bin, whose size and start are read from device memory; each
+// unit is then resolved to its product first.
+template <int S, bool CL, bool BATCH, bool NUM>
+__device__ __forceinline__ void run_bin(const SpArgs &a0)
 {
-    hipLaunchKernelGGL((k_sym<S, CL>), dim3(blocks), dim3(threads), lds, s, a);
-    return hipGetLastError();
-}
-
-template <int S, bool CL>
-static hipError_t go_num(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_num<S, CL>), dim3(blocks), dim3(threads), lds, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_sym(int sclass, bool cluster, const SpArgs &a, int blocks, int threads, size_t lds,
-                      hipStream_t s)
-{
-    if (!cluster) return go_sym<1, false>(a, blocks, threads, lds, s);
-    switch (sclass) {
-    case 0: return go_sym<1, true>(a, blocks, threads, lds, s);
-    case 1: return go_sym<2, true>(a, blocks, threads, lds, s);
-    case 2: return go_sym<4, true>(a, blocks, threads, lds, s);
-    case 3: return go_sym<8, true>(a, blocks, threads, lds, s);
-    default: return go_sym<16, true>(a, blocks, threads, lds, s);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wpb = blockDim.x >> 6;
+    const int wib = uniform((int)(threadIdx.x >> 6));
+    unsigned char *base = smem + (size_t)wib * a0.group_bytes;
+    const int64_t lw = xcd_block() * wpb + wib;
+    if (!BATCH) {
+        if (lw >= a0.count) return;
+        const int u = a0.order[a0.bin_begin + lw];
+        if (NUM) num_unit<S, CL>(a0, u, base);
+        else sym_unit<S, CL>(a0, u, base);
+        return;
+    }
+    const int64_t count = a0.dcount[a0.bin], begin = a0.dbegin[a0.bin];
+    const int64_t W = (int64_t)gridDim.x * wpb;
+    const int64_t e = begin + (lw + 1) * count / W;
+    for (int64_t i = begin + lw * count / W; i < e; ++i) {
+        SpArgs a = a0;
+        const int u = batch_resolve(a, a0.order[i]);
+        if (NUM) num_unit<S, CL>(a, u, base);
+        else sym_unit<S, CL>(a, u, base);
     }
 }
 
-hipError_t launch_num(int sclass, bool cluster, const SpArgs &a, int blocks, int threads, size_t lds,
+template <int S, bool CL, bool BATCH>
+__global__ void __launch_bounds__(256) k_sym(SpArgs a) { run_bin<S, CL, BATCH, false>(a); }
+
+template <int S, bool CL, bool BATCH>
+__global__ void __launch_bounds__(256) k_num(SpArgs a) { run_bin<S, CL, BATCH, true>(a); }
+
+// ================================================================ launchers
+template <int S, bool CL>
+static hipError_t go_sym(bool batch, const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
+{
+    if (batch) hipLaunchKernelGGL((k_sym<S, CL, true>), dim3(blocks), dim3(threads), lds, s, a);
+    else hipLaunchKernelGGL((k_sym<S, CL, false>), dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int S, bool CL>
+static hipError_t go_num(bool batch, const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
+{
+    if (batch) hipLaunchKernelGGL((k_num<S, CL, true>), dim3(blocks), dim3(threads), lds, s, a);
+    else hipLaunchKernelGGL((k_num<S, CL, false>), dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym(int sclass, bool cluster, bool batch, const SpArgs &a, int blocks, int threads, size_t lds,
                       hipStream_t s)
 {
-    if (!cluster) return go_num<1, false>(a, blocks, threads, lds, s);
+    if (!cluster) return go_sym<1, false>(batch, a, blocks, threads, lds, s);
     switch (sclass) {
-    case 0: return go_num<1, true>(a, blocks, threads, lds, s);
-    case 1: return go_num<2, true>(a, blocks, threads, lds, s);
-    case 2: return go_num<4, true>(a, blocks, threads, lds, s);
-    case 3: return go_num<8, true>(a, blocks, threads, lds, s);
-    default: return go_num<16, true>(a, blocks, threads, lds, s);
+    case 0: return go_sym<1, true>(batch, a, blocks, threads, lds, s);
+    case 1: return go_sym<2, true>(batch, a, blocks, threads, lds, s);
+    case 2: return go_sym<4, true>(batch, a, blocks, threads, lds, s);
+    case 3: return go_sym<8, true>(batch, a, blocks, threads, lds, s);
+    default: return go_sym<16, true>(batch, a, blocks, threads, lds, s);
+    }
+}
+
+hipError_t launch_num(int sclass, bool cluster, bool batch, const SpArgs &a, int blocks, int threads, size_t lds,
+                      hipStream_t s)
+{
+    if (!cluster) return go_num<1, false>(batch, a, blocks, threads, lds, s);
+    switch (sclass) {
+    case 0: return go_num<1, true>(batch, a, blocks, threads, lds, s);
+    case 1: return go_num<2, true>(batch, a, blocks, threads, lds, s);
+    case 2: return go_num<4, true>(batch, a, blocks, threads, lds, s);
+    case 3: return go_num<8, true>(batch, a, blocks, threads, lds, s);
+    default: return go_num<16, true>(batch, a, blocks, threads, lds, s);
     }
 }
 

@@ -92,6 +92,28 @@ struct Workspace {
 size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, char *base,
                         Workspace *ws);
 
+// ------------------------------------------------------------ batches
+// One product of a batch as the kernels see it (device copy).  Units of all
+// products are numbered consecutively (unit_base); C row offsets of product
+// p occupy nrows+1 entries from seg_base of one flat array, and its columns
+// and values start at out_base of the flat output arrays.
+struct BatchProb {
+    const int64_t *a_rp;
+    const int32_t *a_col;
+    const double *a_val;
+    const int64_t *cl_row_ptr;
+    const int32_t *perm;
+    const int64_t *cl_col_ptr;
+    const int32_t *cl_col;
+    const uint16_t *cl_mask;
+    const int64_t *cl_val_ptr;
+    const double *cl_val;
+    const int64_t *b_rp;
+    const int32_t *b_col;
+    const double *b_val;
+    int64_t unit_base, nunits, seg_base, nrows, out_base, cap, ncols;
+};
+
 // ------------------------------------------------------------ kernel interface
 struct SpArgs {
     // A as CSR
@@ -129,18 +151,27 @@ struct SpArgs {
     double *dense_vals;
     int64_t dense_words;
     int64_t ncols;
+    // batch launches: the products, their unit bases [nprob+1], the bin's
+    // unit count and start in device memory, per-product error words
+    const BatchProb *batch;
+    const int64_t *batch_units;
+    int nprob, bin;
+    const int64_t *dcount, *dbegin;
+    uint32_t *errs;
 };
 
 // error flag bits
 enum : uint32_t { kErrCapacity = 1u, kErrCount = 2u, kErrPtr = 4u, kErrRange = 8u, kErrUnsorted = 16u };
 
 // launchers (kernels.hip)
-hipError_t launch_sym(int sclass, bool cluster, const SpArgs &a, int blocks, int threads, size_t lds,
+// batch = true: persistent launches over a batch (unit ids are batch-wide,
+// the bin's count and start are read from device memory)
+hipError_t launch_sym(int sclass, bool cluster, bool batch, const SpArgs &a, int blocks, int threads, size_t lds,
                       hipStream_t s);
-hipError_t launch_num(int sclass, bool cluster, const SpArgs &a, int blocks, int threads, size_t lds,
+hipError_t launch_num(int sclass, bool cluster, bool batch, const SpArgs &a, int blocks, int threads, size_t lds,
                       hipStream_t s);
-hipError_t launch_sym_dense(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
-hipError_t launch_num_dense(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
+hipError_t launch_sym_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s);
+hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s);
 
 // launchers (util.hip)
 struct BinArgs {
@@ -158,12 +189,23 @@ struct BinArgs {
     int sym_tmax_log2;
     int num_tmax_by_class[kSClasses];
     int load_pct;
+    // batch: unit ids are batch-wide; c_rp is the flat row-offset array
+    const BatchProb *batch;
+    const int64_t *batch_units;
+    int nprob;
 };
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s);
 hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
+// batches
+hipError_t launch_max_i64(const int64_t *x, int64_t n, int64_t *out, hipStream_t s);
+hipError_t launch_bin_begin(const int64_t *counts, int nbins, int64_t *begin, hipStream_t s);
+hipError_t launch_batch_bound(const BatchProb *batch, int nprob, bool cluster, int64_t *ub, hipStream_t s);
+hipError_t launch_batch_seg_tail(const BatchProb *batch, int nprob, int64_t *flat, hipStream_t s);
+hipError_t launch_batch_seg_rebase(const BatchProb *batch, const int64_t *segs, int nprob, int64_t *flat,
+                                   int64_t nflat, int64_t *base, int64_t *nnz, hipStream_t s);
 hipError_t launch_scatter(const uint8_t *bin, int64_t n, int32_t *hist, int nbins, int64_t *counts, int32_t *order,
                           hipStream_t s);
 int bin_blocks(int64_t nunits);

@@ -6,6 +6,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "unit.h"
 
 namespace hcsp {
 
@@ -59,11 +60,57 @@ __device__ __forceinline__ void chunk_of(int64_t n, int64_t *b, int64_t *e)
     *e = min(n, *b + ch);
 }
 
+// A unit's arrays for the work estimate: the unit's own product, or in a
+// batch the product holding batch-wide unit g.
+struct WorkView {
+    const int64_t *b_rp;
+    const int32_t *col;  // A's columns, or the cluster's union columns
+    const int32_t *perm;
+    int64_t *c_rp;
+    int64_t it0, it1, pos0, u;
+    int s;
+};
+
+template <bool CL, bool BATCH>
+__device__ __forceinline__ WorkView work_view(const BinArgs &a, int64_t g)
+{
+    WorkView w;
+    const int64_t *a_rp = a.a_rp, *cl_row_ptr = a.cl_row_ptr, *cl_col_ptr = a.cl_col_ptr;
+    w.b_rp = a.b_rp;
+    w.col = CL ? a.cl_col : a.a_col;
+    w.perm = a.perm;
+    w.c_rp = a.c_rp;
+    w.u = g;
+    if (BATCH) {
+        const int p = batch_find(a.batch_units, a.nprob, g);
+        const BatchProb &bp = a.batch[p];
+        a_rp = bp.a_rp;
+        cl_row_ptr = bp.cl_row_ptr;
+        cl_col_ptr = bp.cl_col_ptr;
+        w.b_rp = bp.b_rp;
+        w.col = CL ? bp.cl_col : bp.a_col;
+        w.perm = bp.perm;
+        w.c_rp = a.c_rp + bp.seg_base;
+        w.u = g - bp.unit_base;
+    }
+    if (CL) {
+        w.it0 = cl_col_ptr[w.u];
+        w.it1 = cl_col_ptr[w.u + 1];
+        w.pos0 = cl_row_ptr[w.u];
+        w.s = (int)(cl_row_ptr[w.u + 1] - w.pos0);
+    } else {
+        w.it0 = a_rp[w.u];
+        w.it1 = a_rp[w.u + 1];
+        w.pos0 = w.u;
+        w.s = 1;
+    }
+    return w;
+}
+
 // One group of 16 lanes per unit: probes = sum of |B_k| over the unit's
 // columns k (an upper bound on its distinct output columns) and its
-// symbolic bin.  Units with
-// no products get their zero row counts here.
-template <bool CL>
+// symbolic bin.  Units with no products get their zero row counts here.
+template <bool CL, bool BATCH>
 __global__ void __launch_bounds__(256) k_work(BinArgs a)
 {
     __shared__ int hist[kSymBins];
@@ -73,31 +120,22 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
     int64_t cb, ce;
     chunk_of(a.nunits, &cb, &ce);
     for (int64_t u = cb + (threadIdx.x >> 4); u < ce; u += blockDim.x >> 4) {
-        int64_t it0, it1, pos0 = u;
-        int s = 1;
-        if (CL) {
-            it0 = a.cl_col_ptr[u];
-            it1 = a.cl_col_ptr[u + 1];
-            pos0 = a.cl_row_ptr[u];
-            s = (int)(a.cl_row_ptr[u + 1] - pos0);
-        } else {
-            it0 = a.a_rp[u];
-            it1 = a.a_rp[u + 1];
-        }
+        const WorkView w = work_view<CL, BATCH>(a, u);
         int64_t probes = 0;
-        for (int64_t q = it0 + g.gl; q < it1; q += 16) {
-            const int k = CL ? a.cl_col[q] : a.a_col[q];
-            probes += a.b_rp[k + 1] - a.b_rp[k];
+        for (int64_t q = w.it0 + g.gl; q < w.it1; q += 16) {
+            const int k = w.col[q];
+            probes += w.b_rp[k + 1] - w.b_rp[k];
         }
         probes = gsum64(g, probes);
-        const int bin = probes == 0 ? kBinEmpty : sym_bin(sclass_of(s), probes, a.sym_tmax_log2);
+        const int bin = probes == 0 ? kBinEmpty : sym_bin(sclass_of(w.s), probes, a.sym_tmax_log2);
         if (g.gl == 0) {
             a.ws.probes[u] = probes;
             a.ws.bin[u] = (uint8_t)bin;
             atomicAdd(&hist[bin], 1);
             if (bin == kBinEmpty) {
                 a.ws.ucount[u] = 0;
-                for (int l = 0; l < s; ++l) a.c_rp[CL ? (int64_t)a.perm[pos0 + l] : u] = 0;
+                if (a.c_rp)  // null: estimate only
+                    for (int l = 0; l < w.s; ++l) w.c_rp[CL ? (int64_t)w.perm[w.pos0 + l] : w.u] = 0;
             }
         }
     }
@@ -115,14 +153,17 @@ hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s)
 {
     if (a.nunits <= 0) return hipSuccess;
     const int blocks = bin_blocks(a.nunits);
-    if (cluster) hipLaunchKernelGGL((k_work<true>), dim3(blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_work<false>), dim3(blocks), dim3(256), 0, s, a);
+    const bool batch = a.batch != nullptr;
+    if (cluster && batch) hipLaunchKernelGGL((k_work<true, true>), dim3(blocks), dim3(256), 0, s, a);
+    else if (cluster) hipLaunchKernelGGL((k_work<true, false>), dim3(blocks), dim3(256), 0, s, a);
+    else if (batch) hipLaunchKernelGGL((k_work<false, true>), dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_work<false, false>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 // Numeric bin from the exact number of distinct output columns found by the
 // symbolic phase: the smallest table that keeps the fill below load_pct.
-template <bool CL>
+template <bool CL, bool BATCH>
 __global__ void __launch_bounds__(256) k_numbin(BinArgs a)
 {
     __shared__ int hist[kNumBins];
@@ -131,7 +172,11 @@ __global__ void __launch_bounds__(256) k_numbin(BinArgs a)
     int64_t cb, ce;
     chunk_of(a.nunits, &cb, &ce);
     for (int64_t u = cb + threadIdx.x; u < ce; u += blockDim.x) {
-        const int s = CL ? (int)(a.cl_row_ptr[u + 1] - a.cl_row_ptr[u]) : 1;
+        int s = 1;
+        if (CL) {
+            const WorkView w = work_view<CL, BATCH>(a, u);
+            s = w.s;
+        }
         const int sc = sclass_of(s);
         const int32_t U = a.ws.ucount[u];
         int bin;
@@ -162,8 +207,118 @@ hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s)
 {
     if (a.nunits <= 0) return hipSuccess;
     const int blocks = bin_blocks(a.nunits);
-    if (cluster) hipLaunchKernelGGL((k_numbin<true>), dim3(blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_numbin<false>), dim3(blocks), dim3(256), 0, s, a);
+    const bool batch = a.batch != nullptr;
+    if (cluster && batch) hipLaunchKernelGGL((k_numbin<true, true>), dim3(blocks), dim3(256), 0, s, a);
+    else if (cluster) hipLaunchKernelGGL((k_numbin<true, false>), dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_numbin<false, false>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batches
+// Largest value of x[0..n) into *out (which must hold a value <= it).
+__global__ void __launch_bounds__(256) k_max_i64(const int64_t *x, int64_t n, int64_t *out)
+{
+    int64_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, x[i]);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long *)out, (unsigned long long)m);
+}
+
+hipError_t launch_max_i64(const int64_t *x, int64_t n, int64_t *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_max_i64, dim3((unsigned)blocks), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+// Start of every bin in the unit order (exclusive prefix of the bin sizes),
+// kept on the device so batch launches need no host read-back.
+__global__ void k_bin_begin(const int64_t *counts, int nbins, int64_t *begin)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int64_t acc = 0;
+        for (int b = 0; b < nbins; ++b) {
+            begin[b] = acc;
+            acc += counts[b];
+        }
+    }
+}
+
+hipError_t launch_bin_begin(const int64_t *counts, int nbins, int64_t *begin, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_begin, dim3(1), dim3(64), 0, s, counts, nbins, begin);
+    return hipGetLastError();
+}
+
+// Upper bound on nnz(C_p) for every product p of a batch: the number of
+// products sum_i sum_{k in A_i} |B_k| (a cluster counts every member row that
+// has column k).  ub[] must be zero on entry; blockIdx.y splits a product.
+template <bool CL>
+__global__ void __launch_bounds__(256) k_batch_bound(const BatchProb *batch, int64_t *ub)
+{
+    const BatchProb &bp = batch[blockIdx.x];
+    const int64_t n = CL ? (bp.nunits > 0 ? bp.cl_col_ptr[bp.nunits] : 0) : (bp.nrows > 0 ? bp.a_rp[bp.nrows] : 0);
+    int64_t s = 0;
+    for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.y * blockDim.x) {
+        const int k = CL ? bp.cl_col[q] : bp.a_col[q];
+        const int64_t len = bp.b_rp[k + 1] - bp.b_rp[k];
+        s += CL ? len * __popc((uint32_t)bp.cl_mask[q]) : len;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ub[blockIdx.x], (unsigned long long)s);
+}
+
+hipError_t launch_batch_bound(const BatchProb *batch, int nprob, bool cluster, int64_t *ub, hipStream_t s)
+{
+    if (nprob <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nprob, 16);
+    if (cluster) hipLaunchKernelGGL((k_batch_bound<true>), grid, dim3(256), 0, s, batch, ub);
+    else hipLaunchKernelGGL((k_batch_bound<false>), grid, dim3(256), 0, s, batch, ub);
+    return hipGetLastError();
+}
+
+// Row counts of product p sit in flat[seg_base .. seg_base + nrows), with a
+// zero after them; one exclusive scan of the whole flat array is then made
+// local to every product by subtracting the value at its segment start.
+__global__ void k_seg_tail(const BatchProb *batch, int nprob, int64_t *flat)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) flat[batch[p].seg_base + batch[p].nrows] = 0;
+}
+
+__global__ void k_seg_base(const BatchProb *batch, int nprob, const int64_t *flat, int64_t *base, int64_t *nnz)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) {
+        const int64_t b = flat[batch[p].seg_base];
+        base[p] = b;
+        nnz[p] = flat[batch[p].seg_base + batch[p].nrows] - b;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_seg_sub(const int64_t *segs, int nprob, int64_t *flat, int64_t nflat,
+                                                 const int64_t *base)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nflat; x += (int64_t)gridDim.x * blockDim.x)
+        flat[x] -= base[batch_find(segs, nprob, x)];
+}
+
+hipError_t launch_batch_seg_tail(const BatchProb *batch, int nprob, int64_t *flat, hipStream_t s)
+{
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_tail, dim3((nprob + 255) / 256), dim3(256), 0, s, batch, nprob, flat);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_seg_rebase(const BatchProb *batch, const int64_t *segs, int nprob, int64_t *flat,
+                                   int64_t nflat, int64_t *base, int64_t *nnz, hipStream_t s)
+{
+    if (nprob <= 0 || nflat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_base, dim3((nprob + 255) / 256), dim3(256), 0, s, batch, nprob, flat, base, nnz);
+    const int64_t blocks = std::min<int64_t>((nflat + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_seg_sub, dim3((unsigned)blocks), dim3(256), 0, s, segs, nprob, flat, nflat, base);
     return hipGetLastError();
 }
 

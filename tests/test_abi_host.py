@@ -24,7 +24,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     L = hc.lib()
     names = declared_symbols()
-    assert len(names) == 13
+    assert len(names) == 17
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(hc._SIGS), "binding and header disagree"
@@ -105,3 +105,41 @@ def test_workspace_query_is_host_only():
     b.nrows = 49                                      # A.ncols != B.nrows
     rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b), None, ctypes.byref(n))
     assert rc == -1 and "B.nrows" in hc.last_error()
+
+
+def fake_item(kind, nrows, ncols, p):
+    it = hc.c_batch_item()
+    it.A.kind = kind
+    if kind == hc.OP_CSR:
+        it.A.csr = hc.c_csr(nrows, ncols, 10, 1, 1, 1)
+    else:
+        it.A.cl = hc.c_csr_cluster(nrows, ncols, (nrows + 1) // 2, 10, 20, 2, 0, 1, 1, 1, 1, 1, 1, 1)
+    it.B = hc.c_csr(ncols, p, 10, 1, 1, 1)
+    return it
+
+
+def test_batch_plan_init_is_host_only():
+    # sizes only: unit and row totals, flat row-offset length, widest B, workspace bytes
+    items = (hc.c_batch_item * 3)(fake_item(0, 100, 50, 70), fake_item(0, 0, 5, 5), fake_item(0, 30, 40, 900))
+    plan = hc.batch_plan_init(items)
+    assert (plan.count, plan.units, plan.rows, plan.row_ptr_len, plan.max_ncols) == (3, 130, 130, 133, 900)
+    assert plan.ws_bytes > 0 and plan.prepared == 0
+    cl = (hc.c_batch_item * 2)(fake_item(1, 9, 50, 70), fake_item(1, 4, 5, 5))
+    plan = hc.batch_plan_init(cl)
+    assert plan.kind == hc.OP_CLUSTER and plan.units == 5 + 2 and plan.max_class == 1
+
+
+def test_batch_plan_init_errors():
+    mixed = (hc.c_batch_item * 2)(fake_item(0, 10, 5, 5), fake_item(1, 10, 5, 5))
+    with pytest.raises(hc.HcspError) as e:
+        hc.batch_plan_init(mixed)
+    assert e.value.status == -1 and "same kind" in str(e.value)
+    bad = (hc.c_batch_item * 2)(fake_item(0, 10, 5, 5), fake_item(0, 10, 6, 5))
+    bad[1].B.nrows = 7                                # A.ncols != B.nrows in item 1
+    with pytest.raises(hc.HcspError) as e:
+        hc.batch_plan_init(bad)
+    assert "item 1" in str(e.value)
+    # an unprepared plan is refused before any device work
+    plan = hc.batch_plan_init((hc.c_batch_item * 1)(fake_item(0, 10, 5, 5)))
+    rc = hc.lib().hcsp_spgemm_batched(ctypes.byref(plan), None, None, None, None, 0, None)
+    assert rc == -1 and "prepared" in hc.last_error()

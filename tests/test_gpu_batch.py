@@ -1,0 +1,128 @@
+"""GPU parity of the batched path: many products of uneven sizes in one
+launch sequence, each compared bit for bit with the CPU oracle, and the same
+launch sequence captured into a graph and replayed."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2507_21253_amd as hc  # noqa: E402
+
+
+def dev(H):
+    return hc.DeviceCSR.from_host(H)
+
+
+def assert_same(Cg, Cr, where=""):
+    np.testing.assert_array_equal(Cg.rp, Cr.rp, err_msg="row_ptr " + where)
+    np.testing.assert_array_equal(Cg.col, Cr.col, err_msg="col " + where)
+    np.testing.assert_array_equal(Cg.val, Cr.val, err_msg="val " + where)
+
+
+def problems(seeds, n_lo=100, n_hi=4000):
+    return [synth.batch_problem(s, n_lo, n_hi)[1] for s in seeds]
+
+
+def check_batch(bt, hosts, refs=None):
+    torch.cuda.synchronize()
+    nnz = bt.status()
+    for p, H in enumerate(hosts):
+        ref = refs[p] if refs is not None else oracle.spgemm(H, H)
+        assert nnz[p] == ref.nnz, "product %d" % p
+        assert_same(bt.result(p, int(nnz[p])).to_host(), ref, "product %d" % p)
+
+
+def test_batch_mixed_generators_bitwise():
+    hosts = problems(range(1000, 1024))
+    bt = hc.Batch([(d, d) for d in map(dev, hosts)])
+    bt.run()
+    check_batch(bt, hosts)
+
+
+def test_batch_degenerate_members():
+    # an empty product, one with empty rows, a 1x1 one, and rectangular A*B
+    Z = synth.HostCSR(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0), 0, 0)
+    E = synth.HostCSR(np.zeros(8, np.int64), np.zeros(0, np.int32), np.zeros(0), 7, 7)
+    one = synth.from_dense(np.array([[3.0]]))
+    A = synth.uniform(90, 60, 5, 11)
+    B = synth.uniform(60, 130, 7, 12)
+    pairs = [(Z, Z), (E, E), (one, one), (A, B), (synth.stencil(5, 9, 3), synth.stencil(5, 9, 3))]
+    bt = hc.Batch([(dev(a), dev(b)) for a, b in pairs])
+    bt.run()
+    torch.cuda.synchronize()
+    nnz = bt.status()
+    for p, (a, b) in enumerate(pairs):
+        ref = oracle.spgemm(a, b)
+        assert nnz[p] == ref.nnz
+        assert_same(bt.result(p, int(nnz[p])).to_host(), ref, "product %d" % p)
+
+
+def test_batch_forced_dense_path_bitwise():
+    # small shared-memory tables push the larger units onto the global-memory path
+    hosts = problems(range(1100, 1108), 200, 2000) + [synth.uniform(300, 300, 30, 5)]
+    bt = hc.Batch([(d, d) for d in map(dev, hosts)], hc.opts(sym_tmax_log2=7, num_tmax=96))
+    bt.run()
+    check_batch(bt, hosts)
+
+
+def test_batch_equals_unbatched_gpu():
+    hosts = problems(range(1200, 1210), 500, 6000)
+    ds = [dev(H) for H in hosts]
+    bt = hc.Batch([(d, d) for d in ds])
+    bt.run()
+    torch.cuda.synchronize()
+    nnz = bt.status()
+    for p, d in enumerate(ds):
+        C = hc.spgemm(d, d).to_host()
+        assert_same(bt.result(p, int(nnz[p])).to_host(), C, "product %d" % p)
+
+
+def test_batch_of_clustered_operands_bitwise():
+    hosts = problems(range(1300, 1310), 200, 3000)
+    pairs = []
+    for i, H in enumerate(hosts):
+        plan = hc.plan_hierarchical(H, (3, 10), [2, 4, 8, 16][i % 4])
+        D = dev(H)
+        pairs.append((hc.cluster_build(D, plan), D))
+    bt = hc.Batch(pairs)
+    bt.run()
+    check_batch(bt, hosts)
+
+
+def test_batch_graph_replays():
+    # the whole launch sequence captured once; A's values change between
+    # replays (same structure), eager work runs in between, every replay checked
+    hosts = problems(range(1400, 1412), 200, 5000)
+    ds = [dev(H) for H in hosts]
+    bt = hc.Batch([(d, d) for d in ds])
+    bt.run()                                  # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            bt.run(s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep, scale in enumerate([1.0, -0.5, 2.0]):
+        for d in ds:
+            d.val.mul_(scale)                 # eager work between replays
+        torch.cuda.synchronize()
+        cur = []
+        for H, d in zip(hosts, ds):
+            Hs = synth.HostCSR(H.rp, H.col, d.val.cpu().numpy(), H.nrows, H.ncols)
+            cur.append(oracle.spgemm(Hs, Hs))
+        bt.C_col.fill_(-1)
+        bt.C_val.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        check_batch(bt, hosts, cur)
