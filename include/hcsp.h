@@ -124,15 +124,18 @@ enum {
     HCSP_F_SYNC_CHECK = 1   /* numeric: synchronize and report out-of-range writes as HCSP_E_CAPACITY */
 };
 typedef struct hcsp_opts {
-    int32_t lanes;          /* lanes per row/cluster group: 0 = automatic, else 8, 16, 32 or 64 */
+    int32_t lanes;          /* lanes per row/cluster: 0 = automatic (one 64-lane wavefront) or 64 */
     int32_t flags;          /* HCSP_F_* */
     int64_t unit_lo;        /* numeric: first unit (row of a CSR A, cluster of a CSR_Cluster A) */
     int64_t unit_hi;        /* numeric: one past the last unit; <= 0 means all units */
     int64_t out_base;       /* numeric: C_col_d/C_val_d point at global entry out_base of C */
-    int32_t dense_slots;    /* concurrent dense accumulators for very long rows: 0 = default (64) */
+    int32_t dense_slots;    /* concurrent dense accumulators for very long rows: 0 = default (32) */
     int32_t load_pct;       /* numeric hash-table fill target in percent: 0 = default (60) */
     int32_t sym_tmax_log2;  /* largest shared-memory symbolic table, log2 slots: 0 = default */
     int32_t num_tmax;       /* largest shared-memory numeric table, slots: 0 = default */
+    int32_t sym_load_pct;   /* symbolic tables get >= products*100/sym_load_pct slots (products: the
+                               unit's upper bound on distinct columns), 10..100: 0 = default (70) */
+    int32_t reserved;
 } hcsp_opts;
 
 #define HCSP_MAX_BINS 96

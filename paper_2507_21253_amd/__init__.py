@@ -56,7 +56,8 @@ class c_ratio(ctypes.Structure):
 
 class c_opts(ctypes.Structure):
     _fields_ = [("lanes", i32), ("flags", i32), ("unit_lo", i64), ("unit_hi", i64), ("out_base", i64),
-                ("dense_slots", i32), ("load_pct", i32), ("sym_tmax_log2", i32), ("num_tmax", i32)]
+                ("dense_slots", i32), ("load_pct", i32), ("sym_tmax_log2", i32), ("num_tmax", i32),
+                ("sym_load_pct", i32), ("reserved", i32)]
 
 
 class c_sym_info(ctypes.Structure):

@@ -95,6 +95,8 @@ static int make_tune(const hcsp_opts *o, const hcsp_csr *B, bool need_device, Tu
     t->G = 64;
     t->load_pct = o->load_pct ? o->load_pct : 60;
     if (t->load_pct < 10 || t->load_pct > 95) return fail(HCSP_E_INVALID, "opts.load_pct must be in 10..95");
+    t->sym_load_pct = o->sym_load_pct ? o->sym_load_pct : 70;
+    if (t->sym_load_pct < 10 || t->sym_load_pct > 100) return fail(HCSP_E_INVALID, "opts.sym_load_pct must be in 10..100");
     t->lds_budget = need_device ? lds_limit() : 64 * 1024;
     int sym = kSymLog2Max;
     while (sym > kSymLog2Min && sym_wave_bytes(true, 1 << sym) > t->lds_budget) --sym;
@@ -230,6 +232,7 @@ static BinArgs bin_args(const hcsp_operand *A, const hcsp_csr *B, const Workspac
     b.sym_tmax_log2 = tu.sym_tmax_log2;
     num_tmax_classes(tu, A->kind == HCSP_OP_CLUSTER, b.num_tmax_by_class);
     b.load_pct = tu.load_pct;
+    b.sym_load_pct = tu.sym_load_pct;
     return b;
 }
 
@@ -305,6 +308,7 @@ static BinArgs batch_bin_args(const hcsp_batch_plan &plan, const BatchWs &ws, co
     b.sym_tmax_log2 = tu.sym_tmax_log2;
     num_tmax_classes(tu, plan.kind == HCSP_OP_CLUSTER, b.num_tmax_by_class);
     b.load_pct = tu.load_pct;
+    b.sym_load_pct = tu.sym_load_pct;
     b.batch = ws.probs;
     b.batch_units = ws.units;
     b.nprob = plan.count;
@@ -764,8 +768,9 @@ int hcsp_spgemm_batched(const hcsp_batch_plan *plan, int64_t *C_row_ptr_d, int32
     a.order = ws.w.order_sym;
     a.dcount = ws.w.sym_count;
     a.dbegin = ws.sym_begin;
+    const int64_t sym_need = (plan->max_probes * 100 + tu.sym_load_pct - 1) / tu.sym_load_pct;
     int sym_l2 = kSymLog2Min;
-    while (sym_l2 < tu.sym_tmax_log2 && ((int64_t)1 << sym_l2) < plan->max_probes) ++sym_l2;
+    while (sym_l2 < tu.sym_tmax_log2 && ((int64_t)1 << sym_l2) < sym_need) ++sym_l2;
     for (int sc = 0; sc <= (cl ? plan->max_class : 0); ++sc) {
         for (int l2 = kSymLog2Min; l2 <= sym_l2; ++l2) {
             a.bin = 1 + sc * kSymT + (l2 - kSymLog2Min);
@@ -781,7 +786,7 @@ int hcsp_spgemm_batched(const hcsp_batch_plan *plan, int64_t *C_row_ptr_d, int32
             HCSP_HIP(launch_sym(sc, cl, true, a, blocks, threads, lds, s));
         }
     }
-    const bool dense = plan->max_probes > ((int64_t)1 << tu.sym_tmax_log2);
+    const bool dense = sym_need > ((int64_t)1 << tu.sym_tmax_log2);
     if (dense) {
         a.bin = kSymGlobal;
         HCSP_HIP(launch_fill_u32(ws.w.dense_bits, (int64_t)tu.dense_slots * ws.w.dense_words, 0u, s));

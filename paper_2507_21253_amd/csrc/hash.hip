@@ -253,8 +253,9 @@ __device__ __forceinline__ Pass<MS, NUM> fetch_pass(const SpArgs &a, const ItemR
 // distinct columns of the union (used to size the numeric tables) and their
 // smallest and largest value (used by the numeric phase's hash).  Keys go
 // into a power-of-two open-addressing table with a multiplicative hash; the
-// table has at least as many slots as the unit has products, so it never
-// fills.  For clusters each key carries the OR of the masks of the columns k
+// table has at least as many slots as the unit has products (by default
+// 100/70 times as many, so it stays at most 70% full even when nearly every
+// product hits a new column), so it never fills.  For clusters each key carries the OR of the masks of the columns k
 // that reached it: row l's count is the number of keys whose bit l got set,
 // counted (by ballot) when the bit first appears.
 template <int S, bool CL>

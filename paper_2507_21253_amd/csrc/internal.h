@@ -61,6 +61,7 @@ int64_t num_wave_bytes(bool cl, int sclass, int T);
 struct Tune {
     int G;               // lanes per unit (one wavefront)
     int load_pct;        // numeric table fill target
+    int sym_load_pct;    // symbolic table fill bound (percent of the product count)
     int sym_tmax_log2;   // largest symbolic table
     int num_tmax;        // largest numeric table
     int dense_slots;     // concurrent dense accumulators
@@ -189,6 +190,7 @@ struct BinArgs {
     int sym_tmax_log2;
     int num_tmax_by_class[kSClasses];
     int load_pct;
+    int sym_load_pct;
     // batch: unit ids are batch-wide; c_rp is the flat row-offset array
     const BatchProb *batch;
     const int64_t *batch_units;

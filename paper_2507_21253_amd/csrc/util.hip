@@ -40,9 +40,11 @@ __device__ __forceinline__ int ceil_log2(int64_t x)
     return l;
 }
 
-__device__ __forceinline__ int sym_bin(int sc, int64_t probes, int tmax_log2)
+// Table size: the smallest power of two with at least probes*100/load_pct
+// slots (the product count bounds the number of distinct columns).
+__device__ __forceinline__ int sym_bin(int sc, int64_t probes, int tmax_log2, int load_pct)
 {
-    int l = ceil_log2(probes);
+    int l = ceil_log2((probes * 100 + load_pct - 1) / load_pct);
     if (l < kSymLog2Min) l = kSymLog2Min;
     if (l > tmax_log2) return kSymGlobal;
     return 1 + sc * kSymT + (l - kSymLog2Min);
@@ -127,7 +129,7 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
             probes += w.b_rp[k + 1] - w.b_rp[k];
         }
         probes = gsum64(g, probes);
-        const int bin = probes == 0 ? kBinEmpty : sym_bin(sclass_of(w.s), probes, a.sym_tmax_log2);
+        const int bin = probes == 0 ? kBinEmpty : sym_bin(sclass_of(w.s), probes, a.sym_tmax_log2, a.sym_load_pct);
         if (g.gl == 0) {
             a.ws.probes[u] = probes;
             a.ws.bin[u] = (uint8_t)bin;

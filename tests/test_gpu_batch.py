@@ -126,3 +126,39 @@ def test_batch_graph_replays():
         g.replay()
         torch.cuda.synchronize()
         check_batch(bt, hosts, cur)
+
+
+def test_batch_full_size_sampled_rows():
+    # the full batch (512 products, seeds 1000..1511, 1e3..2e5 rows each) in the
+    # launch configuration the benchmark replays; sampled rows of every product
+    # are compared with the oracle row by row, and every row count is checked
+    # against the closed upper bound
+    hosts = [synth.batch_problem(s)[1] for s in range(1000, 1512)]
+    ds = [dev(H) for H in hosts]
+    bt = hc.Batch([(d, d) for d in ds])
+    g = torch.cuda.CUDAGraph()
+    bt.run()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            bt.run(s)
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    nnz = bt.status()
+    rp_all = bt.C_row_ptr.cpu().numpy()
+    rng = np.random.default_rng(7)
+    for p, H in enumerate(hosts):
+        s0 = int(bt.seg_off[p])
+        rp = rp_all[s0:s0 + H.nrows + 1]
+        assert rp[0] == 0 and rp[-1] == nnz[p]
+        rows = [0, H.nrows - 1] + list(rng.integers(0, H.nrows, 3))
+        o0 = int(bt.out_off[p])
+        for r in rows:
+            ref = oracle.spgemm(H, H, (int(r), int(r) + 1))
+            b, e = int(rp[r]), int(rp[r + 1])
+            assert e - b == ref.nnz, "product %d row %d" % (p, r)
+            np.testing.assert_array_equal(bt.C_col[o0 + b:o0 + e].cpu().numpy(), ref.col)
+            np.testing.assert_array_equal(bt.C_val[o0 + b:o0 + e].cpu().numpy(), ref.val)
