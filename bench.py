@@ -47,15 +47,17 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--m", type=int, default=100, help="stencil grid side")
-    p.add_argument("--max-cluster", type=int, default=2)
+    p.add_argument("--max-cluster", type=int, default=0,
+                   help="rows per cluster at most (0: the autotuner's choice for the matrix class, else 2)")
     p.add_argument("--sim", choices=["root", "union"], default="root")
     p.add_argument("--lanes", type=int, default=0)
     p.add_argument("--mode", choices=["bench", "copy", "batch"], default="bench",
                    help="bench: the stencil workload (the headline line); batch: 512 uneven products replayed "
                         "as one captured graph; copy: device copy for counter calibration")
     p.add_argument("--batch-count", type=int, default=512)
-    p.add_argument("--load-pct", type=int, default=0, help="numeric table fill target (0: library default)")
-    p.add_argument("--sym-load-pct", type=int, default=0, help="symbolic table fill bound (0: library default)")
+    p.add_argument("--load-pct", type=int, default=0, help="numeric table fill target (0: autotuned)")
+    p.add_argument("--sym-load-pct", type=int, default=0, help="symbolic table fill bound (0: autotuned)")
+    p.add_argument("--untuned", action="store_true", help="ignore the autotuner's table")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-threads", type=int, default=0)
     return p.parse_args()
@@ -117,16 +119,36 @@ def batch_mode(args):
         products += int(np.diff(H.rp)[H.col].sum())
     log("batch: %d products, %d rows, %d A entries, %d products (%.1fs)"
         % (len(hosts), rows, sum(H.nnz for H in hosts), products, time.perf_counter() - t))
-    bt_opts = hc.opts(load_pct=args.load_pct, sym_load_pct=args.sym_load_pct)
-    bt = hc.Batch([(d, d) for d in ds], bt_opts)
-    bt.run()
+    # the autotuner's choice per matrix class: table options and, where it pays, hierarchical clusters;
+    # products with equal choices form one batch, and all batches go into one graph
+    from paper_2507_21253_amd import tune
+    table = tune.TuneTable() if args.untuned else tune.TuneTable.load()
+    groups = {}
+    t = time.perf_counter()
+    for H, d in zip(hosts, ds):
+        e = table.lookup(hc.features(H))
+        if args.load_pct or args.sym_load_pct:
+            e = dict(e, path="plain", load_pct=args.load_pct or 60, sym_load_pct=args.sym_load_pct or 70)
+        key = (e["path"], e["max_cluster"], e["sym_load_pct"], e["load_pct"])
+        A = d
+        if e["path"] == "hc":
+            A = hc.cluster_build(d, hc.plan_hierarchical(H, (3, 10), e["max_cluster"], hc.SIM_ROOT,
+                                                         nthreads=len(os.sched_getaffinity(0))))
+        groups.setdefault(key, []).append((A, d))
+    t_prep = time.perf_counter() - t
+    log("groups: %s (%.1fs)" % ({"%s/%d/s%d/n%d" % k: len(v) for k, v in groups.items()}, t_prep))
+    order = [pair for k in groups for pair in groups[k]]
+    bts = [hc.Batch(groups[k], hc.opts(sym_load_pct=k[2], load_pct=k[3])) for k in groups]
+    for bt in bts:
+        bt.run()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         with torch.cuda.graph(g, stream=s):
-            bt.run(s)
+            for bt in bts:
+                bt.run(s)
     torch.cuda.current_stream().wait_stream(s)
     for _ in range(args.warmup):
         g.replay()
@@ -140,9 +162,11 @@ def batch_mode(args):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / args.steps
     ms = e0.elapsed_time(e1) / args.steps
-    nnz = bt.status()
-    # the same products one at a time (symbolic, read-back, numeric each), for comparison
-    Ps = [hc.Product(d, d, bt_opts) for d in ds]
+    nnz_by = {id(A): z for bt in bts for (A, _), z in zip(bt.pairs, bt.status())}
+    nnz = np.array([nnz_by[id(A)] for A, _ in order])
+    hosts_in_order = {id(d): H for H, d in zip(hosts, ds)}
+    # the same products one at a time with the library defaults (symbolic, read-back, numeric each)
+    Ps = [hc.Product(d, d) for _, d in order]
     for P in Ps:
         P.run()
     torch.cuda.synchronize()
@@ -153,7 +177,7 @@ def batch_mode(args):
     loop_ms = (time.perf_counter() - t0) * 1e3
     assert all(int(P.info.nnz) == int(z) for P, z in zip(Ps, nnz))
     a_bytes = sum(csr_bytes(H.nrows, H.nnz) for H in hosts)
-    c_bytes = sum(csr_bytes(H.nrows, int(z)) for H, z in zip(hosts, nnz))
+    c_bytes = sum(csr_bytes(hosts_in_order[id(d)].nrows, int(z)) for (_, d), z in zip(order, nnz))
     out = {"metric": "batched SpGEMM GFLOP/s (graph replay of one launch sequence)",
            "value": round(2 * products / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "wall_ms_per_step": round(wall, 4),
@@ -161,7 +185,9 @@ def batch_mode(args):
            "config": {"workload": "batch_%d_stencil5_stencil7_uniform" % len(hosts), "rows": rows,
                       "products": products, "nnz_C": int(nnz.sum())},
            "gbs_compulsory": round((2 * a_bytes + c_bytes) / (ms * 1e-3) / 1e9, 2),
-           "one_at_a_time_ms": round(loop_ms, 3), "speedup_vs_one_at_a_time": round(loop_ms / ms, 3)}
+           "one_at_a_time_ms": round(loop_ms, 3), "speedup_vs_one_at_a_time": round(loop_ms / ms, 3),
+           "tuned_groups": {"%s/%d/s%d/n%d" % k: len(v) for k, v in groups.items()},
+           "tuned_prep_s": round(t_prep, 2)}
     print(json.dumps(out), flush=True)
 
 
@@ -212,6 +238,13 @@ def main():
     products = int(rowlen[M.col].sum())
     flop = 2 * products
 
+    # ---- the autotuner's choices for this matrix class (table options, cluster size)
+    from paper_2507_21253_amd import tune
+    tuned = (tune.TuneTable() if args.untuned else tune.TuneTable.load()).lookup(hc.features(M))
+    if not args.max_cluster:
+        args.max_cluster = tuned["best_cluster_size"] if tuned["tuned"] else 2
+    log("tuner: %s" % tuned)
+
     # ---- preprocessing: hierarchical plan on the host, CSR_Cluster on the device
     ncpu = len(os.sched_getaffinity(0))
     t = time.perf_counter()
@@ -230,7 +263,8 @@ def main():
     t_build = time.perf_counter() - t
     log("CSR_Cluster: ncc %d nslots %d max %d (%.3fs)" % (Dc.ncc, Dc.nslots, Dc.max_cluster, t_build))
 
-    o = hc.opts(lanes=args.lanes, load_pct=args.load_pct, sym_load_pct=args.sym_load_pct)
+    o = hc.opts(lanes=args.lanes, load_pct=args.load_pct or tuned["load_pct"],
+                sym_load_pct=args.sym_load_pct or tuned["sym_load_pct"])
     P_cl = hc.Product(Dc, Md, o)
     P_pl = hc.Product(Md, Md, o)
     wall_cl, sym_cl, num_cl = time_product(P_cl, args.steps, args.warmup, torch)
@@ -251,7 +285,8 @@ def main():
     gflops_pl = flop / (wall_pl * 1e-3) / 1e9
     # dominant kernel family: the numeric launches; its algorithmic bytes are A (clustered), B and C
     ach = comp_cl / (num_cl * 1e-3) / 1e9
-    traffic = numeric_traffic("clustered", "m%d_mc%d_%s" % (m, args.max_cluster, args.sim))
+    traffic = numeric_traffic("clustered", "m%d_mc%d_%s_s%d_n%d" % (m, args.max_cluster, args.sim, o.sym_load_pct,
+                                                                    o.load_pct))
 
     cpu = None
     if not args.no_cpu:
@@ -284,7 +319,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "stencil27_%d^3_relabelled_A2" % m, "nrows": M.nrows, "nnz_A": M.nnz,
                    "nnz_C": nnzC, "products": products, "clustering": "hierarchical",
-                   "jacc_th": "3/10", "max_cluster": args.max_cluster, "similarity": args.sim},
+                   "jacc_th": "3/10", "max_cluster": args.max_cluster, "similarity": args.sim,
+                   "sym_load_pct": o.sym_load_pct, "load_pct": o.load_pct, "autotuned": bool(tuned["tuned"])},
         "gbs_compulsory": round(comp_cl / (wall_cl * 1e-3) / 1e9, 2),
         "phases_ms": {"symbolic_incl_readback": round(sym_cl, 4), "numeric": round(num_cl, 4)},
         "plain_csr": {"gflops": round(gflops_pl, 3), "ms_per_step": round(wall_pl, 4),

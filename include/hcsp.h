@@ -245,6 +245,33 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                         double *C_val_d, int64_t capacity, void *ws_d, size_t ws_bytes,
                         void *stream);
 
+/* ---------------------------------------------------------------- features
+ * HCSP_NFEATURES structure-only features of the product A x B from host
+ * copies of the patterns (A_h, B_h: host arrays; values are not read), for
+ * the autotuner's matrix classes and the learned path selector.  The paper
+ * finds that the gain of clustering and reordering depends on the sparsity
+ * pattern (Sec. "Evaluation") and proposes learning the choice (Sec.
+ * "Conclusion and Future Work"); the feature list itself is this library's:
+ *   0 log2(n+1)           1 log2(nnz+1)          2 mean row length
+ *   3 std row length      4 log2(max row len+1)  5..9 log2(row length+1) at
+ *   the 10/25/50/75/90% quantiles                10 log2(sum of products+1)
+ *   11 log2(mean products per row+1)             12 coefficient of variation
+ *   of products per row   13 log2(max products per row+1)
+ *   14/15 mean/std of |col - row| / ncols        16 mean Jaccard of rows
+ *   (i, i+1) over <= 4096 evenly spaced i        17/18 fraction of those
+ *   pairs with J >= 0.3 / 0.5                    19 column compression of
+ *   the pairs with J >= 0.3: (|S_i|+|S_i+1|)/|S_i u S_i+1|
+ *   20 padding of fixed-length clusters of 8: 8|union|/sum|S_i| over <= 512
+ *   blocks               21 mean over <= 256 sampled rows of the best
+ *   Jaccard with any row sharing a column (<= 64 rows per column)
+ *   22 products / distinct output columns over the sampled rows
+ *   23 fraction of empty rows  24..29 fraction of rows whose product count
+ *   is < 64, < 256, < 1024, < 4096, < 16384, larger  30 log2(B.ncols+1)
+ *   31 fraction of rows longer than twice the mean
+ * out[HCSP_NFEATURES] receives float32 values.  Host only. */
+#define HCSP_NFEATURES 32
+int hcsp_features(const hcsp_csr *A_h, const hcsp_csr *B_h, float *out);
+
 /* ---------------------------------------------------------------- batches
  * Many independent products C_p = A_p x B_p of uneven sizes in one fixed
  * sequence of launches: the units (rows or clusters) of all products are

@@ -101,7 +101,9 @@ _SIGS = {
                             vp], ctypes.c_int),
     "hcsp_spgemm_batched": ([ctypes.POINTER(c_batch_plan), vp, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
     "hcsp_batch_status": ([ctypes.POINTER(c_batch_plan), vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
+    "hcsp_features": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), vp], ctypes.c_int),
 }
+NFEATURES = 32
 
 _lib = None
 
@@ -119,6 +121,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libhcsp.so is not built (run __graft_entry__.build() or "
                                "python paper_2507_21253_amd/build.py); there is no fallback")
+        # torch first: its HIP runtime is then the one the library's HIP calls bind to, so torch's
+        # streams and device memory are valid in the library
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             f = getattr(L, name)
@@ -303,6 +308,16 @@ def plan_hierarchical(A_host, jacc_th=(3, 10), max_cluster: int = 8, sim=SIM_ROO
     _check(lib().hcsp_plan_hierarchical(ctypes.byref(m), _ratio(jacc_th), max_cluster, sim, nthreads, _np(pi),
                                         _np(perm), _np(crp), ctypes.byref(ncl)), "plan_hierarchical")
     return Plan(perm[:A_host.nrows], crp[:ncl.value + 1].copy())
+
+
+def features(A_host, B_host=None) -> np.ndarray:
+    """The library's structure-only features of the product A x B (B defaults to A), float32[32]."""
+    B_host = A_host if B_host is None else B_host
+    a = _host_csr(A_host)
+    b = _host_csr(B_host)
+    out = np.zeros(NFEATURES, np.float32)
+    _check(lib().hcsp_features(ctypes.byref(a), ctypes.byref(b), _np(out)), "features")
+    return out
 
 
 def cluster_workspace(nrows: int, ncl: int) -> int:
