@@ -245,6 +245,30 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                         double *C_val_d, int64_t capacity, void *ws_d, size_t ws_bytes,
                         void *stream);
 
+/* ---------------------------------------------------------------- orderings
+ * Row orderings applied before row-wise or cluster-wise SpGEMM (paper, Sec.
+ * "Matrix Reordering" and its table of reordering algorithms), on host
+ * copies of A (A_h: host arrays).  perm_out_h[n] receives the order:
+ * position p holds original row perm_out_h[p].  Host only; allocate host
+ * memory only.
+ *   hcsp_order_rcm     reverse Cuthill-McKee on the pattern of A + A^T
+ *                      (square A): per connected component a
+ *                      pseudo-peripheral start found from the least
+ *                      (degree, id) unvisited vertex by repeated
+ *                      breadth-first level structures; breadth-first visit
+ *                      of neighbours by ascending (degree, id); the whole
+ *                      sequence reversed.
+ *   hcsp_order_degree  rows by descending length, ties by ascending id.
+ * hcsp_permute_h: out = A with new row r = old row rperm_h[r] and new column
+ * c = old column cperm_h[c] (NULL = identity), rows re-sorted by column;
+ * out's arrays (host) are caller-allocated with A's sizes.  For a symmetric
+ * reordering pass the same order twice: the product of the reordered
+ * matrices is P C P^T.  nthreads host threads (<= 0: one). */
+int hcsp_order_rcm(const hcsp_csr *A_h, int32_t *perm_out_h);
+int hcsp_order_degree(const hcsp_csr *A_h, int32_t *perm_out_h);
+int hcsp_permute_h(const hcsp_csr *A_h, const int32_t *rperm_h, const int32_t *cperm_h, hcsp_csr *out_h,
+                   int32_t nthreads);
+
 /* ---------------------------------------------------------------- features
  * HCSP_NFEATURES structure-only features of the product A x B from host
  * copies of the patterns (A_h, B_h: host arrays; values are not read), for

@@ -83,6 +83,10 @@ def _load():
         lib.orc_cluster_fill.restype = ctypes.c_int
         lib.orc_cluster_spgemm.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64]
         lib.orc_cluster_spgemm.restype = i64
+        lib.orc_order_rcm.argtypes = [i64, vp, vp, vp]
+        lib.orc_order_rcm.restype = ctypes.c_int
+        lib.orc_order_degree.argtypes = [i64, vp, vp]
+        lib.orc_order_degree.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -323,3 +327,20 @@ def cluster_spgemm(Ac: HostCluster, B: HostCSR) -> HostCSR:
     if nnz2 != nnz:
         raise RuntimeError("cluster_spgemm fill failed")
     return HostCSR(rp, col, val, Ac.nrows, B.ncols)
+
+
+def order_rcm(A: HostCSR) -> np.ndarray:
+    """Reverse Cuthill-McKee order of the pattern of A + A^T (Sec. "Matrix Reordering"); perm[p] is the row
+    placed at position p."""
+    perm = np.empty(max(A.nrows, 1), np.int32)
+    if A.nrows and _load().orc_order_rcm(A.nrows, _p(A.rp), _p(A.col), _p(perm)):
+        raise RuntimeError("orc_order_rcm failed")
+    return perm[:A.nrows]
+
+
+def order_degree(A: HostCSR) -> np.ndarray:
+    """Rows by descending length, ties by ascending id (Sec. "Matrix Reordering", degree order)."""
+    perm = np.empty(max(A.nrows, 1), np.int32)
+    if A.nrows and _load().orc_order_degree(A.nrows, _p(A.rp), _p(perm)):
+        raise RuntimeError("orc_order_degree failed")
+    return perm[:A.nrows]

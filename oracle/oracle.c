@@ -16,6 +16,7 @@
  *   orc_plan_hierarchical hierarchical clusters                     [Alg. 3]
  *   orc_cluster_count / orc_cluster_fill   CSR_Cluster layout        [Access Pattern and Matrix Format, Fig. csr_cluster]
  *   orc_cluster_spgemm   cluster-wise product                       [Alg. 1]
+ *   orc_order_rcm / orc_order_degree   row orderings                 [Matrix Reordering, Table of reorderings]
  *
  * Numerical convention (the paper does not fix one): every output entry
  * c_ij starts at +0.0 and takes its contributions in ascending k, each by
@@ -853,4 +854,147 @@ int64_t orc_cluster_spgemm(int64_t nrows, int64_t p, int64_t ncl,
     }
     free(acc); free(mark); free(list);
     return pass_rc ? pass_rc : C_rp[nrows];
+}
+
+/* ------------------------------------------------------------- row orderings */
+/* Reverse Cuthill-McKee [Sec. "Matrix Reordering": bandwidth reduction by
+ * breadth-first search].  The paper takes RCM from a library and states no
+ * details; this follows the textbook procedure:
+ *   graph   = pattern of A + A^T, diagonal dropped
+ *   start   = per connected component, the unvisited vertex of least degree
+ *             (ties: least id), moved to a pseudo-peripheral vertex: from the
+ *             current start build the breadth-first level structure, take the
+ *             least-(degree, id) vertex x of its last level; if x's level
+ *             structure is deeper, x becomes the start and the step repeats
+ *   visit   = breadth-first; a dequeued vertex appends its unvisited
+ *             neighbours in ascending (degree, id)
+ *   result  = the concatenated visit order, reversed.
+ * perm[p] = the vertex placed at position p.  Returns 0, or -1 on
+ * allocation failure. */
+static const int64_t *g_deg;
+
+static int cmp_deg_id(const void *x, const void *y)
+{
+    int32_t a = *(const int32_t *)x, b = *(const int32_t *)y;
+    if (g_deg[a] != g_deg[b]) return g_deg[a] < g_deg[b] ? -1 : 1;
+    return (a > b) - (a < b);
+}
+
+/* breadth-first levels from s, over vertices whose stamp differs from mark;
+ * returns the depth and the least-(degree, id) vertex of the deepest level */
+static int64_t orc_levels(int64_t s, const int64_t *gp, const int32_t *ga, const int64_t *deg, int32_t *stamp,
+                          int32_t mark, int32_t *queue, int32_t *lastv)
+{
+    int64_t head = 0, tail = 0, depth = 0;
+    queue[tail++] = (int32_t)s;
+    stamp[s] = mark;
+    while (head < tail) {
+        int64_t end = tail;
+        int32_t best = queue[head];
+        depth++;
+        for (; head < end; ++head) {
+            int32_t u = queue[head];
+            if (deg[u] < deg[best] || (deg[u] == deg[best] && u < best)) best = u;
+            for (int64_t p = gp[u]; p < gp[u + 1]; ++p) {
+                int32_t w = ga[p];
+                if (stamp[w] != mark) { stamp[w] = mark; queue[tail++] = w; }
+            }
+        }
+        *lastv = best;
+    }
+    return depth;
+}
+
+int orc_order_rcm(int64_t n, const int64_t *rp, const int32_t *col, int32_t *perm)
+{
+    int64_t *cnt = calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *gp = calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *deg = calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *stamp = malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t *queue = malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t *order = malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t *byd = malloc(sizeof(int32_t) * (size_t)(n + 1));
+    char *done = calloc((size_t)n + 1, 1);
+    int32_t *raw = NULL, *ga = NULL;
+    int rc = -1;
+    if (!cnt || !gp || !deg || !stamp || !queue || !order || !byd || !done) goto out;
+    /* symmetric adjacency with duplicates, then sorted and deduplicated */
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (col[p] != i) { cnt[i]++; cnt[col[p]]++; }
+    int64_t tot = 0;
+    for (int64_t i = 0; i < n; ++i) { int64_t c = cnt[i]; cnt[i] = tot; tot += c; }
+    cnt[n] = tot;
+    raw = malloc(sizeof(int32_t) * (size_t)(tot + 1));
+    ga = malloc(sizeof(int32_t) * (size_t)(tot + 1));
+    if (!raw || !ga) goto out;
+    {
+        int64_t *fill = gp;  /* borrowed as a cursor, rebuilt below */
+        for (int64_t i = 0; i < n; ++i) fill[i] = cnt[i];
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+                if (col[p] != i) { raw[fill[i]++] = col[p]; raw[fill[col[p]]++] = (int32_t)i; }
+    }
+    gp[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t *a = raw + cnt[i];
+        int64_t m = cnt[i + 1] - cnt[i], k = 0;
+        sort_i32(a, m);
+        for (int64_t q = 0; q < m; ++q)
+            if (q == 0 || a[q] != a[q - 1]) a[k++] = a[q];
+        deg[i] = k;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        gp[i + 1] = gp[i] + deg[i];
+        memcpy(ga + gp[i], raw + cnt[i], sizeof(int32_t) * (size_t)deg[i]);
+    }
+    g_deg = deg;
+    for (int64_t i = 0; i < n; ++i) qsort(ga + gp[i], (size_t)deg[i], sizeof(int32_t), cmp_deg_id);
+    for (int64_t i = 0; i < n; ++i) { byd[i] = (int32_t)i; stamp[i] = -1; }
+    qsort(byd, (size_t)n, sizeof(int32_t), cmp_deg_id);
+    {
+        int64_t placed = 0, next = 0;
+        int32_t mark = 0;
+        while (placed < n) {
+            while (done[byd[next]]) next++;
+            int32_t start = byd[next], x;
+            int64_t depth = orc_levels(start, gp, ga, deg, stamp, ++mark, queue, &x);
+            for (;;) {
+                int32_t y;
+                int64_t d2 = orc_levels(x, gp, ga, deg, stamp, ++mark, queue, &y);
+                if (d2 <= depth) break;
+                start = x; depth = d2; x = y;
+            }
+            int64_t head = placed;
+            order[placed++] = start;
+            done[start] = 1;
+            while (head < placed) {
+                int32_t u = order[head++];
+                for (int64_t p = gp[u]; p < gp[u + 1]; ++p)
+                    if (!done[ga[p]]) { done[ga[p]] = 1; order[placed++] = ga[p]; }
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) perm[i] = order[n - 1 - i];
+    rc = 0;
+out:
+    free(cnt); free(gp); free(deg); free(stamp); free(queue); free(order); free(byd); free(done);
+    free(raw); free(ga);
+    return rc;
+}
+
+/* Degree order [Sec. "Matrix Reordering": rows in descending order of their
+ * degree]: descending row length, equal lengths in ascending row id. */
+int orc_order_degree(int64_t n, const int64_t *rp, int32_t *perm)
+{
+    /* counting sort by length, longest first, stable in row id */
+    int64_t maxl = 0;
+    for (int64_t i = 0; i < n; ++i) if (rp[i + 1] - rp[i] > maxl) maxl = rp[i + 1] - rp[i];
+    int64_t *start = calloc((size_t)maxl + 2, sizeof(int64_t));
+    if (!start) return -1;
+    for (int64_t i = 0; i < n; ++i) start[maxl - (rp[i + 1] - rp[i]) + 1]++;
+    for (int64_t l = 0; l <= maxl; ++l) start[l + 1] += start[l];
+    for (int64_t i = 0; i < n; ++i) perm[start[maxl - (rp[i + 1] - rp[i])]++] = (int32_t)i;
+    free(start);
+    return 0;
 }

@@ -102,6 +102,9 @@ _SIGS = {
     "hcsp_spgemm_batched": ([ctypes.POINTER(c_batch_plan), vp, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
     "hcsp_batch_status": ([ctypes.POINTER(c_batch_plan), vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
     "hcsp_features": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), vp], ctypes.c_int),
+    "hcsp_order_rcm": ([ctypes.POINTER(c_csr), vp], ctypes.c_int),
+    "hcsp_order_degree": ([ctypes.POINTER(c_csr), vp], ctypes.c_int),
+    "hcsp_permute_h": ([ctypes.POINTER(c_csr), vp, vp, ctypes.POINTER(c_csr), i32], ctypes.c_int),
 }
 NFEATURES = 32
 
@@ -308,6 +311,41 @@ def plan_hierarchical(A_host, jacc_th=(3, 10), max_cluster: int = 8, sim=SIM_ROO
     _check(lib().hcsp_plan_hierarchical(ctypes.byref(m), _ratio(jacc_th), max_cluster, sim, nthreads, _np(pi),
                                         _np(perm), _np(crp), ctypes.byref(ncl)), "plan_hierarchical")
     return Plan(perm[:A_host.nrows], crp[:ncl.value + 1].copy())
+
+
+def order_rcm(A_host) -> np.ndarray:
+    """Reverse Cuthill-McKee order (position -> original row) of the pattern of A + A^T."""
+    m = _host_csr(A_host)
+    perm = np.empty(max(A_host.nrows, 1), np.int32)
+    _check(lib().hcsp_order_rcm(ctypes.byref(m), _np(perm)), "order_rcm")
+    return perm[:A_host.nrows]
+
+
+def order_degree(A_host) -> np.ndarray:
+    """Rows by descending length, ties by ascending id (position -> original row)."""
+    m = _host_csr(A_host)
+    perm = np.empty(max(A_host.nrows, 1), np.int32)
+    _check(lib().hcsp_order_degree(ctypes.byref(m), _np(perm)), "order_degree")
+    return perm[:A_host.nrows]
+
+
+def permute_h(A_host, rperm=None, cperm=None, nthreads: int = 0):
+    """Host copy of A with rows and columns reordered (new row r = old row rperm[r], new column c = old
+    column cperm[c]); rows come out sorted.  Returns an object with rp, col, val, nrows, ncols."""
+    from types import SimpleNamespace
+    val = np.ascontiguousarray(A_host.val, np.float64)
+    a = _host_csr(A_host)
+    a.val = _np(val)
+    rp = np.empty(A_host.nrows + 1, np.int64)
+    col = np.empty(max(len(A_host.col), 1), np.int32)
+    v = np.empty(max(len(A_host.col), 1), np.float64)
+    o = c_csr(A_host.nrows, A_host.ncols, len(A_host.col), _np(rp), _np(col), _np(v))
+    rpn = None if rperm is None else np.ascontiguousarray(rperm, np.int32)
+    cpn = None if cperm is None else np.ascontiguousarray(cperm, np.int32)
+    _check(lib().hcsp_permute_h(ctypes.byref(a), _np(rpn), _np(cpn), ctypes.byref(o),
+                                nthreads or len(os.sched_getaffinity(0))), "permute_h")
+    n = len(A_host.col)
+    return SimpleNamespace(rp=rp, col=col[:n], val=v[:n], nrows=A_host.nrows, ncols=A_host.ncols, nnz=n)
 
 
 def features(A_host, B_host=None) -> np.ndarray:

@@ -24,7 +24,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     L = hc.lib()
     names = declared_symbols()
-    assert len(names) == 18
+    assert len(names) == 21
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(hc._SIGS), "binding and header disagree"
@@ -143,3 +143,23 @@ def test_batch_plan_init_errors():
     plan = hc.batch_plan_init((hc.c_batch_item * 1)(fake_item(0, 10, 5, 5)))
     rc = hc.lib().hcsp_spgemm_batched(ctypes.byref(plan), None, None, None, None, 0, None)
     assert rc == -1 and "prepared" in hc.last_error()
+
+
+def test_orderings_match_oracle():
+    for name, A in inputs():
+        if A.nrows == A.ncols:
+            np.testing.assert_array_equal(hc.order_rcm(A), oracle.order_rcm(A), err_msg=name)
+        np.testing.assert_array_equal(hc.order_degree(A), oracle.order_degree(A), err_msg=name)
+
+
+def test_permute_h_is_the_symmetric_permutation():
+    A = synth.uniform(60, 60, 7, 4)
+    p = synth.perm(60, 8)
+    B = hc.permute_h(A, p, p, nthreads=3)
+    D, P = synth.to_dense(A)
+    Db, Pb = synth.to_dense(B)
+    np.testing.assert_array_equal(Pb, P[np.ix_(p, p)])
+    np.testing.assert_array_equal(Db, D[np.ix_(p, p)])
+    assert all(np.all(np.diff(B.col[B.rp[i]:B.rp[i + 1]]) > 0) for i in range(60))
+    with pytest.raises(hc.HcspError):
+        hc.permute_h(A, np.zeros(60, np.int32), None)        # not a permutation

@@ -470,3 +470,75 @@ def test_clusterwise_uniform_random_bitwise():
     plan = oracle.plan_hierarchical(A, (1, 20), 16)
     Cc = oracle.cluster_spgemm(oracle.cluster_build(A, plan), B)
     assert_csr_equal(oracle.spgemm(A, B), Cc, bitwise=True)
+
+
+# ------------------------------------------------------------ row orderings
+
+def _graph(n, edges):
+    D = np.zeros((n, n))
+    P = np.zeros((n, n), bool)
+    for a, b in edges:
+        P[a, b] = P[b, a] = True
+        D[a, b] = D[b, a] = 1.0
+    return synth.from_dense(D, P)
+
+
+def _bandwidth(H, perm):
+    inv = np.empty(H.nrows, np.int64)
+    inv[perm] = np.arange(H.nrows)
+    r = np.repeat(np.arange(H.nrows), np.diff(H.rp))
+    return int(np.max(np.abs(inv[r] - inv[H.col]))) if len(H.col) else 0
+
+
+def test_rcm_hand_example():
+    g = json.load(open(os.path.join(GOLDEN, "rcm_hand_example.json")))
+    H = _graph(6, g["edges"])
+    assert oracle.order_rcm(H).tolist() == g["perm"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_rcm_recovers_a_shuffled_path(seed):
+    # a path 0-1-...-(n-1) under a random labelling: RCM lays it out again, bandwidth 1
+    n = 200
+    q = synth.perm(n, seed)
+    H = _graph(n, [(int(q[i]), int(q[i + 1])) for i in range(n - 1)])
+    p = oracle.order_rcm(H)
+    assert sorted(p.tolist()) == list(range(n))
+    assert _bandwidth(H, p) == 1
+
+
+@pytest.mark.parametrize("m", [5, 8, 13])
+def test_rcm_grid_bandwidth(m):
+    # 5-point grid: breadth-first levels from a corner are anti-diagonals, bandwidth m;
+    # relabelled, the bandwidth stays within 2m (the labels only break ties)
+    S = synth.stencil(5, m, 1)
+    assert _bandwidth(S, oracle.order_rcm(S)) == m
+    Q = synth.perm(m * m, 5)
+    R = synth.relabel(S, Q, Q)
+    assert _bandwidth(R, oracle.order_rcm(R)) <= 2 * m
+
+
+def test_rcm_components_are_contiguous_and_isolated_vertices_kept():
+    # two shuffled paths and isolated vertices: each component occupies one contiguous block
+    edges = [(0, 5), (5, 2), (2, 7), (1, 4), (4, 9)]
+    H = _graph(11, edges)
+    p = oracle.order_rcm(H).tolist()
+    assert sorted(p) == list(range(11))
+    pos = {v: i for i, v in enumerate(p)}
+    for comp in ([0, 5, 2, 7], [1, 4, 9]):
+        ix = sorted(pos[v] for v in comp)
+        assert ix == list(range(ix[0], ix[0] + len(comp)))
+    assert _bandwidth(H, p) == 1
+
+
+def test_degree_order():
+    A = synth.from_dense(np.array([[1, 0, 0, 0], [1, 1, 1, 0], [0, 1, 1, 0], [1, 1, 1, 1.0]]))
+    assert oracle.order_degree(A).tolist() == [3, 1, 2, 0]
+    R = synth.rmat(9, 8, 0.57, 0.19, 0.19, 2)
+    p = oracle.order_degree(R)
+    ln = np.diff(R.rp)[p]
+    assert np.all(ln[:-1] >= ln[1:]) and sorted(p.tolist()) == list(range(R.nrows))
+    # equal lengths keep ascending ids
+    for L in np.unique(ln):
+        ids = p[ln == L]
+        assert np.all(np.diff(ids) > 0)
