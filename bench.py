@@ -50,6 +50,10 @@ def parse():
     p.add_argument("--max-cluster", type=int, default=0,
                    help="rows per cluster at most (0: the autotuner's choice for the matrix class, else 2)")
     p.add_argument("--sim", choices=["root", "union"], default="root")
+    p.add_argument("--reorder", choices=["rcm", "degree", "none"], default="none",
+                   help="row order of A before clustering (A = M with rows permuted, B = M)")
+    p.add_argument("--symmetric", action="store_true",
+                   help="permute M symmetrically (rows and columns; B reordered too) instead of A's rows only")
     p.add_argument("--lanes", type=int, default=0)
     p.add_argument("--mode", choices=["bench", "copy", "batch"], default="bench",
                    help="bench: the stencil workload (the headline line); batch: 512 uneven products replayed "
@@ -245,36 +249,54 @@ def main():
         args.max_cluster = tuned["best_cluster_size"] if tuned["tuned"] else 2
     log("tuner: %s" % tuned)
 
-    # ---- preprocessing: hierarchical plan on the host, CSR_Cluster on the device
+    # ---- preprocessing: reordering (host), hierarchical plan (host), CSR_Cluster (device)
     ncpu = len(os.sched_getaffinity(0))
     t = time.perf_counter()
-    plan = hc.plan_hierarchical(M, (3, 10), args.max_cluster, hc.SIM_UNION if args.sim == "union" else hc.SIM_ROOT,
+    if args.reorder == "none":
+        R = M
+    else:
+        P = hc.order_rcm(M) if args.reorder == "rcm" else hc.order_degree(M)
+        R = hc.permute_h(M, P, P if args.symmetric else None, ncpu)
+    t_reorder = time.perf_counter() - t
+    t = time.perf_counter()
+    plan = hc.plan_hierarchical(R, (3, 10), args.max_cluster, hc.SIM_UNION if args.sim == "union" else hc.SIM_ROOT,
                                 nthreads=ncpu)
     t_plan = time.perf_counter() - t
-    log("plan: %d clusters (%.2fs, %d threads)" % (plan.nclusters, t_plan, ncpu))
+    log("reorder %s %.2fs; plan: %d clusters (%.2fs, %d threads)" % (args.reorder, t_reorder, plan.nclusters,
+                                                                     t_plan, ncpu))
     Md = hc.DeviceCSR.from_host(M)
+    Rd = Md if R is M else hc.DeviceCSR.from_host(R)
+    Bd = Rd if args.symmetric else Md          # right operand: M, or the reordered M
     torch.cuda.synchronize()
     for _ in range(2):
-        Dc = hc.cluster_build(Md, plan)
+        Dc = hc.cluster_build(Rd, plan)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    Dc = hc.cluster_build(Md, plan)
+    Dc = hc.cluster_build(Rd, plan)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t
     log("CSR_Cluster: ncc %d nslots %d max %d (%.3fs)" % (Dc.ncc, Dc.nslots, Dc.max_cluster, t_build))
 
     o = hc.opts(lanes=args.lanes, load_pct=args.load_pct or tuned["load_pct"],
                 sym_load_pct=args.sym_load_pct or tuned["sym_load_pct"])
-    P_cl = hc.Product(Dc, Md, o)
+    P_cl = hc.Product(Dc, Bd, o)
     P_pl = hc.Product(Md, Md, o)
     wall_cl, sym_cl, num_cl = time_product(P_cl, args.steps, args.warmup, torch)
     nnzC = P_cl.info.nnz
     wall_pl, sym_pl, num_pl = time_product(P_pl, args.steps, args.warmup, torch)
     assert P_pl.info.nnz == nnzC
+    wall_ro = None
+    if R is not M:
+        P_ro = hc.Product(Rd, Bd, o)
+        wall_ro, sym_ro, num_ro = time_product(P_ro, args.steps, args.warmup, torch)
+        assert P_ro.info.nnz == nnzC
+        del P_ro
     if m >= 3:
         assert nnzC == (5 * m - 6) ** 3, "nnz(C) differs from the closed form"
-    log("clustered: %.3f ms/step (sym %.3f, num %.3f); plain: %.3f ms/step (sym %.3f, num %.3f)"
-        % (wall_cl, sym_cl, num_cl, wall_pl, sym_pl, num_pl))
+    log("clustered: %.3f ms/step (sym %.3f, num %.3f); plain: %.3f ms/step (sym %.3f, num %.3f); "
+        "plain reordered: %s" % (wall_cl, sym_cl, num_cl, wall_pl, sym_pl, num_pl,
+                                 "-" if wall_ro is None else "%.3f ms/step (sym %.3f, num %.3f)" % (wall_ro, sym_ro,
+                                                                                                   num_ro)))
 
     bytes_A = csr_bytes(M.nrows, M.nnz)
     bytes_Acl = Dc.bytes()
@@ -285,8 +307,8 @@ def main():
     gflops_pl = flop / (wall_pl * 1e-3) / 1e9
     # dominant kernel family: the numeric launches; its algorithmic bytes are A (clustered), B and C
     ach = comp_cl / (num_cl * 1e-3) / 1e9
-    traffic = numeric_traffic("clustered", "m%d_mc%d_%s_s%d_n%d" % (m, args.max_cluster, args.sim, o.sym_load_pct,
-                                                                    o.load_pct))
+    traffic = numeric_traffic("clustered", "m%d_%s%s_mc%d_%s_s%d_n%d" % (
+        m, args.reorder, "sym" if args.symmetric else "", args.max_cluster, args.sim, o.sym_load_pct, o.load_pct))
 
     cpu = None
     if not args.no_cpu:
@@ -318,7 +340,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "stencil27_%d^3_relabelled_A2" % m, "nrows": M.nrows, "nnz_A": M.nnz,
-                   "nnz_C": nnzC, "products": products, "clustering": "hierarchical",
+                   "nnz_C": nnzC, "products": products, "reorder": args.reorder + (" symmetric" if args.symmetric
+                                                                                  else " rows of A"),
+                   "clustering": "hierarchical",
                    "jacc_th": "3/10", "max_cluster": args.max_cluster, "similarity": args.sim,
                    "sym_load_pct": o.sym_load_pct, "load_pct": o.load_pct, "autotuned": bool(tuned["tuned"])},
         "gbs_compulsory": round(comp_cl / (wall_cl * 1e-3) / 1e9, 2),
@@ -327,8 +351,12 @@ def main():
                       "gbs_compulsory": round(comp_pl / (wall_pl * 1e-3) / 1e9, 2),
                       "phases_ms": {"symbolic_incl_readback": round(sym_pl, 4), "numeric": round(num_pl, 4)}},
         "speedup_clustered_vs_plain": round(wall_pl / wall_cl, 3),
-        "preprocessing": {"plan_host_s": round(t_plan, 3), "plan_threads": ncpu, "cluster_build_s": round(t_build, 4),
-                          "in_spgemms": round((t_plan + t_build) / (wall_cl * 1e-3), 1),
+        "plain_csr_reordered": None if wall_ro is None else {
+            "gflops": round(flop / (wall_ro * 1e-3) / 1e9, 3), "ms_per_step": round(wall_ro, 4),
+            "phases_ms": {"symbolic_incl_readback": round(sym_ro, 4), "numeric": round(num_ro, 4)}},
+        "preprocessing": {"reorder_host_s": round(t_reorder, 3), "plan_host_s": round(t_plan, 3), "plan_threads": ncpu,
+                          "cluster_build_s": round(t_build, 4),
+                          "in_spgemms": round((t_reorder + t_plan + t_build) / (wall_cl * 1e-3), 1),
                           "nclusters": plan.nclusters, "ncc": Dc.ncc, "nslots": Dc.nslots,
                           "csr_cluster_over_csr_bytes": round(bytes_Acl / bytes_A, 3)},
         "roofline": {"bound": "hbm", "kernel": "k_num (numeric phase launches)", "achieved": round(ach, 1),
