@@ -68,7 +68,7 @@ def parse():
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_num_stencil27_100_relabelled.md")
-KERNEL_SOURCES = ["paper_2507_21253_amd/csrc/hash.hip", "paper_2507_21253_amd/csrc/dense.hip"]
+KERNEL_SOURCES = ["paper_2507_21253_amd/csrc/hash.hip"]
 
 
 def numeric_traffic(key: str, config: str):

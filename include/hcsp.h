@@ -129,7 +129,8 @@ typedef struct hcsp_opts {
     int64_t unit_lo;        /* numeric: first unit (row of a CSR A, cluster of a CSR_Cluster A) */
     int64_t unit_hi;        /* numeric: one past the last unit; <= 0 means all units */
     int64_t out_base;       /* numeric: C_col_d/C_val_d point at global entry out_base of C */
-    int32_t dense_slots;    /* concurrent dense accumulators for very long rows: 0 = default (32) */
+    int32_t dense_slots;    /* concurrent dense accumulators for very long rows: 0 = as many as fit in
+                               4 GiB (32..1024) */
     int32_t load_pct;       /* numeric hash-table fill target in percent: 0 = default (60) */
     int32_t sym_tmax_log2;  /* largest shared-memory symbolic table, log2 slots: 0 = default */
     int32_t num_tmax;       /* largest shared-memory numeric table, slots: 0 = default */
@@ -295,6 +296,44 @@ int hcsp_permute_h(const hcsp_csr *A_h, const int32_t *rperm_h, const int32_t *c
  * out[HCSP_NFEATURES] receives float32 values.  Host only. */
 #define HCSP_NFEATURES 32
 int hcsp_features(const hcsp_csr *A_h, const hcsp_csr *B_h, float *out);
+
+/* ---------------------------------------------------------------- learned selector
+ * A 32-64-64-5 multilayer perceptron in float32 that, from the structure
+ * features above, scores the product paths (logits z[0..3]) and predicts the
+ * log compression ratio log(nnz(C) / products) (z[4]); it is trained on the
+ * GPU with these kernels.  The paper proposes learning the reordering and
+ * clustering choice as future work (Sec. "Conclusion and Future Work"); the
+ * model is this library's.
+ *   x_n = (x - mu) / sd;  h1 = relu(W1 x_n + b1);  h2 = relu(W2 h1 + b2);
+ *   z = W3 h2 + b3;
+ *   loss = mean_b(-log softmax(z_b[0..3])[y_b]) + lam * mean_b((z_b[4] - t_b)^2)
+ * Device arrays (float32 unless noted):
+ *   params_d[HCSP_MLP_NPARAMS]  W1 (64x32 row-major), b1 (64), W2 (64x64),
+ *                               b2 (64), W3 (5x64), b3 (5)
+ *   norm_d[2*32]                mu then sd of the features
+ *   X_d[B*32], Z_d[B*5]
+ *   act_d[B*HCSP_MLP_NACT]      per sample: x_n (32), W1 x_n + b1 (64),
+ *                               W2 h1 + b2 (64); written by forward when not
+ *                               NULL, read by backward
+ *   y_d[B] (int32 class), t_d[B] (target log ratio), loss_d[B] (per-sample
+ *   loss), delta_d[B*HCSP_MLP_NDELTA] (scratch), grad_d[HCSP_MLP_NPARAMS]
+ * hcsp_mlp_adam applies one Adam step (step >= 1, bias-corrected) to params
+ * with moment arrays m_d, v_d[HCSP_MLP_NPARAMS] (zero before step 1).  All
+ * three run on the stream and never synchronize. */
+#define HCSP_MLP_NIN 32
+#define HCSP_MLP_NH 64
+#define HCSP_MLP_NOUT 5
+#define HCSP_MLP_NCLS 4
+#define HCSP_MLP_NPARAMS 6597
+#define HCSP_MLP_NACT 160
+#define HCSP_MLP_NDELTA 133
+int hcsp_mlp_forward(const float *params_d, const float *norm_d, const float *X_d, int32_t B, float *Z_d,
+                     float *act_d, void *stream);
+int hcsp_mlp_backward(const float *params_d, const float *act_d, const float *Z_d, const int32_t *y_d,
+                      const float *t_d, int32_t B, float lam, float *delta_d, float *loss_d, float *grad_d,
+                      void *stream);
+int hcsp_mlp_adam(float *params_d, const float *grad_d, float *m_d, float *v_d, int32_t step, float lr, float beta1,
+                  float beta2, float eps, void *stream);
 
 /* ---------------------------------------------------------------- batches
  * Many independent products C_p = A_p x B_p of uneven sizes in one fixed

@@ -105,7 +105,12 @@ _SIGS = {
     "hcsp_order_rcm": ([ctypes.POINTER(c_csr), vp], ctypes.c_int),
     "hcsp_order_degree": ([ctypes.POINTER(c_csr), vp], ctypes.c_int),
     "hcsp_permute_h": ([ctypes.POINTER(c_csr), vp, vp, ctypes.POINTER(c_csr), i32], ctypes.c_int),
+    "hcsp_mlp_forward": ([vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+    "hcsp_mlp_backward": ([vp, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, vp], ctypes.c_int),
+    "hcsp_mlp_adam": ([vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp],
+                      ctypes.c_int),
 }
+MLP_NPARAMS, MLP_NACT, MLP_NDELTA = 6597, 160, 133
 NFEATURES = 32
 
 _lib = None
@@ -536,3 +541,20 @@ class Batch:
             nnz = int(rp[-1].item())
         o0 = int(self.out_off[p])
         return DeviceCSR(rp, self.C_col[o0:o0 + nnz], self.C_val[o0:o0 + nnz], A.nrows, B.ncols)
+
+
+# ------------------------------------------------------------------ learned selector (device arrays)
+
+def mlp_forward(params, norm, X, Z, act=None, stream=None):
+    _check(lib().hcsp_mlp_forward(_tp(params), _tp(norm), _tp(X), X.shape[0], _tp(Z), _tp(act), _stream(stream)),
+           "mlp_forward")
+
+
+def mlp_backward(params, act, Z, y, t, lam, delta, loss, grad, stream=None):
+    _check(lib().hcsp_mlp_backward(_tp(params), _tp(act), _tp(Z), _tp(y), _tp(t), Z.shape[0], float(lam),
+                                   _tp(delta), _tp(loss), _tp(grad), _stream(stream)), "mlp_backward")
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().hcsp_mlp_adam(_tp(params), _tp(grad), _tp(m), _tp(v), int(step), float(lr), float(beta1),
+                               float(beta2), float(eps), _stream(stream)), "mlp_adam")

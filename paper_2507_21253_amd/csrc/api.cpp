@@ -103,11 +103,13 @@ static int make_tune(const hcsp_opts *o, const hcsp_csr *B, bool need_device, Tu
     if (o->sym_tmax_log2) sym = std::max(kSymLog2Min + 1, std::min(sym, (int)o->sym_tmax_log2));
     t->sym_tmax_log2 = sym;
     t->num_tmax = o->num_tmax ? o->num_tmax : (1 << 30);
-    t->dense_slots = o->dense_slots ? o->dense_slots : 32;
+    // dense accumulators: by default as many as fit in 4 GiB, between 32 and 1024
+    const int64_t per_slot = 8 * std::max<int64_t>(B->ncols, 1) + 4 * ((B->ncols + 31) / 32);
+    t->dense_slots = o->dense_slots ? o->dense_slots
+                                    : (int)std::max<int64_t>(32, std::min<int64_t>(1024, (4ll << 30) / per_slot));
     if (t->dense_slots < 4) t->dense_slots = 4;
     t->dense_slots &= ~3;
-    // keep the dense accumulators within 16 GiB
-    const int64_t per_slot = 8 * std::max<int64_t>(B->ncols, 1) + 4 * ((B->ncols + 31) / 32);
+    // and never more than 16 GiB
     while (t->dense_slots > 4 && (int64_t)t->dense_slots * per_slot > (16ll << 30)) t->dense_slots -= 4;
     return HCSP_OK;
 }

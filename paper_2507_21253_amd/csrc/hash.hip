@@ -559,6 +559,194 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     }
 }
 
+// ================================================================ global-memory path
+// Units whose tables do not fit in shared memory.  Each wavefront owns a
+// bitmap over all columns of B (and, numeric, a value array of the same
+// width) in the workspace and takes units one after another; the products
+// are walked in the same 64-wide passes as above.  Cluster members are done
+// one after another (a product counts for member l when bit l of its
+// column's mask is set).
+constexpr int kGmSym = 16 * 64 + 8 * kRoundPasses;     // items + start bits
+constexpr int kGmNumCl = kGmSym + 8 * 16 * 64;         // + staged cluster values
+
+int64_t gm_wave_bytes(bool cl, bool num) { return num && cl ? kGmNumCl : kGmSym; }
+
+template <bool BATCH>
+__device__ __forceinline__ int gm_unit(SpArgs &a, const SpArgs &a0, int64_t i)
+{
+    a = a0;
+    return BATCH ? batch_resolve(a, a0.order[i]) : a0.order[i];
+}
+
+// Symbolic: bits are set with atomic ORs that return nothing (no wait per
+// product); the row's count is the popcount of its bitmap, which the same
+// sweep clears for the next row.
+template <bool CL, bool BATCH>
+__global__ void __launch_bounds__(256) k_sym_gm(SpArgs a0)
+{
+    constexpr int S = CL ? 16 : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = (int)__lane_id();
+    const int wib = uniform((int)(threadIdx.x >> 6));
+    const int64_t wv = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned char *base = smem + (size_t)wib * kGmSym;
+    ItemRec *items = (ItemRec *)base;
+    uint64_t *sbits = (uint64_t *)(base + 16 * 64);
+    uint32_t *bm = a0.dense_bits + wv * a0.dense_words;
+    const int64_t count = BATCH ? a0.dcount[a0.bin] : a0.count;
+    const int64_t begin = BATCH ? a0.dbegin[a0.bin] : a0.bin_begin;
+    const uint64_t le = lanemask_le(lane);
+    for (int64_t ti = wv; ti < count; ti += nw) {
+        SpArgs a;
+        const int u = gm_unit<BATCH>(a, a0, begin + ti);
+        const UnitView v = unit_view<CL>(a, u);
+        for (int l = 0; l < v.s; ++l) {
+            int64_t q0 = v.it0;
+            int off0 = 0;
+            while (q0 < v.it1) {
+                const int E = load_round<CL, S, false>(a, v, q0, off0, items, sbits, nullptr, nullptr);
+                const int npass = (E + 63) >> 6;
+                int cum = 0;
+                for (int p = 0; p < npass; ++p) {
+                    const uint64_t w = uniform64(sbits[p]);
+                    const Pass<CL, false> d = fetch_pass<CL, false>(a, items, w, cum, (p << 6) + lane, E, le);
+                    cum += __popcll(w);
+                    if (d.j != kDummyKey && (!CL || ((d.m >> l) & 1u))) atomicOr(&bm[d.j >> 5], 1u << (d.j & 31));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            int64_t cnt = 0;
+            for (int64_t x = lane; x < a.dense_words; x += 64) {
+                const uint32_t word = __hip_atomic_load(&bm[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (word) {
+                    cnt += __popc(word);
+                    bm[x] = 0u;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+            if (lane == 0) a.c_rp[member_row<CL>(a, v, l)] = cnt;
+        }
+        if (lane == 0) a.ucount[u] = INT32_MAX;
+    }
+}
+
+// Numeric: within a pass the products are applied item by item (ascending
+// k), and every item waits for its stores before the next item may read the
+// same accumulator entries.  The first touch of a column (its bitmap bit)
+// starts the entry from +0.0.  Output: the bitmap in column order.
+template <bool CL, bool BATCH>
+__global__ void __launch_bounds__(256) k_num_gm(SpArgs a0)
+{
+    constexpr int S = CL ? 16 : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = (int)__lane_id();
+    const int wib = uniform((int)(threadIdx.x >> 6));
+    const int64_t wv = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned char *base = smem + (size_t)wib * (CL ? kGmNumCl : kGmSym);
+    ItemRec *items = (ItemRec *)base;
+    uint64_t *sbits = (uint64_t *)(base + 16 * 64);
+    double *aval = (double *)(base + kGmSym);
+    uint32_t *bm = a0.dense_bits + wv * a0.dense_words;
+    double *acc = a0.dense_vals + wv * a0.ncols;  // stride: the widest B of the launch
+    const int64_t count = BATCH ? a0.dcount[a0.bin] : a0.count;
+    const int64_t begin = BATCH ? a0.dbegin[a0.bin] : a0.bin_begin;
+    const uint64_t le = lanemask_le(lane);
+    for (int64_t ti = wv; ti < count; ti += nw) {
+        SpArgs a;
+        const int u = gm_unit<BATCH>(a, a0, begin + ti);
+        if (u < a.unit_lo || u >= a.unit_hi) continue;
+        const UnitView v = unit_view<CL>(a, u);
+        for (int l = 0; l < v.s; ++l) {
+            int64_t q0 = v.it0;
+            int off0 = 0;
+            while (q0 < v.it1) {
+                const int E = load_round<CL, S, true>(a, v, q0, off0, items, sbits, aval, nullptr);
+                const int npass = (E + 63) >> 6;
+                int cum = 0;
+                for (int p = 0; p < npass; ++p) {
+                    const uint64_t w = uniform64(sbits[p]);
+                    const int last = min(63, E - 1 - (p << 6));
+                    const int tf = cum + (int)(w & 1ull) - 1;
+                    const int tl = cum + __popcll(w & lanemask_le(last)) - 1;
+                    const Pass<CL, true> d = fetch_pass<CL, true>(a, items, w, cum, (p << 6) + lane, E, le);
+                    cum += __popcll(w);
+                    for (int tt = tf; tt <= tl; ++tt) {
+                        double av = d.a;
+                        if (CL) {
+                            if (!((uniform((int)items[tt].x) >> l) & 1)) continue;
+                            av = aval[uniform((int)items[tt].y) * S + l];
+                        }
+                        if (d.t == tt && d.j != kDummyKey) {
+                            const uint32_t bit = 1u << (d.j & 31);
+                            const uint32_t old = atomicOr(&bm[d.j >> 5], bit);
+                            const double prev = (old & bit) ? __hip_atomic_load(&acc[d.j], __ATOMIC_RELAXED,
+                                                                                 __HIP_MEMORY_SCOPE_WORKGROUP)
+                                                            : 0.0;
+                            __hip_atomic_store(&acc[d.j], __fma_rn(av, d.b, prev), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            const int64_t row = member_row<CL>(a, v, l);
+            const int64_t o0 = a.c_rp[row] - a.out_base;
+            const int64_t want = a.c_rp[row + 1] - a.c_rp[row];
+            int64_t wsum = 0;
+            for (int64_t w0 = 0; w0 < a.dense_words; w0 += 64) {
+                const int64_t wi = w0 + lane;
+                uint32_t word = wi < a.dense_words
+                                    ? __hip_atomic_load(&bm[wi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : 0u;
+                const int c = __popc(word);
+                const int pre = wave_incl_scan(c);
+                const int tot = __shfl(pre, 63);
+                int64_t dst = o0 + wsum + pre - c;
+                if (word) bm[wi] = 0u;
+                while (word) {
+                    const int b = __ffs(word) - 1;
+                    word &= word - 1u;
+                    const int j = (int)(wi * 32 + b);
+                    if (dst >= 0 && dst < a.cap && dst - o0 < want) {
+                        a.c_col[dst] = j;
+                        a.c_val[dst] = __hip_atomic_load(&acc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        atomicOr(a.err, kErrCapacity);
+                    }
+                    ++dst;
+                }
+                wsum += tot;
+            }
+            if (lane == 0 && wsum != want) atomicOr(a.err, kErrCount);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        }
+    }
+}
+
+hipError_t launch_sym_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s)
+{
+    const size_t lds = 4 * (size_t)kGmSym;
+    if (cluster && batch) hipLaunchKernelGGL((k_sym_gm<true, true>), dim3(blocks), dim3(256), lds, s, a);
+    else if (cluster) hipLaunchKernelGGL((k_sym_gm<true, false>), dim3(blocks), dim3(256), lds, s, a);
+    else if (batch) hipLaunchKernelGGL((k_sym_gm<false, true>), dim3(blocks), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_sym_gm<false, false>), dim3(blocks), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s)
+{
+    const size_t lds = 4 * (size_t)(cluster ? kGmNumCl : kGmSym);
+    if (cluster && batch) hipLaunchKernelGGL((k_num_gm<true, true>), dim3(blocks), dim3(256), lds, s, a);
+    else if (cluster) hipLaunchKernelGGL((k_num_gm<true, false>), dim3(blocks), dim3(256), lds, s, a);
+    else if (batch) hipLaunchKernelGGL((k_num_gm<false, true>), dim3(blocks), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_num_gm<false, false>), dim3(blocks), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
 // ================================================================ kernels
 // A bin's units: one per wavefront with the grid sized to the bin, or, for a
 // batch (BATCH), a persistent grid whose wavefronts each take one contiguous
