@@ -62,6 +62,7 @@ def parse():
     p.add_argument("--load-pct", type=int, default=0, help="numeric table fill target (0: autotuned)")
     p.add_argument("--sym-load-pct", type=int, default=0, help="symbolic table fill bound (0: autotuned)")
     p.add_argument("--untuned", action="store_true", help="ignore the autotuner's table")
+    p.add_argument("--margin", type=float, default=0.1, help="margin on the predicted compression ratio")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-threads", type=int, default=0)
     return p.parse_args()
@@ -293,6 +294,33 @@ def main():
         del P_ro
     if m >= 3:
         assert nnzC == (5 * m - 6) ** 3, "nnz(C) differs from the closed form"
+    # ---- the learned selector and nnz predictor, when a trained model is in the tree
+    learned_out = None
+    from paper_2507_21253_amd import learned
+    if os.path.exists(learned.MODEL):
+        sel = learned.Selector.load()
+        f = hc.features(M)[None, :]
+        z = sel.logits(f)[0]
+        ratio_pred = float(np.exp(z[len(learned.PATHS)]))
+        ratio = min(1.0, ratio_pred * (1 + args.margin))
+        PP = hc.PredictedProduct(Md, Md, ratio, o)
+        for _ in range(args.warmup):
+            PP.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            PP.run()
+        torch.cuda.synchronize()
+        wall_pp = (time.perf_counter() - t) * 1e3 / args.steps
+        assert PP.nnz == nnzC
+        learned_out = {"selector_choice": learned.PATHS[int(np.argmax(z[:len(learned.PATHS)]))],
+                       "ratio_predicted": round(ratio_pred, 4), "ratio_true": round(nnzC / products, 4),
+                       "margin": args.margin, "predicted_size_product": {
+                           "ms_per_step": round(wall_pp, 4), "gflops": round(flop / (wall_pp * 1e-3) / 1e9, 3),
+                           "rows_recomputed_exactly": int(PP.n_overflow)}}
+        log("learned: %s" % learned_out)
+        del PP
+
     log("clustered: %.3f ms/step (sym %.3f, num %.3f); plain: %.3f ms/step (sym %.3f, num %.3f); "
         "plain reordered: %s" % (wall_cl, sym_cl, num_cl, wall_pl, sym_pl, num_pl,
                                  "-" if wall_ro is None else "%.3f ms/step (sym %.3f, num %.3f)" % (wall_ro, sym_ro,
@@ -363,6 +391,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": comp_cl},
         "cpu_baseline": cpu,
+        "learned": learned_out,
     }
     print(json.dumps(out), flush=True)
 

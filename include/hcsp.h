@@ -246,6 +246,35 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                         double *C_val_d, int64_t capacity, void *ws_d, size_t ws_bytes,
                         void *stream);
 
+/* ---------------------------------------------------------------- predicted sizes
+ * A product without a symbolic phase in front: every row's output count is
+ * predicted as capacity_i = min(p_i, ceil(p_i * ratio)), p_i the row's
+ * product count (an upper bound on its count) and ratio a predicted
+ * compression nnz(C)/products with margin (e.g. from the learned predictor);
+ * the numeric phase runs with hash tables sized for capacity_i and writes
+ * into a padded scratch.  Rows whose keys do not fit are recomputed exactly:
+ * the symbolic phase runs for those rows only (the exact fallback), then the
+ * numeric phase.  Finally the predicted rows move to their exact places.  The
+ * result is the same C as hcsp_spgemm_symbolic + hcsp_spgemm_numeric, bit
+ * for bit.  CSR A only.
+ *   hcsp_spgemm_products      products = sum over A's entries (i, k) of |B_k|
+ *                             (device computation; ws_d >= 8 bytes;
+ *                             synchronizes)
+ *   hcsp_predicted_workspace  workspace bytes for (ratio, products); host only
+ *   hcsp_spgemm_predicted     C_row_ptr_d[n+1] exact offsets, C_col_d/C_val_d
+ *                             with capacity >= nnz(C) (else HCSP_E_CAPACITY
+ *                             after nnz_h is set), nnz_h and n_overflow_h
+ *                             (rows recomputed exactly; both nullable).
+ *                             ratio in (0, 1].  Synchronizes. */
+int hcsp_spgemm_products(const hcsp_csr *A, const hcsp_csr *B, int64_t *products_h, void *ws_d, size_t ws_bytes,
+                         void *stream);
+int hcsp_predicted_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
+                             int64_t products, size_t *bytes);
+int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
+                          int64_t products, int64_t *C_row_ptr_d, int32_t *C_col_d, double *C_val_d,
+                          int64_t capacity, int64_t *nnz_h, int64_t *n_overflow_h, void *ws_d, size_t ws_bytes,
+                          void *stream);
+
 /* ---------------------------------------------------------------- orderings
  * Row orderings applied before row-wise or cluster-wise SpGEMM (paper, Sec.
  * "Matrix Reordering" and its table of reordering algorithms), on host

@@ -105,6 +105,13 @@ _SIGS = {
     "hcsp_order_rcm": ([ctypes.POINTER(c_csr), vp], ctypes.c_int),
     "hcsp_order_degree": ([ctypes.POINTER(c_csr), vp], ctypes.c_int),
     "hcsp_permute_h": ([ctypes.POINTER(c_csr), vp, vp, ctypes.POINTER(c_csr), i32], ctypes.c_int),
+    "hcsp_spgemm_products": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), ctypes.POINTER(i64), vp, ctypes.c_size_t,
+                              vp], ctypes.c_int),
+    "hcsp_predicted_workspace": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
+                                  ctypes.c_float, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hcsp_spgemm_predicted": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts), ctypes.c_float,
+                               i64, vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, ctypes.c_size_t,
+                               vp], ctypes.c_int),
     "hcsp_mlp_forward": ([vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
     "hcsp_mlp_backward": ([vp, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, vp], ctypes.c_int),
     "hcsp_mlp_adam": ([vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp],
@@ -558,3 +565,48 @@ def mlp_backward(params, act, Z, y, t, lam, delta, loss, grad, stream=None):
 def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(lib().hcsp_mlp_adam(_tp(params), _tp(grad), _tp(m), _tp(v), int(step), float(lr), float(beta1),
                                float(beta2), float(eps), _stream(stream)), "mlp_adam")
+
+
+# ------------------------------------------------------------------ predicted sizes
+
+def spgemm_products(A: DeviceCSR, B: DeviceCSR, stream=None) -> int:
+    import torch
+    ws = torch.empty(8, dtype=torch.uint8, device=B.row_ptr.device)
+    a, b = A.c(), B.c()
+    out = i64()
+    _check(lib().hcsp_spgemm_products(ctypes.byref(a), ctypes.byref(b), ctypes.byref(out), _tp(ws), 8,
+                                      _stream(stream)), "spgemm_products")
+    return out.value
+
+
+class PredictedProduct:
+    """C = A x B with row sizes predicted from a compression ratio (nnz(C)/products, margin included); rows
+    the prediction does not hold are recomputed through the exact symbolic phase.  ``run()`` returns C;
+    ``n_overflow`` is the number of rows recomputed."""
+
+    def __init__(self, A: DeviceCSR, B: DeviceCSR, ratio: float, o: c_opts | None = None, capacity=None):
+        import torch
+        self.A, self.B, self.o = A, B, o or c_opts()
+        self.ratio = float(min(1.0, max(ratio, 1e-6)))
+        self.products = spgemm_products(A, B)
+        a, b = A.c(), B.c()
+        n = ctypes.c_size_t()
+        _check(lib().hcsp_predicted_workspace(ctypes.byref(a), ctypes.byref(b), ctypes.byref(self.o), self.ratio,
+                                              self.products, ctypes.byref(n)), "predicted_workspace")
+        dev = B.row_ptr.device
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        self.C_row_ptr = torch.empty(A.nrows + 1, dtype=torch.int64, device=dev)
+        cap = self.products if capacity is None else capacity
+        self.C_col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        self.C_val = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        self.nnz = self.n_overflow = None
+
+    def run(self, stream=None) -> DeviceCSR:
+        a, b = self.A.c(), self.B.c()
+        nnz, novf = i64(), i64()
+        _check(lib().hcsp_spgemm_predicted(ctypes.byref(a), ctypes.byref(b), ctypes.byref(self.o), self.ratio,
+                                           self.products, _tp(self.C_row_ptr), _tp(self.C_col), _tp(self.C_val),
+                                           self.C_col.numel(), ctypes.byref(nnz), ctypes.byref(novf), _tp(self.ws),
+                                           self.ws.numel(), _stream(stream)), "spgemm_predicted")
+        self.nnz, self.n_overflow = nnz.value, novf.value
+        return DeviceCSR(self.C_row_ptr, self.C_col[:self.nnz], self.C_val[:self.nnz], self.A.nrows, self.B.ncols)

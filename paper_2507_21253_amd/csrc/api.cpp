@@ -1,6 +1,7 @@
 // C ABI of libhcsp: argument checks, workspace layout, bin dispatch and the
 // two-phase SpGEMM orchestration (symbolic, then numeric) on one HIP stream.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -432,10 +433,14 @@ int hcsp_spgemm_workspace(const hcsp_operand *A, const hcsp_csr *B, const hcsp_o
     return HCSP_OK;
 }
 
-int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, int64_t *C_row_ptr_d,
-                         hcsp_sym_info *info, void *ws_d, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+// Symbolic phase over the units with active[u] != 0 (all when null); the
+// counts of the other rows must already be in C_row_ptr_d, since the final
+// scan covers every row.
+static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, int64_t *C_row_ptr_d,
+                         hcsp_sym_info *info, void *ws_d, size_t ws_bytes, void *stream, const uint8_t *active)
 {
-    clear_error();
     OpView v;
     int rc = check_operands(A, B, &v);
     if (rc) return rc;
@@ -455,6 +460,7 @@ int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     HCSP_HIP(launch_fill_i64(C_row_ptr_d + v.nrows, 1, 0, s));
 
     BinArgs ba = bin_args(A, B, ws, tu, v.nunits, C_row_ptr_d);
+    ba.active = active;
     HCSP_HIP(launch_work(v.cluster, ba, s));
     HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.bin_hist, kSymBins, ws.sym_count, ws.order_sym, s));
     int64_t cnt[HCSP_MAX_BINS];
@@ -506,6 +512,15 @@ int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     info->lanes = tu.G;
     info->valid = 1;
     return HCSP_OK;
+}
+
+extern "C" {
+
+int hcsp_spgemm_symbolic(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, int64_t *C_row_ptr_d,
+                         hcsp_sym_info *info, void *ws_d, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    return symbolic_impl(A, B, opts, C_row_ptr_d, info, ws_d, ws_bytes, stream, nullptr);
 }
 
 int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, const hcsp_sym_info *info,
@@ -574,6 +589,193 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
         if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "output capacity too small for the requested units");
         if (e & kErrCount) return fail(HCSP_E_INVALID, "row counts differ from the symbolic phase (inputs changed?)");
     }
+    return HCSP_OK;
+}
+
+// ================================================================ predicted sizes
+
+int hcsp_spgemm_products(const hcsp_csr *A, const hcsp_csr *B, int64_t *products_h, void *ws_d, size_t ws_bytes,
+                         void *stream)
+{
+    clear_error();
+    hcsp_operand op;
+    std::memset(&op, 0, sizeof op);
+    if (A) op.csr = *A;
+    OpView v;
+    int rc = check_operands(A ? &op : nullptr, B, &v);
+    if (rc) return rc;
+    if (!products_h || !ws_d || ws_bytes < 8) return fail(HCSP_E_INVALID, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t *acc = (int64_t *)ws_d;
+    HCSP_HIP(launch_fill_i64(acc, 1, 0, s));
+    HCSP_HIP(launch_products(*A, *B, acc, s));
+    HCSP_HIP(hipMemcpyAsync(products_h, acc, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    return HCSP_OK;
+}
+
+// padded scratch entries for a predicted product
+static int64_t pred_entries(float ratio, int64_t products, int64_t nrows)
+{
+    const double e = std::ceil((double)ratio * (double)products) + (double)nrows;
+    return std::max<int64_t>(1, std::min<int64_t>(products, (int64_t)e));
+}
+
+struct PredWs {
+    int64_t *pad_off, *novf;
+    uint8_t *active;
+    int32_t *scol;
+    double *sval;
+    int64_t entries;
+};
+
+static size_t layout_pred(size_t base_bytes, int64_t nrows, int64_t entries, char *base, PredWs *p)
+{
+    size_t off = base_bytes;
+    auto take = [&](size_t bytes) -> void * {
+        off = align_up(off, 256);
+        void *q = base ? (void *)(base + off) : nullptr;
+        off += bytes;
+        return q;
+    };
+    p->pad_off = (int64_t *)take(8 * ((size_t)nrows + 1));
+    p->novf = (int64_t *)take(8);
+    p->active = (uint8_t *)take((size_t)std::max<int64_t>(nrows, 1));
+    p->scol = (int32_t *)take(4 * (size_t)entries);
+    p->sval = (double *)take(8 * (size_t)entries);
+    p->entries = entries;
+    return align_up(off, 256);
+}
+
+int hcsp_predicted_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
+                             int64_t products, size_t *bytes)
+{
+    clear_error();
+    hcsp_operand op;
+    std::memset(&op, 0, sizeof op);
+    if (A) op.csr = *A;
+    OpView v;
+    int rc = check_operands(A ? &op : nullptr, B, &v);
+    if (rc) return rc;
+    if (!bytes || !(ratio > 0.0f && ratio <= 1.0f) || products < 0)
+        return fail(HCSP_E_INVALID, "bad arguments (ratio must be in (0, 1])");
+    Tune tu;
+    rc = make_tune(opts, B, false, &tu);
+    if (rc) return rc;
+    Workspace ws;
+    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, nullptr, &ws);
+    PredWs p;
+    *bytes = layout_pred(base, v.nrows, pred_entries(ratio, products, v.nrows), nullptr, &p);
+    return HCSP_OK;
+}
+
+int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
+                          int64_t products, int64_t *C_row_ptr_d, int32_t *C_col_d, double *C_val_d,
+                          int64_t capacity, int64_t *nnz_h, int64_t *n_overflow_h, void *ws_d, size_t ws_bytes,
+                          void *stream)
+{
+    clear_error();
+    hcsp_operand op;
+    std::memset(&op, 0, sizeof op);
+    if (A) op.csr = *A;
+    OpView v;
+    int rc = check_operands(A ? &op : nullptr, B, &v);
+    if (rc) return rc;
+    if (!(ratio > 0.0f && ratio <= 1.0f) || products < 0 || !C_row_ptr_d || capacity < 0 ||
+        (capacity > 0 && (!C_col_d || !C_val_d)))
+        return fail(HCSP_E_INVALID, "bad arguments (ratio must be in (0, 1])");
+    Tune tu;
+    rc = make_tune(opts, B, true, &tu);
+    if (rc) return rc;
+    Workspace ws;
+    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, (char *)ws_d, &ws);
+    PredWs pw;
+    const size_t need = layout_pred(base, v.nrows, pred_entries(ratio, products, v.nrows), (char *)ws_d, &pw);
+    if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "predicted-size workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = v.nrows;
+
+    HCSP_HIP(launch_fill_i64(ws.num_count, HCSP_MAX_BINS, 0, s));
+    HCSP_HIP(launch_fill_u32(ws.err, 1, 0u, s));
+    HCSP_HIP(launch_fill_i64(C_row_ptr_d + n, 1, 0, s));
+    HCSP_HIP(launch_fill_i64(pw.pad_off + n, 1, 0, s));
+    HCSP_HIP(launch_fill_i64(pw.novf, 1, 0, s));
+    // 1. capacities and bins from the prediction, padded row starts
+    BinArgs ba = bin_args(&op, B, ws, tu, n, C_row_ptr_d);
+    ba.ratio = ratio;
+    ba.pad = pw.pad_off;
+    HCSP_HIP(launch_work_pred(ba, s));
+    HCSP_HIP(launch_scatter(ws.bin, n, ws.bin_hist, kNumBins, ws.num_count, ws.order_num, s));
+    HCSP_HIP(launch_scan_exclusive(pw.pad_off, n + 1, ws.scan_tmp, s));
+    int64_t cnt[HCSP_MAX_BINS];
+    HCSP_HIP(hipMemcpyAsync(cnt, ws.num_count, 8 * kNumBins, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    // 2. numeric with the predicted tables, into the padded scratch
+    SpArgs a = base_args(&op, B, ws, tu);
+    a.order = ws.order_num;
+    a.c_rp = C_row_ptr_d;
+    a.c_col = pw.scol;
+    a.c_val = pw.sval;
+    a.cap = pw.entries;
+    a.pad_off = pw.pad_off;
+    int64_t start = 0;
+    for (int b = 0; b < kNumBins; ++b) {
+        const int64_t c = cnt[b];
+        if (c > 0 && b != kBinEmpty && b != kNumGlobal) {
+            a.bin_begin = start;
+            a.count = c;
+            a.T = num_table((b - 1) % kNumT);
+            const int64_t gb = num_wave_bytes(false, 0, a.T);
+            a.group_bytes = (int)gb;
+            int blocks, threads;
+            size_t lds;
+            geometry(gb, c, &blocks, &threads, &lds);
+            rc = ensure_lds(lds, tu.lds_budget);
+            if (rc) return rc;
+            HCSP_HIP(launch_num_pred(a, blocks, threads, lds, s));
+        }
+        start += c;
+    }
+    // 3. rows the prediction did not hold: exact symbolic (it also scans every
+    //    row's count into offsets), else just the scan
+    int64_t novf = 0, nnz = 0;
+    HCSP_HIP(launch_mark_overflow(C_row_ptr_d, n, pw.active, pw.novf, s));
+    HCSP_HIP(hipMemcpyAsync(&novf, pw.novf, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    hcsp_sym_info info;
+    if (novf > 0) {
+        rc = symbolic_impl(&op, B, opts, C_row_ptr_d, &info, ws_d, base, stream, pw.active);
+        if (rc) return rc;
+        nnz = info.nnz;
+    } else {
+        HCSP_HIP(launch_scan_exclusive(C_row_ptr_d, n + 1, ws.scan_tmp, s));
+        HCSP_HIP(hipMemcpyAsync(&nnz, C_row_ptr_d + n, 8, hipMemcpyDeviceToHost, s));
+        HCSP_HIP(hipStreamSynchronize(s));
+    }
+    if (nnz_h) *nnz_h = nnz;
+    if (n_overflow_h) *n_overflow_h = novf;
+    if (nnz > capacity) return fail(HCSP_E_CAPACITY, "C capacity smaller than nnz(C) = " + std::to_string(nnz));
+    // 4. the other rows computed exactly; predicted rows to their exact place
+    if (novf > 0) {
+        hcsp_opts o2;
+        std::memset(&o2, 0, sizeof o2);
+        if (opts) o2 = *opts;
+        o2.flags &= ~HCSP_F_SYNC_CHECK;
+        o2.unit_lo = 0;
+        o2.unit_hi = 0;
+        o2.out_base = 0;
+        rc = hcsp_spgemm_numeric(&op, B, &o2, &info, C_row_ptr_d, C_col_d, C_val_d, capacity, ws_d, base, stream);
+        if (rc) return rc;
+    } else {
+        HCSP_HIP(launch_fill_u32(ws.err, 1, 0u, s));
+    }
+    HCSP_HIP(launch_copy_rows(pw.pad_off, pw.scol, pw.sval, C_row_ptr_d, pw.active, n, C_col_d, C_val_d, capacity,
+                              ws.err, s));
+    uint32_t e = 0;
+    HCSP_HIP(hipMemcpyAsync(&e, ws.err, 4, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "output capacity too small");
+    if (e & kErrCount) return fail(HCSP_E_INVALID, "row counts differ between the phases (inputs changed?)");
     return HCSP_OK;
 }
 

@@ -373,9 +373,16 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
 // counts kept while inserting) plus the smaller keys with the same home,
 // which all lie on the probe path from that home; no sort is needed, and a
 // CSR row's entries are written straight to their final positions.
-template <int S, bool CL>
+// PRED (CSR rows only): no symbolic phase ran; the table was sized from a
+// predicted capacity (ucount) and the key range is a bound from the rows of
+// B.  Probing gives up when the table is full, and a row whose keys did not
+// fit or exceed the capacity records -1 as its count and writes nothing;
+// otherwise its entries go to its padded slot (pad_off) and its count to
+// c_rp[row].
+template <int S, bool CL, bool PRED = false>
 __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned char *base)
 {
+    static_assert(!PRED || (S == 1 && !CL), "predicted sizes are for CSR rows");
     constexpr bool MS = CL && S > 1;  // several member rows (masks needed)
     const int lane = (int)__lane_id();
     if (u < a.unit_lo || u >= a.unit_hi) return;
@@ -414,12 +421,18 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         const int h = (int)((float)(uint32_t)(j - lo) * scale);
         return h < T ? h : T - 1;
     };
+    bool full = false;  // PRED: a key found no free slot
     auto probe = [&](int j) -> int {
         if (j == kDummyKey) return TX;
         const int h0 = home(j);
         int h = h0;
         int old = atomicCAS(&keys[h], kEmpty, j);
+        int steps = 0;
         while (old != kEmpty && old != j) {
+            if (PRED && ++steps >= TX) {
+                full = true;
+                return TX;
+            }
             if (++h == TX) h = 0;
             old = atomicCAS(&keys[h], kEmpty, j);
         }
@@ -492,10 +505,17 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     }
     if (lane == 0) hcnt[T] = U;
     int64_t o0 = 0, want = 0;
-    if (!MS) {
-        const int64_t row = member_row<CL>(a, v, 0);
-        o0 = a.c_rp[row] - a.out_base;
-        want = a.c_rp[row + 1] - a.c_rp[row];
+    const int64_t row0 = member_row<CL>(a, v, 0);
+    if (PRED) {
+        if (__ballot(full) != 0ull || U > a.ucount[u]) {
+            if (lane == 0) a.c_rp[row0] = -1;
+            return;
+        }
+        o0 = a.pad_off[row0];
+        want = U;
+    } else if (!MS) {
+        o0 = a.c_rp[row0] - a.out_base;
+        want = a.c_rp[row0 + 1] - a.c_rp[row0];
     }
     for (int c0 = 0; c0 < TX; c0 += 64) {
         const int sidx = c0 + lane;
@@ -522,6 +542,10 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
                 atomicOr(a.err, kErrCapacity);
             }
         }
+    }
+    if (PRED) {
+        if (lane == 0) a.c_rp[row0] = U;
+        return;
     }
     if (!MS) {
         if (lane == 0 && U != want) atomicOr(a.err, kErrCount);
@@ -752,7 +776,7 @@ hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int block
 // batch (BATCH), a persistent grid whose wavefronts each take one contiguous
 // slice of the bin, whose size and start are read from device memory; each
 // unit is then resolved to its product first.
-template <int S, bool CL, bool BATCH, bool NUM>
+template <int S, bool CL, bool BATCH, bool NUM, bool PRED = false>
 __device__ __forceinline__ void run_bin(const SpArgs &a0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -763,7 +787,7 @@ __device__ __forceinline__ void run_bin(const SpArgs &a0)
     if (!BATCH) {
         if (lw >= a0.count) return;
         const int u = a0.order[a0.bin_begin + lw];
-        if (NUM) num_unit<S, CL>(a0, u, base);
+        if (NUM) num_unit<S, CL, PRED>(a0, u, base);
         else sym_unit<S, CL>(a0, u, base);
         return;
     }
@@ -783,6 +807,14 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a) { run_bin<S, CL, BATCH, f
 
 template <int S, bool CL, bool BATCH>
 __global__ void __launch_bounds__(256) k_num(SpArgs a) { run_bin<S, CL, BATCH, true>(a); }
+
+__global__ void __launch_bounds__(256) k_num_pred(SpArgs a) { run_bin<1, false, false, true, true>(a); }
+
+hipError_t launch_num_pred(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_num_pred, dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
 
 // ================================================================ launchers
 template <int S, bool CL>

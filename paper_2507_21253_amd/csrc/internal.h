@@ -159,6 +159,9 @@ struct SpArgs {
     int nprob, bin;
     const int64_t *dcount, *dbegin;
     uint32_t *errs;
+    // predicted sizes: padded row starts (numeric writes there and stores its
+    // row count, or -1 when the prediction was too small, into c_rp)
+    const int64_t *pad_off;
 };
 
 // error flag bits
@@ -172,6 +175,8 @@ hipError_t launch_sym(int sclass, bool cluster, bool batch, const SpArgs &a, int
 hipError_t launch_num(int sclass, bool cluster, bool batch, const SpArgs &a, int blocks, int threads, size_t lds,
                       hipStream_t s);
 hipError_t launch_sym_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s);
+// numeric with predicted sizes (CSR rows): bounded probing, padded output
+hipError_t launch_num_pred(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s);
 hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s);
 
 // launchers (util.hip)
@@ -195,6 +200,11 @@ struct BinArgs {
     const BatchProb *batch;
     const int64_t *batch_units;
     int nprob;
+    // restriction to the units with active[u] != 0 (nullable: all units)
+    const uint8_t *active;
+    // predicted sizes: row capacity min(products, ceil(products * ratio)) into pad[]
+    float ratio;
+    int64_t *pad;
 };
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
@@ -203,6 +213,13 @@ hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s);
 hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
 // batches
 hipError_t launch_max_i64(const int64_t *x, int64_t n, int64_t *out, hipStream_t s);
+// predicted sizes
+hipError_t launch_products(const hcsp_csr &A, const hcsp_csr &B, int64_t *out, hipStream_t s);
+hipError_t launch_work_pred(const BinArgs &a, hipStream_t s);
+hipError_t launch_mark_overflow(const int64_t *c_rp, int64_t n, uint8_t *active, int64_t *count, hipStream_t s);
+hipError_t launch_copy_rows(const int64_t *pad_off, const int32_t *scol, const double *sval, const int64_t *c_rp,
+                            const uint8_t *active, int64_t n, int32_t *C_col, double *C_val, int64_t cap,
+                            uint32_t *err, hipStream_t s);
 hipError_t launch_bin_begin(const int64_t *counts, int nbins, int64_t *begin, hipStream_t s);
 hipError_t launch_batch_bound(const BatchProb *batch, int nprob, bool cluster, int64_t *ub, hipStream_t s);
 hipError_t launch_batch_seg_tail(const BatchProb *batch, int nprob, int64_t *flat, hipStream_t s);

@@ -129,6 +129,8 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
             probes += w.b_rp[k + 1] - w.b_rp[k];
         }
         probes = gsum64(g, probes);
+        const bool on = !a.active || a.active[u];
+        if (!on) probes = 0;
         const int bin = probes == 0 ? kBinEmpty : sym_bin(sclass_of(w.s), probes, a.sym_tmax_log2, a.sym_load_pct);
         if (g.gl == 0) {
             a.ws.probes[u] = probes;
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
             atomicAdd(&hist[bin], 1);
             if (bin == kBinEmpty) {
                 a.ws.ucount[u] = 0;
-                if (a.c_rp)  // null: estimate only
+                if (a.c_rp && on)  // null: estimate only; inactive units keep their count
                     for (int l = 0; l < w.s; ++l) w.c_rp[CL ? (int64_t)w.perm[w.pos0 + l] : w.u] = 0;
             }
         }
@@ -213,6 +215,148 @@ hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s)
     if (cluster && batch) hipLaunchKernelGGL((k_numbin<true, true>), dim3(blocks), dim3(256), 0, s, a);
     else if (cluster) hipLaunchKernelGGL((k_numbin<true, false>), dim3(blocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_numbin<false, false>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ predicted sizes
+// Sum over A's entries (i, k) of |B_k|: the number of products of A x B.
+__global__ void __launch_bounds__(256) k_products(const int64_t *a_rp, const int32_t *a_col, int64_t nnz,
+                                                  const int64_t *b_rp, int64_t *out)
+{
+    int64_t s = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
+        const int k = a_col[q];
+        s += b_rp[k + 1] - b_rp[k];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)out, (unsigned long long)s);
+}
+
+hipError_t launch_products(const hcsp_csr &A, const hcsp_csr &B, int64_t *out, hipStream_t s)
+{
+    if (A.nnz <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((A.nnz + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_products, dim3((unsigned)blocks), dim3(256), 0, s, A.row_ptr, A.col, A.nnz, B.row_ptr, out);
+    return hipGetLastError();
+}
+
+// Per CSR row: products, a column range that holds every output column (the
+// smallest first and largest last column over the rows of B it reaches), and
+// the predicted capacity min(products, ceil(products * ratio)), which picks
+// the numeric bin directly (no symbolic phase).  Empty rows get count 0.
+__global__ void __launch_bounds__(256) k_work_pred(BinArgs a)
+{
+    __shared__ int hist[kNumBins];
+    for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const Group g = make_group(16);
+    int64_t cb, ce;
+    chunk_of(a.nunits, &cb, &ce);
+    for (int64_t u = cb + (threadIdx.x >> 4); u < ce; u += blockDim.x >> 4) {
+        int64_t probes = 0;
+        int lo = INT_MAX, hi = -1;
+        for (int64_t q = a.a_rp[u] + g.gl; q < a.a_rp[u + 1]; q += 16) {
+            const int k = a.a_col[q];
+            const int64_t b0 = a.b_rp[k], b1 = a.b_rp[k + 1];
+            if (b1 > b0) {
+                probes += b1 - b0;
+                lo = min(lo, a.b_col[b0]);
+                hi = max(hi, a.b_col[b1 - 1]);
+            }
+        }
+        probes = gsum64(g, probes);
+        lo = gmin32(g, lo);
+        hi = gmax32(g, hi);
+        int bin = kBinEmpty;
+        int64_t cap = 0;
+        if (probes > 0) {
+            cap = min(probes, (int64_t)ceilf((float)probes * a.ratio));
+            cap = max(cap, (int64_t)1);
+            const int64_t need = (cap * 100 + a.load_pct - 1) / a.load_pct;
+            bin = kNumGlobal;
+            for (int t = 0; t < kNumT; ++t) {
+                const int T = num_table(t);
+                if (T > a.num_tmax_by_class[0]) break;
+                if (T >= need) {
+                    bin = 1 + t;
+                    break;
+                }
+            }
+        }
+        if (g.gl == 0) {
+            a.ws.probes[u] = probes;
+            a.ws.keylo[u] = lo;
+            a.ws.keyhi[u] = hi;
+            a.ws.ucount[u] = (int32_t)cap;
+            a.ws.bin[u] = (uint8_t)bin;
+            a.pad[u] = bin == kNumGlobal ? 0 : cap;
+            if (bin == kBinEmpty || bin == kNumGlobal) a.c_rp[u] = bin == kBinEmpty ? 0 : -1;
+            atomicAdd(&hist[bin], 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) a.ws.bin_hist[(int64_t)blockIdx.x * HCSP_MAX_BINS + i] = hist[i];
+}
+
+hipError_t launch_work_pred(const BinArgs &a, hipStream_t s)
+{
+    if (a.nunits <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_work_pred, dim3(bin_blocks(a.nunits)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// active[u] = the predicted pass gave up on row u (count -1); *count += rows.
+__global__ void __launch_bounds__(256) k_mark_overflow(const int64_t *c_rp, int64_t n, uint8_t *active, int64_t *count)
+{
+    int64_t c = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const bool o = c_rp[u] < 0;
+        active[u] = o;
+        c += o;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd((unsigned long long *)count, (unsigned long long)c);
+}
+
+hipError_t launch_mark_overflow(const int64_t *c_rp, int64_t n, uint8_t *active, int64_t *count, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_mark_overflow, dim3((unsigned)blocks), dim3(256), 0, s, c_rp, n, active, count);
+    return hipGetLastError();
+}
+
+// Rows finished by the predicted pass move from their padded slot to their
+// exact place in C (one 64-lane group per row).
+__global__ void __launch_bounds__(256) k_copy_rows(const int64_t *pad_off, const int32_t *scol, const double *sval,
+                                                   const int64_t *c_rp, const uint8_t *active, int64_t n,
+                                                   int32_t *C_col, double *C_val, int64_t cap, uint32_t *err)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t u = w0; u < n; u += nw) {
+        if (active[u]) continue;
+        const int64_t d0 = c_rp[u], len = c_rp[u + 1] - d0, s0 = pad_off[u];
+        if (d0 < 0 || d0 + len > cap) {
+            if (lane == 0) atomicOr(err, kErrCapacity);
+            continue;
+        }
+        for (int64_t e = lane; e < len; e += 64) {
+            C_col[d0 + e] = scol[s0 + e];
+            C_val[d0 + e] = sval[s0 + e];
+        }
+    }
+}
+
+hipError_t launch_copy_rows(const int64_t *pad_off, const int32_t *scol, const double *sval, const int64_t *c_rp,
+                            const uint8_t *active, int64_t n, int32_t *C_col, double *C_val, int64_t cap,
+                            uint32_t *err, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 3) / 4, 16384);
+    hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)blocks), dim3(256), 0, s, pad_off, scol, sval, c_rp, active, n,
+                       C_col, C_val, cap, err);
     return hipGetLastError();
 }
 

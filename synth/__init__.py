@@ -241,7 +241,7 @@ def batch_problem(seed: int, n_lo: float = 1e3, n_hi: float = 2e5) -> tuple[str,
 
 def learned_problem(seed: int, n_lo: float = 1e4, n_hi: float = 5e5) -> tuple[str, HostCSR]:
     """One matrix of the learned selector's data set: the generators above (2-D 5-point, 3-D 7-point and
-    27-point stencils, uniform-random with 4..32 entries per row, R-MAT of scale 13..15 with edge factor
+    27-point stencils, uniform-random with 4..32 entries per row, R-MAT of scale 12..14 with edge factor
     8..16), size log-uniform in [n_lo, n_hi] rows, and in half of the cases a seeded symmetric relabelling
     (natural order destroyed).  Returns (name, M)."""
     k = key(seed, 91)
@@ -257,7 +257,7 @@ def learned_problem(seed: int, n_lo: float = 1e4, n_hi: float = 5e5) -> tuple[st
         d = 4 + int(u64(k, 2) % 29)
         name, A = "uniform%d" % d, uniform(n, n, d, seed)
     else:
-        sc = 13 + int(u64(k, 3) % 3)
+        sc = 12 + int(u64(k, 3) % 3)
         ef = 8 + int(u64(k, 4) % 9)
         name, A = "rmat%d_%d" % (sc, ef), rmat(sc, ef, 0.57, 0.19, 0.19, seed)
     if u64(k, 5) & 1:

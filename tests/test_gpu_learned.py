@@ -1,0 +1,116 @@
+"""GPU parity of the learned selector's kernels against the float64 oracle
+(forward pass, back-propagation, Adam), and what the trained network gains
+over fixed policies on held-out matrices."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2507_21253_amd as hc  # noqa: E402
+from paper_2507_21253_amd import learned  # noqa: E402
+
+
+def data(seed, B=96):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0, 2, (B, 32)).astype(np.float32)
+    y = rng.integers(0, 4, B).astype(np.int32)
+    t = rng.normal(0, 1, B).astype(np.float32)
+    mu = rng.normal(0, 1, 32).astype(np.float32)
+    sd = rng.uniform(0.5, 2, 32).astype(np.float32)
+    theta = (mlp.init(seed) + rng.normal(0, 0.05, mlp.NPARAMS)).astype(np.float32)
+    return X, y, t, mu, sd, theta
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_pass(X, y, t, mu, sd, theta, lam):
+    B = X.shape[0]
+    P, norm, Xd = dev(theta), dev(np.concatenate([mu, sd])), dev(X)
+    Z = torch.empty(B, 5, dtype=torch.float32, device="cuda")
+    act = torch.empty(B, hc.MLP_NACT, dtype=torch.float32, device="cuda")
+    delta = torch.empty(B, hc.MLP_NDELTA, dtype=torch.float32, device="cuda")
+    loss = torch.empty(B, dtype=torch.float32, device="cuda")
+    g = torch.empty(hc.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    hc.mlp_forward(P, norm, Xd, Z, act)
+    hc.mlp_backward(P, act, Z, dev(y), dev(t), lam, delta, loss, g)
+    torch.cuda.synchronize()
+    return Z.cpu().numpy(), loss.cpu().numpy(), g.cpu().numpy()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_forward_loss_and_gradient_match_oracle(seed):
+    X, y, t, mu, sd, theta = data(seed)
+    lam = 0.5
+    Z, loss, g = gpu_pass(X, y, t, mu, sd, theta, lam)
+    # the oracle runs in float64 on the float32 inputs
+    z_ref, _ = mlp.forward(theta.astype(np.float64), mu.astype(np.float64), sd.astype(np.float64), X)
+    np.testing.assert_allclose(Z, z_ref, rtol=1e-4, atol=1e-4 * np.abs(z_ref).max())
+    l_ref = mlp.loss(theta.astype(np.float64), mu.astype(np.float64), sd.astype(np.float64), X, y, t, lam)
+    assert loss.mean() == pytest.approx(l_ref, rel=1e-4)
+    g_ref = mlp.grad(theta.astype(np.float64), mu.astype(np.float64), sd.astype(np.float64), X, y, t, lam)
+    scale = np.abs(g_ref).max()
+    assert np.abs(g - g_ref).max() <= 1e-4 * scale
+    np.testing.assert_allclose(g, g_ref, rtol=1e-3, atol=1e-5 * scale)
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(4)
+    theta = rng.normal(size=hc.MLP_NPARAMS).astype(np.float32)
+    m = np.zeros(hc.MLP_NPARAMS, np.float32)
+    v = np.zeros(hc.MLP_NPARAMS, np.float32)
+    P, M, V = dev(theta), dev(m), dev(v)
+    th64, m64, v64 = theta.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in range(1, 6):
+        g = rng.normal(size=hc.MLP_NPARAMS).astype(np.float32)
+        hc.mlp_adam(P, dev(g), M, V, step, lr=1e-2)
+        th64, m64, v64 = mlp.adam_step(th64, g.astype(np.float64), m64, v64, step, lr=1e-2)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(P.cpu().numpy(), th64, rtol=1e-5, atol=1e-6)
+
+
+def test_gpu_training_follows_the_oracle():
+    # same data, same initial weights: a few full-batch Adam steps on the GPU (float32) and in the
+    # oracle (float64) stay close, and both fit a learnable rule
+    rng = np.random.default_rng(6)
+    X = rng.normal(size=(256, 32)).astype(np.float32)
+    y = ((X[:, 0] > 0).astype(int) + 2 * (X[:, 1] > 0).astype(int)).astype(np.int32)
+    t = (0.5 * X[:, 2]).astype(np.float32)
+    sel = learned.Selector(seed=1)
+    theta0 = sel.params.astype(np.float64)
+    hist = sel.fit(X, y, t, epochs=300, lr=3e-3)
+    mu, sd = X.mean(0).astype(np.float64), np.maximum(X.std(0), 1e-3).astype(np.float64)
+    th, m, v = theta0, np.zeros(mlp.NPARAMS), np.zeros(mlp.NPARAMS)
+    for s in range(1, 301):
+        th, m, v = mlp.adam_step(th, mlp.grad(th, mu, sd, X, y, t, 1.0), m, v, s, lr=3e-3)
+    l_gpu = mlp.loss(sel.params.astype(np.float64), mu, sd, X, y, t, 1.0)
+    l_ref = mlp.loss(th, mu, sd, X, y, t, 1.0)
+    assert l_gpu == pytest.approx(l_ref, rel=0.05)
+    assert hist[-1] < 0.2 * hist[0]
+    assert np.mean(sel.choose(X) == y) > 0.9
+
+
+@pytest.mark.skipif(not os.path.exists(learned.DATA), reason="no labelled data set in the tree")
+def test_selector_gains_on_held_out_matrices():
+    ds = learned.load()
+    train, held = learned.split(ds)
+    y, t = learned.targets(train)
+    sel = learned.Selector(seed=1)
+    sel.fit(train["features"], y, t, epochs=1500)
+    ev = learned.evaluate(sel, held)
+    print(ev)
+    # no worse than always clustering (the method without the network), and never worse than 5% above
+    # the per-matrix best
+    assert ev["selector_ms"] <= ev["always_hc2_ms"]
+    assert ev["selector_ms"] <= ev["always_variable_ms"]
+    assert ev["selector_ms"] <= 1.05 * ev["best_ms"]
+    assert ev["log_ratio_abs_err_median"] < 0.25
