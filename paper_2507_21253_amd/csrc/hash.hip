@@ -24,6 +24,7 @@
 // being masked off; B is addressed by 32-bit offsets from a scalar base; and
 // the loads of several passes are issued before any of them is consumed.
 #include <climits>
+#include <type_traits>
 
 #include "unit.h"
 
@@ -182,7 +183,7 @@ __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, in
     const int blc = min(bl, kRoundW);
     const int incl = wave_incl_scan(blc);
     const int P = incl - blc;
-    const int E = min(__shfl(incl, 63), kRoundW);
+    const int E = uniform(min(__shfl(incl, 63), kRoundW));
     const bool in = blc > 0 && P < kRoundW;
     const uint64_t inb = __ballot(in);
     if (in) {
@@ -219,7 +220,8 @@ __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, in
 }
 
 // One lane's share of one pass: its entry of the flattened product list.
-// Lanes past the end get the dummy key and read B at offset 0.
+// Lanes past the end get the dummy key and read B at offset 0; FULL passes
+// (every lane inside the round) skip those checks.
 template <bool MS, bool NUM>
 struct Pass {
     int j;
@@ -228,14 +230,14 @@ struct Pass {
     double b, a;
 };
 
-template <bool MS, bool NUM>
+template <bool MS, bool NUM, bool FULL = false>
 __device__ __forceinline__ Pass<MS, NUM> fetch_pass(const SpArgs &a, const ItemRec *items, uint64_t w, int cum,
                                                     int e, int E, uint64_t le)
 {
     Pass<MS, NUM> d;
     d.t = cum + __popcll(w & le) - 1;
     const ItemRec it = items[d.t];
-    const bool ok = e < E;
+    const bool ok = FULL || e < E;
     const uint32_t off = ok ? it.bs + (uint32_t)(e - it.P) : 0u;
     const int j = ld_col(a.b_col, off);
     d.j = ok ? j : kDummyKey;
@@ -287,8 +289,9 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
 
     // one compare-and-swap takes an empty slot or confirms the key already
     // there; only collisions walk on
-    auto probe = [&](const Pass<MS, false> &d) {
-        uint32_t h = d.j == kDummyKey ? (uint32_t)T : ((uint32_t)d.j * 2654435761u) >> hshift;
+    auto probe = [&](const Pass<MS, false> &d, auto full_t) {
+        constexpr bool FULL = decltype(full_t)::value;
+        uint32_t h = !FULL && d.j == kDummyKey ? (uint32_t)T : ((uint32_t)d.j * 2654435761u) >> hshift;
         int old = atomicCAS(&keys[h], kEmpty, d.j);
         while (old != kEmpty && old != d.j) {
             h = (h + 1u) & hmask;
@@ -311,22 +314,27 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
         const int E = load_round<CL, S, false>(a, v, q0, off0, items, sbits, nullptr, nullptr);
         const int npass = (E + 63) >> 6;
         int cum = 0, p = 0;
-        for (; p + kR <= npass; p += kR) {
+        auto batch = [&](auto full_t) {
+            constexpr bool FULL = decltype(full_t)::value;
             Pass<MS, false> d[kR];
 #pragma unroll
             for (int rr = 0; rr < kR; ++rr) {
                 const uint64_t w = uniform64(sbits[p + rr]);
-                d[rr] = fetch_pass<MS, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                d[rr] = fetch_pass<MS, false, FULL>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
                 cum += __popcll(w);
             }
 #pragma unroll
             for (int rr = 0; rr < kR; ++rr) {
-                if (d[rr].j != kDummyKey) {
+                if (FULL || d[rr].j != kDummyKey) {
                     kmin = min(kmin, d[rr].j);
                     kmax = max(kmax, d[rr].j);
                 }
-                probe(d[rr]);
+                probe(d[rr], full_t);
             }
+        };
+        for (; p + kR <= npass; p += kR) {
+            if (((p + kR) << 6) <= E) batch(std::true_type{});
+            else batch(std::false_type{});
         }
         for (; p < npass; ++p) {
             const uint64_t w = uniform64(sbits[p]);
@@ -336,7 +344,7 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
                 kmin = min(kmin, d.j);
                 kmax = max(kmax, d.j);
             }
-            probe(d);
+            probe(d, std::false_type{});
         }
     }
     int U = inserted;
@@ -422,8 +430,8 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         return h < T ? h : T - 1;
     };
     bool full = false;  // PRED: a key found no free slot
-    auto probe = [&](int j) -> int {
-        if (j == kDummyKey) return TX;
+    auto probe = [&](int j, auto full_t) -> int {
+        if (!decltype(full_t)::value && j == kDummyKey) return TX;
         const int h0 = home(j);
         int h = h0;
         int old = atomicCAS(&keys[h], kEmpty, j);
@@ -466,20 +474,24 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         const int E = load_round<CL, S, true>(a, v, q0, off0, items, sbits, aval, areg);
         const int npass = (E + 63) >> 6;
         int cum = 0, p = 0;
-        for (; p + kR <= npass; p += kR) {
+        auto batch = [&](auto full_t) {
+            constexpr bool FULL = decltype(full_t)::value;
             Pass<MS, true> d[kR];
             int tf[kR], tl[kR];
 #pragma unroll
             for (int rr = 0; rr < kR; ++rr) {
                 const uint64_t w = uniform64(sbits[p + rr]);
-                const int last = min(63, E - 1 - ((p + rr) << 6));
                 tf[rr] = cum + (int)(w & 1ull) - 1;
-                tl[rr] = cum + __popcll(w & lanemask_le(last)) - 1;
-                d[rr] = fetch_pass<MS, true>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                tl[rr] = cum + (FULL ? __popcll(w) : __popcll(w & lanemask_le(min(63, E - 1 - ((p + rr) << 6))))) - 1;
+                d[rr] = fetch_pass<MS, true, FULL>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
                 cum += __popcll(w);
             }
 #pragma unroll
-            for (int rr = 0; rr < kR; ++rr) apply(d[rr], probe(d[rr].j), tf[rr], tl[rr]);
+            for (int rr = 0; rr < kR; ++rr) apply(d[rr], probe(d[rr].j, full_t), tf[rr], tl[rr]);
+        };
+        for (; p + kR <= npass; p += kR) {
+            if (((p + kR) << 6) <= E) batch(std::true_type{});
+            else batch(std::false_type{});
         }
         for (; p < npass; ++p) {
             const uint64_t w = uniform64(sbits[p]);
@@ -488,7 +500,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             const int tl = cum + __popcll(w & lanemask_le(last)) - 1;
             const Pass<MS, true> d = fetch_pass<MS, true>(a, items, w, cum, (p << 6) + lane, E, le);
             cum += __popcll(w);
-            apply(d, probe(d.j), tf, tl);
+            apply(d, probe(d.j, std::false_type{}), tf, tl);
         }
     }
 
