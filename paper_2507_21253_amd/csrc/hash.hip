@@ -235,7 +235,11 @@ __device__ __forceinline__ Pass<MS, NUM> fetch_pass(const SpArgs &a, const ItemR
                                                     int e, int E, uint64_t le)
 {
     Pass<MS, NUM> d;
-    d.t = cum + __popcll(w & le) - 1;
+    // start bits at or below this lane: bit 0 plus the bits of w >> 1 below it
+    const uint64_t w1 = w >> 1;
+    d.t = cum + (int)(w & 1ull) - 1 +
+          (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(w1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)w1, 0u));
+    (void)le;
     const ItemRec it = items[d.t];
     const bool ok = FULL || e < E;
     const uint32_t off = ok ? it.bs + (uint32_t)(e - it.P) : 0u;
@@ -518,6 +522,8 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     if (lane == 0) hcnt[T] = U;
     int64_t o0 = 0, want = 0;
     const int64_t row0 = member_row<CL>(a, v, 0);
+    int32_t *ccol = nullptr;
+    double *cval = nullptr;
     if (PRED) {
         if (__ballot(full) != 0ull || U > a.ucount[u]) {
             if (lane == 0) a.c_rp[row0] = -1;
@@ -528,6 +534,13 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     } else if (!MS) {
         o0 = a.c_rp[row0] - a.out_base;
         want = a.c_rp[row0 + 1] - a.c_rp[row0];
+    }
+    // a CSR row's place in C (uniform): the whole row must fit, else every
+    // entry is reported and none written
+    const bool row_fits = o0 >= 0 && o0 + want <= a.cap;
+    if (!MS && row_fits) {
+        ccol = a.c_col + o0;
+        cval = a.c_val + o0;
     }
     for (int c0 = 0; c0 < TX; c0 += 64) {
         const int sidx = c0 + lane;
@@ -546,10 +559,9 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             order[rank] = (uint16_t)sidx;
         } else {
             // a CSR row goes straight to its place in C
-            const int64_t dst = o0 + rank;
-            if (dst >= 0 && dst < a.cap && rank < want) {
-                a.c_col[dst] = key;
-                a.c_val[dst] = vals[sidx];
+            if (row_fits && rank < want) {
+                ccol[rank] = key;
+                cval[rank] = vals[sidx];
             } else {
                 atomicOr(a.err, kErrCapacity);
             }
@@ -817,8 +829,16 @@ __device__ __forceinline__ void run_bin(const SpArgs &a0)
 template <int S, bool CL, bool BATCH>
 __global__ void __launch_bounds__(256) k_sym(SpArgs a) { run_bin<S, CL, BATCH, false>(a); }
 
+// Wavefronts per SIMD the numeric kernels must allow (their register budget):
+// 7 (5 in batches) keeps narrow units at 72 (96) vector registers.
+template <int S, bool BATCH>
+struct NumOcc {
+    static constexpr int W = S <= 2 ? (BATCH ? 5 : 7) : 1;
+};
+
 template <int S, bool CL, bool BATCH>
-__global__ void __launch_bounds__(256) k_num(SpArgs a) { run_bin<S, CL, BATCH, true>(a); }
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NumOcc<S, BATCH>::W)))
+k_num(SpArgs a) { run_bin<S, CL, BATCH, true>(a); }
 
 __global__ void __launch_bounds__(256) k_num_pred(SpArgs a) { run_bin<1, false, false, true, true>(a); }
 
