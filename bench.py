@@ -134,7 +134,7 @@ def batch_mode(args):
         e = table.lookup(hc.features(H))
         if args.load_pct or args.sym_load_pct:
             e = dict(e, path="plain", load_pct=args.load_pct or 60, sym_load_pct=args.sym_load_pct or 70)
-        key = (e["path"], e["max_cluster"], e["sym_load_pct"], e["load_pct"])
+        key = (e["path"], e["max_cluster"], e["sym_load_pct"], e["cl_load_pct"] if e["path"] == "hc" else e["load_pct"])
         A = d
         if e["path"] == "hc":
             A = hc.cluster_build(d, hc.plan_hierarchical(H, (3, 10), e["max_cluster"], hc.SIM_ROOT,
@@ -280,7 +280,9 @@ def main():
 
     o = hc.opts(lanes=args.lanes, load_pct=args.load_pct or tuned["load_pct"],
                 sym_load_pct=args.sym_load_pct or tuned["sym_load_pct"])
-    P_cl = hc.Product(Dc, Bd, o)
+    o_cl = hc.opts(lanes=args.lanes, load_pct=args.load_pct or tuned["cl_load_pct"],
+                   sym_load_pct=args.sym_load_pct or tuned["sym_load_pct"])
+    P_cl = hc.Product(Dc, Bd, o_cl)
     P_pl = hc.Product(Md, Md, o)
     wall_cl, sym_cl, num_cl = time_product(P_cl, args.steps, args.warmup, torch)
     nnzC = P_cl.info.nnz
@@ -336,7 +338,8 @@ def main():
     # dominant kernel family: the numeric launches; its algorithmic bytes are A (clustered), B and C
     ach = comp_cl / (num_cl * 1e-3) / 1e9
     traffic = numeric_traffic("clustered", "m%d_%s%s_mc%d_%s_s%d_n%d" % (
-        m, args.reorder, "sym" if args.symmetric else "", args.max_cluster, args.sim, o.sym_load_pct, o.load_pct))
+        m, args.reorder, "sym" if args.symmetric else "", args.max_cluster, args.sim, o_cl.sym_load_pct,
+        o_cl.load_pct))
 
     cpu = None
     if not args.no_cpu:
@@ -372,7 +375,8 @@ def main():
                                                                                   else " rows of A"),
                    "clustering": "hierarchical",
                    "jacc_th": "3/10", "max_cluster": args.max_cluster, "similarity": args.sim,
-                   "sym_load_pct": o.sym_load_pct, "load_pct": o.load_pct, "autotuned": bool(tuned["tuned"])},
+                   "sym_load_pct": o.sym_load_pct, "load_pct": o_cl.load_pct, "plain_load_pct": o.load_pct,
+                   "autotuned": bool(tuned["tuned"])},
         "gbs_compulsory": round(comp_cl / (wall_cl * 1e-3) / 1e9, 2),
         "phases_ms": {"symbolic_incl_readback": round(sym_cl, 4), "numeric": round(num_cl, 4)},
         "plain_csr": {"gflops": round(gflops_pl, 3), "ms_per_step": round(wall_pl, 4),

@@ -16,7 +16,10 @@ Tuned per class:
     phase),
   * ``path`` and ``max_cluster`` -- plain CSR, or CSR_Cluster from
     hierarchical clustering (Alg. 3, threshold 3/10) with at most 2, 4 or 8
-    rows per cluster.
+    rows per cluster;
+  * ``cl_load_pct`` -- the numeric fill target for the clustered product
+    (a cluster's table carries a value column per member, so a different
+    fill can pay).
 
 The decision is steady-state product time (symbolic + nnz read-back +
 numeric), the regime of repeated products over one structure that the
@@ -90,10 +93,24 @@ def tune_matrix(H, reps: int = 3, threads: int = 0) -> dict:
         ms = _time_ms(Product(Dc, D, o), reps)
         times["hc%d" % mc] = ms
         cand.append(("hc", mc, ms))
-    path, mc, ms = min(cand, key=lambda c: c[2])
     best_hc = min((c for c in cand if c[0] == "hc"), key=lambda c: c[2])
+    # stage 3: numeric fill for the clustered product at its best size
+    plan = plan_hierarchical(H, (3, 10), best_hc[1], SIM_ROOT, nthreads=threads)
+    Dc = cluster_build(D, plan)
+    cl_best = (best_hc[2], nl)
+    for cl in NUM_LOADS:
+        if cl == nl:
+            continue
+        ms = _time_ms(Product(Dc, D, opts(sym_load_pct=sl, load_pct=cl)), reps)
+        times["hc%d_n%d" % (best_hc[1], cl)] = ms
+        if ms < cl_best[0]:
+            cl_best = (ms, cl)
+    cand = [c if c[0] != "hc" or c[1] != best_hc[1] else ("hc", c[1], cl_best[0]) for c in cand]
+    times["hc%d" % best_hc[1]] = cl_best[0]
+    path, mc, ms = min(cand, key=lambda c: c[2])
     return {"class": matrix_class(f), "path": path, "max_cluster": mc, "best_cluster_size": best_hc[1],
-            "sym_load_pct": sl, "load_pct": nl, "ms": ms, "times_ms": times, "prep_s": prep,
+            "sym_load_pct": sl, "load_pct": nl, "cl_load_pct": cl_best[1], "ms": ms, "times_ms": times,
+            "prep_s": prep,
             "features": [float(x) for x in f], "nrows": int(H.nrows), "nnz": int(H.nnz)}
 
 
@@ -120,16 +137,19 @@ class TuneTable:
         of per-matrix times relative to each matrix's own best."""
         e = self.entries.setdefault(r["class"], {"runs": []})
         e["runs"].append({k: r[k] for k in ("path", "max_cluster", "best_cluster_size", "sym_load_pct",
-                                            "load_pct", "ms", "times_ms", "nrows", "nnz")})
+                                            "load_pct", "cl_load_pct", "ms", "times_ms", "nrows", "nnz")})
         runs = e["runs"]
         keys = set.intersection(*[set(x["times_ms"]) for x in runs])
         score = {k: sum(x["times_ms"][k] / x["ms"] for x in runs) for k in keys}
         stage1 = min((k for k in score if k.startswith("plain_")), key=score.get)
         sl, nl = (int(v[1:]) for v in stage1.split("_")[1:])
         paths = {"plain": score[stage1]}
-        paths.update({k: score[k] for k in score if k.startswith("hc")})
+        paths.update({k: score[k] for k in score if k.startswith("hc") and "_" not in k})
         win = min(paths, key=paths.get)
-        hcs = [k for k in paths if k.startswith("hc")]
+        hcs = [k for k in paths if k.startswith("hc") and "_" not in k]
+        # the clustered product's fill: the runs' own choices, most frequent (ties: the smaller)
+        cls = sorted(x.get("cl_load_pct", nl) for x in runs)
+        e["cl_load_pct"] = max(set(cls), key=lambda c: (cls.count(c), -c))
         e.update({"sym_load_pct": sl, "load_pct": nl, "path": "plain" if win == "plain" else "hc",
                   "max_cluster": 0 if win == "plain" else int(win[2:]),
                   "best_cluster_size": int(min(hcs, key=paths.get)[2:]) if hcs else 2})
@@ -137,9 +157,10 @@ class TuneTable:
     def lookup(self, f: np.ndarray) -> dict:
         e = self.entries.get(matrix_class(f))
         if e is None:
-            return dict(DEFAULT, best_cluster_size=2, tuned=False)
+            return dict(DEFAULT, best_cluster_size=2, cl_load_pct=DEFAULT["load_pct"], tuned=False)
         return {"path": e["path"], "max_cluster": e["max_cluster"], "best_cluster_size": e["best_cluster_size"],
-                "sym_load_pct": e["sym_load_pct"], "load_pct": e["load_pct"], "tuned": True}
+                "sym_load_pct": e["sym_load_pct"], "load_pct": e["load_pct"],
+                "cl_load_pct": e.get("cl_load_pct", e["load_pct"]), "tuned": True}
 
     def opts_for(self, f: np.ndarray):
         e = self.lookup(f)

@@ -51,7 +51,7 @@ def test_features_similarity_of_neighbours():
 
 def run(cls, times, best, path="plain", mc=0):
     return {"class": cls, "path": path, "max_cluster": mc, "best_cluster_size": 2, "sym_load_pct": 70,
-            "load_pct": 60, "ms": best, "times_ms": times, "nrows": 10, "nnz": 10}
+            "load_pct": 60, "cl_load_pct": 70, "ms": best, "times_ms": times, "nrows": 10, "nnz": 10}
 
 
 def test_tune_table_choice_rule_and_roundtrip(tmp_path):
@@ -60,6 +60,7 @@ def test_tune_table_choice_rule_and_roundtrip(tmp_path):
     t.add(run("rl2_cv0_cr2_sim2", times, 1.2, "hc", 2))
     e = t.entries["rl2_cv0_cr2_sim2"]
     assert (e["path"], e["max_cluster"], e["sym_load_pct"], e["load_pct"]) == ("hc", 2, 100, 60)
+    assert e["cl_load_pct"] == 70
     # a second matrix of the class where plain wins by far moves the choice
     t.add(run("rl2_cv0_cr2_sim2", {"plain_s70_n60": 1.0, "plain_s100_n60": 1.1, "hc2": 3.0, "hc4": 4.0,
                                    "hc8": 5.0}, 1.0))
