@@ -100,7 +100,7 @@ static int make_tune(const hcsp_opts *o, const hcsp_csr *B, bool need_device, Tu
     if (t->sym_load_pct < 10 || t->sym_load_pct > 100) return fail(HCSP_E_INVALID, "opts.sym_load_pct must be in 10..100");
     t->lds_budget = need_device ? lds_limit() : 64 * 1024;
     int sym = kSymLog2Max;
-    while (sym > kSymLog2Min && sym_wave_bytes(true, 1 << sym) > t->lds_budget) --sym;
+    while (sym > kSymLog2Min && sym_wave_bytes(2, 1 << sym) > t->lds_budget) --sym;
     if (o->sym_tmax_log2) sym = std::max(kSymLog2Min + 1, std::min(sym, (int)o->sym_tmax_log2));
     t->sym_tmax_log2 = sym;
     t->num_tmax = o->num_tmax ? o->num_tmax : (1 << 30);
@@ -486,7 +486,7 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
                 const int l2 = (b - 1) % kSymT + kSymLog2Min;
                 a.T = 1 << l2;
                 a.log2T = l2;
-                const int64_t gb = sym_wave_bytes(v.cluster && sc > 0, a.T);
+                const int64_t gb = sym_wave_bytes(v.cluster ? mask_bytes_of_class(sc) : 0, a.T);
                 a.group_bytes = (int)gb;
                 int blocks, threads;
                 size_t lds;
@@ -980,7 +980,7 @@ int hcsp_spgemm_batched(const hcsp_batch_plan *plan, int64_t *C_row_ptr_d, int32
             a.bin = 1 + sc * kSymT + (l2 - kSymLog2Min);
             a.T = 1 << l2;
             a.log2T = l2;
-            const int64_t gb = sym_wave_bytes(cl && sc > 0, a.T);
+            const int64_t gb = sym_wave_bytes(cl ? mask_bytes_of_class(sc) : 0, a.T);
             a.group_bytes = (int)gb;
             int blocks, threads;
             size_t lds;

@@ -103,38 +103,62 @@ __device__ __forceinline__ double ld_val(const double *base, uint32_t off)
 }
 
 // ---------------------------------------------------------------- LDS layout
-// Slot counts include one reserved dummy slot at the end.
+// Slot counts include one reserved dummy slot at the end.  A cluster's
+// member-presence masks take one byte per slot (up to 8 rows) or two (16).
+template <int S>
+using MaskT = typename std::conditional<(S <= 8), uint8_t, uint16_t>::type;
+
+// Atomic OR of m into the mask of slot h (through the aligned 32-bit word
+// that holds it); returns the mask before.
+template <int S>
+__device__ __forceinline__ uint32_t mask_or(MaskT<S> *masks, uint32_t h, uint32_t m)
+{
+    const uintptr_t p = (uintptr_t)(masks + h);
+    const int sh = 8 * (int)(p & 3u);
+    const uint32_t old = atomicOr((uint32_t *)(p & ~(uintptr_t)3), m << sh);
+    return (old >> sh) & (S <= 8 ? 0xffu : 0xffffu);
+}
+
+// sizes of the cluster mask region (rounded to whole 32-bit words)
+__host__ __device__ constexpr int mask_region(int mb, int slots) { return (mb * slots + 3) & ~3; }
+
 struct SymLayout {
     int keys, masks, items, sbits, bytes;
-    __host__ __device__ SymLayout(bool cl, int T)
+    __host__ __device__ SymLayout(int mb, int T)  // mb: mask bytes per slot, 0 for one-row units
     {
         keys = 0;
         masks = keys + 4 * (T + 1);
-        items = (masks + (cl ? 4 * (T + 1) : 0) + 15) & ~15;
+        items = (masks + mask_region(mb, T + 1) + 15) & ~15;
         sbits = items + 16 * 64;
         bytes = (sbits + 8 * kRoundPasses + 15) & ~15;
     }
 };
 
+// The rank-ordered slot list of a cluster (2 bytes per slot) reuses the
+// item and start-bit area, which is free once the passes are done, when it
+// fits there.
 struct NumLayout {
     int keys, masks, vals, aval, order, items, sbits, hcnt, bytes;
     __host__ __device__ NumLayout(bool cl, int S, int TX)
     {
         const int T = TX - kTail;
+        cl = cl && S > 1;
+        const int mb = cl ? (S <= 8 ? 1 : 2) : 0;
+        const bool order_in_items = 2 * TX <= 16 * 64 + 8 * kRoundPasses;
         keys = 0;
         masks = keys + 4 * (TX + 1);
-        cl = cl && S > 1;
-        vals = (masks + (cl ? 4 * (TX + 1) : 0) + 15) & ~15;
+        vals = (masks + mask_region(mb, TX + 1) + 15) & ~15;
         aval = vals + 8 * S * (TX + 1);
-        order = aval + (cl && !a_in_regs(S) ? 8 * S * 64 : 0);
-        items = (order + (cl ? 2 * TX : 0) + 15) & ~15;
+        const int end = aval + (cl && !a_in_regs(S) ? 8 * S * 64 : 0);
+        items = (end + (cl && !order_in_items ? 2 * TX : 0) + 15) & ~15;
+        order = cl && order_in_items ? items : end;
         sbits = items + 16 * 64;
         hcnt = sbits + 8 * kRoundPasses;
         bytes = (hcnt + 4 * (T + 1) + 15) & ~15;
     }
 };
 
-int64_t sym_wave_bytes(bool multi, int T) { return SymLayout(multi, T).bytes; }
+int64_t sym_wave_bytes(int mask_bytes, int T) { return SymLayout(mask_bytes, T).bytes; }
 int64_t num_wave_bytes(bool cl, int sclass, int T) { return NumLayout(cl, 1 << sclass, T + kTail).bytes; }
 
 // ---------------------------------------------------------------- rounds
@@ -270,14 +294,14 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
     constexpr bool MS = CL && S > 1;  // several member rows (masks needed)
     const int lane = (int)__lane_id();
     const int T = a.T;
-    const SymLayout L(MS, T);
+    const SymLayout L(MS ? (S <= 8 ? 1 : 2) : 0, T);
     int *keys = (int *)(base + L.keys);
-    uint32_t *masks = (uint32_t *)(base + L.masks);
+    MaskT<S> *masks = (MaskT<S> *)(base + L.masks);
     ItemRec *items = (ItemRec *)(base + L.items);
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
     for (int i = lane; i <= T; i += 64) {
         keys[i] = i == T ? kDummyKey : kEmpty;
-        if (MS) masks[i] = 0u;
+        if (MS) masks[i] = 0;
     }
     int mcnt[S];  // wave-uniform per-member counts
 #pragma unroll
@@ -304,7 +328,7 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
         inserted += old == kEmpty;
         if (MS) {
             // member rows that see this column for the first time
-            uint32_t fresh = d.m & ~atomicOr(&masks[h], d.m);
+            uint32_t fresh = d.m & ~mask_or<S>(masks, h, d.m);
             if (h == (uint32_t)T) fresh = 0u;
             if (__ballot(fresh != 0u)) {
 #pragma unroll
@@ -402,7 +426,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     const int T = a.T, TX = a.T + kTail;
     const NumLayout L(MS, S, TX);
     int *keys = (int *)(base + L.keys);
-    uint32_t *masks = (uint32_t *)(base + L.masks);
+    MaskT<S> *masks = (MaskT<S> *)(base + L.masks);
     double *vals = (double *)(base + L.vals);
     double *aval = (double *)(base + L.aval);
     uint16_t *order = (uint16_t *)(base + L.order);
@@ -415,7 +439,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     for (int i = lane; i <= TX; i += 64) {
         keys[i] = i == TX ? kDummyKey : kEmpty;
         if (i < T) hcnt[i] = 0;
-        if (MS) masks[i] = 0u;
+        if (MS) masks[i] = 0;
 #pragma unroll
         for (int l = 0; l < S; ++l)
             if (l < v.s) vals[l * VS + i] = 0.0;
@@ -458,7 +482,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             if (MS) {
                 const uint32_t mt = (uint32_t)uniform((int)items[tt].x);
                 const int src = uniform((int)items[tt].y);
-                atomicOr(&masks[h], mt);  // lanes of one sub-step hold distinct slots
+                masks[h] = (MaskT<S>)(masks[h] | mt);  // lanes of one sub-step hold distinct slots
 #pragma unroll
                 for (int l = 0; l < S; ++l) {
                     if ((mt >> l) & 1u) {

@@ -54,7 +54,9 @@ __host__ __device__ inline int sclass_of(int s)
 }
 
 // Shared-memory bytes of one wavefront's tables (layouts in hash.hip).
-int64_t sym_wave_bytes(bool multi, int T);  // multi: units of several rows (masks kept)
+int64_t sym_wave_bytes(int mask_bytes, int T);  // mask bytes per slot: 0 for one-row units
+// mask bytes per slot of a member-count class (0: one row, 1: up to 8 rows, 2: 16)
+inline int mask_bytes_of_class(int sc) { return sc == 0 ? 0 : (sc <= 3 ? 1 : 2); }
 int64_t num_wave_bytes(bool cl, int sclass, int T);
 
 // Tuning derived from hcsp_opts.
