@@ -37,6 +37,7 @@ from . import (DeviceCSR, Product, SIM_ROOT, cluster_build, features, opts, plan
 
 SYM_LOADS = (50, 70, 100)
 NUM_LOADS = (50, 60, 70)
+CL_LOADS = (50, 55, 60, 65, 70)
 MAX_CLUSTERS = (2, 4, 8)
 DEFAULT = {"path": "plain", "max_cluster": 0, "sym_load_pct": 70, "load_pct": 60}
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
@@ -81,32 +82,21 @@ def tune_matrix(H, reps: int = 3, threads: int = 0) -> dict:
             if best is None or ms < best[0]:
                 best = (ms, sl, nl)
     _, sl, nl = best
-    o = opts(sym_load_pct=sl, load_pct=nl)
-    # stage 2: cluster size, with those tables
+    # stage 2: cluster size and the clustered product's numeric fill (its tables carry a value column per
+    # member, so its best fill can differ from the plain product's)
     prep = {}
-    cand = [("plain", 0, best[0])]
     for mc in MAX_CLUSTERS:
         t = time.perf_counter()
         plan = plan_hierarchical(H, (3, 10), mc, SIM_ROOT, nthreads=threads)
         Dc = cluster_build(D, plan)
         prep["hc%d" % mc] = time.perf_counter() - t
-        ms = _time_ms(Product(Dc, D, o), reps)
-        times["hc%d" % mc] = ms
-        cand.append(("hc", mc, ms))
-    best_hc = min((c for c in cand if c[0] == "hc"), key=lambda c: c[2])
-    # stage 3: numeric fill for the clustered product at its best size
-    plan = plan_hierarchical(H, (3, 10), best_hc[1], SIM_ROOT, nthreads=threads)
-    Dc = cluster_build(D, plan)
-    cl_best = (best_hc[2], nl)
-    for cl in NUM_LOADS:
-        if cl == nl:
-            continue
-        ms = _time_ms(Product(Dc, D, opts(sym_load_pct=sl, load_pct=cl)), reps)
-        times["hc%d_n%d" % (best_hc[1], cl)] = ms
-        if ms < cl_best[0]:
-            cl_best = (ms, cl)
-    cand = [c if c[0] != "hc" or c[1] != best_hc[1] else ("hc", c[1], cl_best[0]) for c in cand]
-    times["hc%d" % best_hc[1]] = cl_best[0]
+        for cl in CL_LOADS:
+            times["hc%d_n%d" % (mc, cl)] = _time_ms(Product(Dc, D, opts(sym_load_pct=sl, load_pct=cl)), reps)
+        times["hc%d" % mc] = min(times["hc%d_n%d" % (mc, cl)] for cl in CL_LOADS)
+        del Dc
+    cand = [("plain", 0, best[0])] + [("hc", mc, times["hc%d" % mc]) for mc in MAX_CLUSTERS]
+    best_hc = min(cand[1:], key=lambda c: c[2])
+    cl_best = min((times["hc%d_n%d" % (best_hc[1], cl)], cl) for cl in CL_LOADS)
     path, mc, ms = min(cand, key=lambda c: c[2])
     return {"class": matrix_class(f), "path": path, "max_cluster": mc, "best_cluster_size": best_hc[1],
             "sym_load_pct": sl, "load_pct": nl, "cl_load_pct": cl_best[1], "ms": ms, "times_ms": times,
@@ -147,9 +137,10 @@ class TuneTable:
         paths.update({k: score[k] for k in score if k.startswith("hc") and "_" not in k})
         win = min(paths, key=paths.get)
         hcs = [k for k in paths if k.startswith("hc") and "_" not in k]
-        # the clustered product's fill: the runs' own choices, most frequent (ties: the smaller)
-        cls = sorted(x.get("cl_load_pct", nl) for x in runs)
-        e["cl_load_pct"] = max(set(cls), key=lambda c: (cls.count(c), -c))
+        # the clustered product's fill at the class's best size: least summed relative time
+        bcs = int(min(hcs, key=paths.get)[2:]) if hcs else 2
+        cl_keys = [k for k in score if k.startswith("hc%d_n" % bcs)]
+        e["cl_load_pct"] = int(min(cl_keys, key=score.get).split("_n")[1]) if cl_keys else nl
         e.update({"sym_load_pct": sl, "load_pct": nl, "path": "plain" if win == "plain" else "hc",
                   "max_cluster": 0 if win == "plain" else int(win[2:]),
                   "best_cluster_size": int(min(hcs, key=paths.get)[2:]) if hcs else 2})

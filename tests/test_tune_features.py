@@ -56,16 +56,20 @@ def run(cls, times, best, path="plain", mc=0):
 
 def test_tune_table_choice_rule_and_roundtrip(tmp_path):
     t = tune.TuneTable()
-    times = {"plain_s70_n60": 2.0, "plain_s100_n60": 1.5, "hc2": 1.2, "hc4": 1.8, "hc8": 3.0}
+    times = {"plain_s70_n60": 2.0, "plain_s100_n60": 1.5, "hc2": 1.2, "hc4": 1.8, "hc8": 3.0,
+             "hc2_n60": 1.3, "hc2_n70": 1.2}
     t.add(run("rl2_cv0_cr2_sim2", times, 1.2, "hc", 2))
     e = t.entries["rl2_cv0_cr2_sim2"]
     assert (e["path"], e["max_cluster"], e["sym_load_pct"], e["load_pct"]) == ("hc", 2, 100, 60)
     assert e["cl_load_pct"] == 70
     # a second matrix of the class where plain wins by far moves the choice
     t.add(run("rl2_cv0_cr2_sim2", {"plain_s70_n60": 1.0, "plain_s100_n60": 1.1, "hc2": 3.0, "hc4": 4.0,
-                                   "hc8": 5.0}, 1.0))
+                                   "hc8": 5.0, "hc2_n60": 3.0, "hc2_n70": 3.2}, 1.0))
     e = t.entries["rl2_cv0_cr2_sim2"]
     assert e["path"] == "plain" and e["best_cluster_size"] == 2
+    # fill of the clustered product: least summed relative time, 1.3/1.2 + 3.0/1.0 < 1.2/1.2 + 3.2/1.0
+    assert e["cl_load_pct"] == 60
+
     p = tmp_path / "t.json"
     t.save(str(p))
     u = tune.TuneTable.load(str(p))
