@@ -3,10 +3,12 @@
 
 Workload (default): C = M*M for M the 27-point stencil on a 100^3 grid with
 values U(-1,1), symmetrically relabelled by a seeded random permutation so
-the natural locality is gone.  Hierarchical clustering (Alg. 3, jacc_th 0.3,
-max cluster 2 by default, the fastest measured; the paper uses 8) then
-regroups similar rows into CSR_Cluster and the product runs cluster-wise
-(Alg. 1).  One step = symbolic phase (binning, counts,
+the natural locality is gone.  The method recovers it: A's rows are put in
+reverse Cuthill-McKee order, hierarchical clustering (Alg. 3, jacc_th 0.3,
+at most 2 rows per cluster by default -- the autotuner's choice; the paper
+uses 8) regroups similar rows into CSR_Cluster, and the product runs
+cluster-wise (Alg. 1) against B = M.  The baseline is the plain row-wise
+product of M in its given order.  One step = symbolic phase (binning, counts,
 scan), the nnz read-back, and the numeric phase of the clustered product;
 the plain-CSR product of the same matrix is timed the same way for the
 comparison.  Clustering itself (host plan + device CSR_Cluster build) is
@@ -50,7 +52,9 @@ def parse():
     p.add_argument("--max-cluster", type=int, default=0,
                    help="rows per cluster at most (0: the autotuner's choice for the matrix class, else 2)")
     p.add_argument("--sim", choices=["root", "union"], default="root")
-    p.add_argument("--reorder", choices=["rcm", "degree", "none"], default="none",
+    p.add_argument("--clustering", choices=["hierarchical", "variable", "fixed"], default="hierarchical",
+                   help="plan: Alg. 3 (default), Alg. 2 (threshold 3/10) or fixed-length blocks")
+    p.add_argument("--reorder", choices=["rcm", "degree", "none"], default="rcm",
                    help="row order of A before clustering (A = M with rows permuted, B = M)")
     p.add_argument("--symmetric", action="store_true",
                    help="permute M symmetrically (rows and columns; B reordered too) instead of A's rows only")
@@ -260,8 +264,13 @@ def main():
         R = hc.permute_h(M, P, P if args.symmetric else None, ncpu)
     t_reorder = time.perf_counter() - t
     t = time.perf_counter()
-    plan = hc.plan_hierarchical(R, (3, 10), args.max_cluster, hc.SIM_UNION if args.sim == "union" else hc.SIM_ROOT,
-                                nthreads=ncpu)
+    if args.clustering == "variable":
+        plan = hc.plan_variable(R, (3, 10), args.max_cluster)
+    elif args.clustering == "fixed":
+        plan = hc.plan_fixed(R.nrows, args.max_cluster)
+    else:
+        plan = hc.plan_hierarchical(R, (3, 10), args.max_cluster,
+                                    hc.SIM_UNION if args.sim == "union" else hc.SIM_ROOT, nthreads=ncpu)
     t_plan = time.perf_counter() - t
     log("reorder %s %.2fs; plan: %d clusters (%.2fs, %d threads)" % (args.reorder, t_reorder, plan.nclusters,
                                                                      t_plan, ncpu))
@@ -373,7 +382,7 @@ def main():
         "config": {"workload": "stencil27_%d^3_relabelled_A2" % m, "nrows": M.nrows, "nnz_A": M.nnz,
                    "nnz_C": nnzC, "products": products, "reorder": args.reorder + (" symmetric" if args.symmetric
                                                                                   else " rows of A"),
-                   "clustering": "hierarchical",
+                   "clustering": args.clustering,
                    "jacc_th": "3/10", "max_cluster": args.max_cluster, "similarity": args.sim,
                    "sym_load_pct": o.sym_load_pct, "load_pct": o_cl.load_pct, "plain_load_pct": o.load_pct,
                    "autotuned": bool(tuned["tuned"])},

@@ -139,9 +139,9 @@ struct SymLayout {
 // fits there.
 struct NumLayout {
     int keys, masks, vals, aval, order, items, sbits, hcnt, bytes;
-    __host__ __device__ NumLayout(bool cl, int S, int TX)
+    __host__ __device__ NumLayout(bool cl, int S, int T)
     {
-        const int T = TX - kTail;
+        const int TX = T + num_tail(T);
         cl = cl && S > 1;
         const int mb = cl ? (S <= 8 ? 1 : 2) : 0;
         const bool order_in_items = 2 * TX <= 16 * 64 + 8 * kRoundPasses;
@@ -154,12 +154,12 @@ struct NumLayout {
         order = cl && order_in_items ? items : end;
         sbits = items + 16 * 64;
         hcnt = sbits + 8 * kRoundPasses;
-        bytes = (hcnt + 4 * (T + 1) + 15) & ~15;
+        bytes = (hcnt + 2 * (T + 1) + 15) & ~15;  // 16-bit home counts
     }
 };
 
 int64_t sym_wave_bytes(int mask_bytes, int T) { return SymLayout(mask_bytes, T).bytes; }
-int64_t num_wave_bytes(bool cl, int sclass, int T) { return NumLayout(cl, 1 << sclass, T + kTail).bytes; }
+int64_t num_wave_bytes(bool cl, int sclass, int T) { return NumLayout(cl, 1 << sclass, T).bytes; }
 
 // ---------------------------------------------------------------- rounds
 // Loads the next round of items into LDS: lane i takes column q0+i of the
@@ -423,8 +423,8 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     const int lane = (int)__lane_id();
     if (u < a.unit_lo || u >= a.unit_hi) return;
 
-    const int T = a.T, TX = a.T + kTail;
-    const NumLayout L(MS, S, TX);
+    const int T = a.T, TX = a.T + num_tail(a.T);
+    const NumLayout L(MS, S, T);
     int *keys = (int *)(base + L.keys);
     MaskT<S> *masks = (MaskT<S> *)(base + L.masks);
     double *vals = (double *)(base + L.vals);
@@ -432,7 +432,9 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     uint16_t *order = (uint16_t *)(base + L.order);
     ItemRec *items = (ItemRec *)(base + L.items);
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
-    int *hcnt = (int *)(base + L.hcnt);  // per-home key counts, then their exclusive prefix
+    // per-home key counts, then their exclusive prefix (16 bits: a table holds
+    // fewer than 2^16 keys); counted through the aligned 32-bit words
+    uint16_t *hcnt = (uint16_t *)(base + L.hcnt);
 
     const int VS = TX + 1;  // value column stride (slots incl. the dummy)
     const UnitView v = unit_view<CL>(a, u);
@@ -472,7 +474,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             if (++h == TX) h = 0;
             old = atomicCAS(&keys[h], kEmpty, j);
         }
-        if (old == kEmpty) atomicAdd(&hcnt[h0], 1);
+        if (old == kEmpty) atomicAdd((uint32_t *)(hcnt + (h0 & ~1)), 1u << (16 * (h0 & 1)));
         return h;
     };
     // products of one pass, applied item by item (ascending k)
@@ -540,10 +542,10 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         const int i = c0 + lane;
         const int cnt = i < T ? hcnt[i] : 0;
         const int incl = wave_incl_scan(cnt);
-        if (i < T) hcnt[i] = U + incl - cnt;
+        if (i < T) hcnt[i] = (uint16_t)(U + incl - cnt);
         U += __shfl(incl, 63);
     }
-    if (lane == 0) hcnt[T] = U;
+    if (lane == 0) hcnt[T] = (uint16_t)U;
     int64_t o0 = 0, want = 0;
     const int64_t row0 = member_row<CL>(a, v, 0);
     int32_t *ccol = nullptr;
@@ -572,7 +574,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         if (key == kEmpty) continue;
         const int hx = home(key);
         int rank = hcnt[hx];
-        if (hcnt[hx + 1] - rank > 1) {
+        if ((int)hcnt[hx + 1] - rank > 1) {
             for (int x = hx;; x = x + 1 == TX ? 0 : x + 1) {
                 const int kx = keys[x];
                 if (kx == kEmpty) break;

@@ -38,8 +38,10 @@ constexpr int kSymBins = 2 + kSClasses * kSymT;   // + empty + global
 constexpr int kNumBins = 2 + kSClasses * kNumT;
 constexpr int kSymGlobal = kSymBins - 1;
 constexpr int kNumGlobal = kNumBins - 1;
-constexpr int kTail = 32;
-constexpr int kBinBlocks = 4096;            // blocks of the binning kernels                    // numeric probe tail past the hashed range
+// numeric probe tail past the hashed range: short for small tables (space),
+// longer for large ones, whose runs near the end would otherwise wrap
+__host__ __device__ constexpr int num_tail(int T) { return T <= 256 ? 16 : 32; }
+constexpr int kBinBlocks = 4096;            // blocks of the binning kernels
 static_assert(kSymBins <= HCSP_MAX_BINS && kNumBins <= HCSP_MAX_BINS, "bin count");
 
 __host__ __device__ inline int num_table(int t)
