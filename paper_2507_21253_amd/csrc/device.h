@@ -10,6 +10,23 @@ namespace hcsp {
 constexpr int kWave = 64;
 constexpr int kEmpty = -1;
 
+// Values the whole wavefront agrees on, moved to scalar registers (the
+// first active lane's copy).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <class T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    return (T *)(uintptr_t)uniform64((uint64_t)(uintptr_t)p);
+}
+
 // A group of G consecutive lanes (G a power of two, 1 <= G <= 64) of one
 // wavefront that works on one row or cluster.  Groups never span waves, so
 // every group-level exchange is wave-local and needs no barrier.

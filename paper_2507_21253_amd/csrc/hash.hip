@@ -67,15 +67,6 @@ __device__ __forceinline__ int wave_incl_scan(int v)
     return v;
 }
 
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t v)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ __forceinline__ int64_t readlane_i64(int64_t v, int l)
 {
     const int lo = __builtin_amdgcn_readlane((int)v, l);
@@ -134,9 +125,9 @@ struct SymLayout {
     }
 };
 
-// The rank-ordered slot list of a cluster (2 bytes per slot) reuses the
-// item and start-bit area, which is free once the passes are done, when it
-// fits there.
+// The arrays of the final sweep (the per-home key counts and, for a cluster,
+// the rank-ordered slot list, 2 bytes per entry) reuse the item and start-bit
+// area, which is free once the passes are done, when they fit there.
 struct NumLayout {
     int keys, masks, vals, aval, order, items, sbits, hcnt, bytes;
     __host__ __device__ NumLayout(bool cl, int S, int T)
@@ -144,17 +135,20 @@ struct NumLayout {
         const int TX = T + num_tail(T);
         cl = cl && S > 1;
         const int mb = cl ? (S <= 8 ? 1 : 2) : 0;
-        const bool order_in_items = 2 * TX <= 16 * 64 + 8 * kRoundPasses;
         keys = 0;
         masks = keys + 4 * (TX + 1);
         vals = (masks + mask_region(mb, TX + 1) + 15) & ~15;
         aval = vals + 8 * S * (TX + 1);
         const int end = aval + (cl && !a_in_regs(S) ? 8 * S * 64 : 0);
-        items = (end + (cl && !order_in_items ? 2 * TX : 0) + 15) & ~15;
-        order = cl && order_in_items ? items : end;
+        items = (end + 15) & ~15;
         sbits = items + 16 * 64;
-        hcnt = sbits + 8 * kRoundPasses;
-        bytes = (hcnt + 2 * (T + 1) + 15) & ~15;  // 16-bit home counts
+        const int top = sbits + 8 * kRoundPasses;
+        const int ord_b = cl ? (2 * TX + 3) & ~3 : 0;
+        const int hc_b = 2 * (T + 1);  // 16-bit counts, read through aligned 32-bit words
+        const int at = ord_b + hc_b <= top - items ? items : top;
+        order = at;
+        hcnt = at + ord_b;
+        bytes = (at == items ? top : hcnt + hc_b + 15) & ~15;
     }
 };
 
@@ -251,7 +245,7 @@ struct Pass {
     int j;
     int t;        // item index (lanes past the end: the last item)
     uint32_t m;   // cluster: the item's row mask (symbolic)
-    double b, a;
+    double b;     // numeric: b_kj (a_ik is read per item when the products are applied)
 };
 
 template <bool MS, bool NUM, bool FULL = false>
@@ -273,7 +267,6 @@ __device__ __forceinline__ Pass<MS, NUM> fetch_pass(const SpArgs &a, const ItemR
     if (NUM) {
         const double b = ld_val(a.b_val, off);
         d.b = ok ? b : 0.0;
-        d.a = MS ? 0.0 : __longlong_as_double(((long long)it.y << 32) | it.x);
     }
     return d;
 }
@@ -406,7 +399,7 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
 // the unit's smallest and largest output column) with linear probing.
 // Because h never decreases with j, a key's rank among the unit's keys is
 // the number of keys whose home slot is lower (a prefix sum of per-home
-// counts kept while inserting) plus the smaller keys with the same home,
+// counts, taken once all keys are in) plus the smaller keys with the same home,
 // which all lie on the probe path from that home; no sort is needed, and a
 // CSR row's entries are written straight to their final positions.
 // PRED (CSR rows only): no symbolic phase ran; the table was sized from a
@@ -433,14 +426,14 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     ItemRec *items = (ItemRec *)(base + L.items);
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
     // per-home key counts, then their exclusive prefix (16 bits: a table holds
-    // fewer than 2^16 keys); counted through the aligned 32-bit words
+    // fewer than 2^16 keys); counted through the aligned 32-bit words once the
+    // passes are done (the array may share the item area)
     uint16_t *hcnt = (uint16_t *)(base + L.hcnt);
 
     const int VS = TX + 1;  // value column stride (slots incl. the dummy)
     const UnitView v = unit_view<CL>(a, u);
     for (int i = lane; i <= TX; i += 64) {
         keys[i] = i == TX ? kDummyKey : kEmpty;
-        if (i < T) hcnt[i] = 0;
         if (MS) masks[i] = 0;
 #pragma unroll
         for (int l = 0; l < S; ++l)
@@ -474,7 +467,6 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             if (++h == TX) h = 0;
             old = atomicCAS(&keys[h], kEmpty, j);
         }
-        if (old == kEmpty) atomicAdd((uint32_t *)(hcnt + (h0 & ~1)), 1u << (16 * (h0 & 1)));
         return h;
     };
     // products of one pass, applied item by item (ascending k)
@@ -494,7 +486,9 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
                     }
                 }
             } else {
-                vals[h] = __fma_rn(d.a, d.b, vals[h]);
+                // the item's a_ik (same address in every lane)
+                const double av = *(const double *)&items[tt].x;
+                vals[h] = __fma_rn(av, d.b, vals[h]);
             }
         }
     };
@@ -537,6 +531,14 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     // ---- rank every key.  h never decreases with j, so the keys smaller than
     // x are exactly those with a lower home slot plus the smaller ones sharing
     // x's home; the latter sit on x's probe path from that home on.
+    for (int i = lane; 2 * i < T; i += 64) ((uint32_t *)hcnt)[i] = 0u;  // T is even
+    for (int c0 = 0; c0 < TX; c0 += 64) {
+        const int sidx = c0 + lane;
+        const int key = sidx < TX ? keys[sidx] : kEmpty;
+        if (key == kEmpty) continue;
+        const int h0 = home(key);
+        atomicAdd((uint32_t *)(hcnt + (h0 & ~1)), 1u << (16 * (h0 & 1)));
+    }
     int U = 0;
     for (int c0 = 0; c0 < T; c0 += 64) {
         const int i = c0 + lane;
@@ -649,7 +651,7 @@ template <bool BATCH>
 __device__ __forceinline__ int gm_unit(SpArgs &a, const SpArgs &a0, int64_t i)
 {
     a = a0;
-    return BATCH ? batch_resolve(a, a0.order[i]) : a0.order[i];
+    return BATCH ? batch_resolve(a, a0.order[i]) : uniform(a0.order[i]);
 }
 
 // Symbolic: bits are set with atomic ORs that return nothing (no wait per
@@ -748,7 +750,7 @@ __global__ void __launch_bounds__(256) k_num_gm(SpArgs a0)
                     const Pass<CL, true> d = fetch_pass<CL, true>(a, items, w, cum, (p << 6) + lane, E, le);
                     cum += __popcll(w);
                     for (int tt = tf; tt <= tl; ++tt) {
-                        double av = d.a;
+                        double av = CL ? 0.0 : *(const double *)&items[tt].x;  // a_ik of the item
                         if (CL) {
                             if (!((uniform((int)items[tt].x) >> l) & 1)) continue;
                             av = aval[uniform((int)items[tt].y) * S + l];
@@ -836,7 +838,7 @@ __device__ __forceinline__ void run_bin(const SpArgs &a0)
     const int64_t lw = xcd_block() * wpb + wib;
     if (!BATCH) {
         if (lw >= a0.count) return;
-        const int u = a0.order[a0.bin_begin + lw];
+        const int u = uniform(a0.order[a0.bin_begin + lw]);
         if (NUM) num_unit<S, CL, PRED>(a0, u, base);
         else sym_unit<S, CL>(a0, u, base);
         return;
@@ -856,10 +858,11 @@ template <int S, bool CL, bool BATCH>
 __global__ void __launch_bounds__(256) k_sym(SpArgs a) { run_bin<S, CL, BATCH, false>(a); }
 
 // Wavefronts per SIMD the numeric kernels must allow (their register budget):
-// 7 (5 in batches) keeps narrow units at 72 (96) vector registers.
+// CSR rows 8 (64 vector registers), two-row clusters 7 (72); in batches,
+// whose unit arguments are resolved per unit, 6 (80).
 template <int S, bool BATCH>
 struct NumOcc {
-    static constexpr int W = S <= 2 ? (BATCH ? 5 : 7) : 1;
+    static constexpr int W = S == 1 && !BATCH ? 8 : S <= 2 ? (BATCH ? 6 : 7) : 1;
 };
 
 template <int S, bool CL, bool BATCH>

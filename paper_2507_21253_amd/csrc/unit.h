@@ -13,19 +13,21 @@ struct UnitView {
     int s;              // member rows
 };
 
+// Read by a whole wavefront for its (wave-uniform) unit u: every field is
+// moved to scalar registers.
 template <bool CL>
 __device__ __forceinline__ UnitView unit_view(const SpArgs &a, int u)
 {
     UnitView v;
     if (CL) {
-        v.it0 = a.cl_col_ptr[u];
-        v.it1 = a.cl_col_ptr[u + 1];
-        v.pos0 = a.cl_row_ptr[u];
-        v.s = (int)(a.cl_row_ptr[u + 1] - v.pos0);
-        v.vbase = a.cl_val_ptr[u];
+        v.it0 = (int64_t)uniform64((uint64_t)a.cl_col_ptr[u]);
+        v.it1 = (int64_t)uniform64((uint64_t)a.cl_col_ptr[u + 1]);
+        v.pos0 = (int64_t)uniform64((uint64_t)a.cl_row_ptr[u]);
+        v.s = uniform((int)(a.cl_row_ptr[u + 1] - v.pos0));
+        v.vbase = (int64_t)uniform64((uint64_t)a.cl_val_ptr[u]);
     } else {
-        v.it0 = a.a_rp[u];
-        v.it1 = a.a_rp[u + 1];
+        v.it0 = (int64_t)uniform64((uint64_t)a.a_rp[u]);
+        v.it1 = (int64_t)uniform64((uint64_t)a.a_rp[u + 1]);
         v.pos0 = u;
         v.s = 1;
         v.vbase = 0;
@@ -47,34 +49,39 @@ __device__ __forceinline__ int batch_find(const int64_t *bases, int nprob, int64
 }
 
 // Points the arguments at the product holding batch-wide unit g and returns
-// the unit's index inside that product.
+// the unit's index inside that product.  Called by a whole wavefront with a
+// wave-uniform g; the product's fields are moved to scalar registers.
 __device__ __forceinline__ int batch_resolve(SpArgs &a, int64_t g)
 {
-    const int p = batch_find(a.batch_units, a.nprob, g);
+    g = (int64_t)uniform64((uint64_t)g);
+    const int p = uniform(batch_find(a.batch_units, a.nprob, g));
     const BatchProb &bp = a.batch[p];
-    a.a_rp = bp.a_rp;
-    a.a_col = bp.a_col;
-    a.a_val = bp.a_val;
-    a.cl_row_ptr = bp.cl_row_ptr;
-    a.perm = bp.perm;
-    a.cl_col_ptr = bp.cl_col_ptr;
-    a.cl_col = bp.cl_col;
-    a.cl_mask = bp.cl_mask;
-    a.cl_val_ptr = bp.cl_val_ptr;
-    a.cl_val = bp.cl_val;
-    a.b_rp = bp.b_rp;
-    a.b_col = bp.b_col;
-    a.b_val = bp.b_val;
-    a.keylo += bp.unit_base;
-    a.keyhi += bp.unit_base;
-    a.ucount += bp.unit_base;
-    a.c_rp += bp.seg_base;
-    if (a.c_col) a.c_col += bp.out_base;
-    if (a.c_val) a.c_val += bp.out_base;
-    a.cap = bp.cap;
+    a.a_rp = uniform_ptr(bp.a_rp);
+    a.a_col = uniform_ptr(bp.a_col);
+    a.a_val = uniform_ptr(bp.a_val);
+    a.cl_row_ptr = uniform_ptr(bp.cl_row_ptr);
+    a.perm = uniform_ptr(bp.perm);
+    a.cl_col_ptr = uniform_ptr(bp.cl_col_ptr);
+    a.cl_col = uniform_ptr(bp.cl_col);
+    a.cl_mask = uniform_ptr(bp.cl_mask);
+    a.cl_val_ptr = uniform_ptr(bp.cl_val_ptr);
+    a.cl_val = uniform_ptr(bp.cl_val);
+    a.b_rp = uniform_ptr(bp.b_rp);
+    a.b_col = uniform_ptr(bp.b_col);
+    a.b_val = uniform_ptr(bp.b_val);
+    const int64_t ub = (int64_t)uniform64((uint64_t)bp.unit_base);
+    const int64_t sb = (int64_t)uniform64((uint64_t)bp.seg_base);
+    const int64_t ob = (int64_t)uniform64((uint64_t)bp.out_base);
+    a.keylo += ub;
+    a.keyhi += ub;
+    a.ucount += ub;
+    a.c_rp += sb;
+    if (a.c_col) a.c_col += ob;
+    if (a.c_val) a.c_val += ob;
+    a.cap = (int64_t)uniform64((uint64_t)bp.cap);
     a.err = a.errs + p;
-    a.ncols = bp.ncols;
-    return (int)(g - bp.unit_base);
+    a.ncols = (int64_t)uniform64((uint64_t)bp.ncols);
+    return (int)(g - ub);
 }
 
 template <bool CL>
