@@ -149,6 +149,8 @@ typedef struct hcsp_sym_info {
     int64_t num_bin_count[HCSP_MAX_BINS];
     int32_t lanes;                     /* lanes per group actually used */
     int32_t valid;                     /* set to 1 by hcsp_spgemm_symbolic */
+    int32_t load_pct;                  /* numeric table fill the bins were chosen for */
+    int32_t reserved;
 } hcsp_sym_info;
 
 /* -------------------------------------------------------------- library */

@@ -62,7 +62,8 @@ class c_opts(ctypes.Structure):
 
 class c_sym_info(ctypes.Structure):
     _fields_ = [("nnz", i64), ("units", i64), ("sym_bin_count", i64 * MAX_BINS),
-                ("num_bin_count", i64 * MAX_BINS), ("lanes", i32), ("valid", i32)]
+                ("num_bin_count", i64 * MAX_BINS), ("lanes", i32), ("valid", i32), ("load_pct", i32),
+                ("reserved", i32)]
 
 
 class c_batch_item(ctypes.Structure):

@@ -121,7 +121,7 @@ static void num_tmax_classes(const Tune &tu, bool cl, int out[kSClasses])
         int best = 0;
         for (int t = 0; t < kNumT; ++t) {
             const int T = num_table(t);
-            if (T <= tu.num_tmax && num_wave_bytes(cl, sc, T) <= tu.lds_budget) best = T;
+            if (T <= tu.num_tmax && num_wave_bytes(cl, sc, T, tu.load_pct) <= tu.lds_budget) best = T;
         }
         out[sc] = best;
     }
@@ -510,6 +510,7 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     info->units = v.nunits;
     for (int b = 0; b < kNumBins; ++b) info->num_bin_count[b] = ncnt[b];
     info->lanes = tu.G;
+    info->load_pct = tu.load_pct;
     info->valid = 1;
     return HCSP_OK;
 }
@@ -537,7 +538,8 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
     Tune tu;
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
-    if (tu.G != info->lanes) return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
+    if (tu.G != info->lanes || tu.load_pct != info->load_pct)
+        return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
     Workspace ws;
     const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, (char *)ws_d, &ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
@@ -570,7 +572,8 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                 const int sc = (b - 1) / kNumT;
                 const int t = (b - 1) % kNumT;
                 a.T = num_table(t);
-                const int64_t gb = num_wave_bytes(v.cluster, sc, a.T);
+                a.vcap = num_vcap(a.T, tu.load_pct);
+                const int64_t gb = num_wave_bytes(v.cluster, sc, a.T, tu.load_pct);
                 a.group_bytes = (int)gb;
                 int blocks, threads;
                 size_t lds;
@@ -725,7 +728,8 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
             a.bin_begin = start;
             a.count = c;
             a.T = num_table((b - 1) % kNumT);
-            const int64_t gb = num_wave_bytes(false, 0, a.T);
+            a.vcap = num_vcap(a.T, tu.load_pct);
+            const int64_t gb = num_wave_bytes(false, 0, a.T, tu.load_pct);
             a.group_bytes = (int)gb;
             int blocks, threads;
             size_t lds;
@@ -1022,7 +1026,8 @@ int hcsp_spgemm_batched(const hcsp_batch_plan *plan, int64_t *C_row_ptr_d, int32
             }
             a.bin = 1 + sc * kNumT + t;
             a.T = T;
-            const int64_t gb = num_wave_bytes(cl, sc, T);
+            a.vcap = num_vcap(T, tu.load_pct);
+            const int64_t gb = num_wave_bytes(cl, sc, T, tu.load_pct);
             a.group_bytes = (int)gb;
             int blocks, threads;
             size_t lds;

@@ -30,11 +30,11 @@
 
 namespace hcsp {
 
-// passes whose B loads are in flight together (fewer for wide clusters, whose
+// passes whose B loads are in flight together (fewer for clusters, whose
 // per-member updates need more registers)
 template <int S>
 struct Depth {
-    static constexpr int R = S >= 8 ? 2 : (S >= 4 ? 4 : 6);
+    static constexpr int R = S >= 8 ? 2 : (S >= 4 ? 4 : (S == 2 ? 5 : 6));
 };
 constexpr int kRoundW = 4096;               // products per round
 constexpr int kRoundPasses = kRoundW / 64;  // == 64: one start-bit word per lane
@@ -128,17 +128,23 @@ struct SymLayout {
 // The arrays of the final sweep (the per-home key counts and, for a cluster,
 // the rank-ordered slot list, 2 bytes per entry) reuse the item and start-bit
 // area, which is free once the passes are done, when they fit there.
+// A cluster of several rows keeps its member values (and masks) compactly:
+// one entry per distinct key, numbered in insertion order (at most vcap keys,
+// plus a dummy entry), found through a 16-bit index per slot.  A CSR row
+// keeps its value in the key's slot.
 struct NumLayout {
-    int keys, masks, vals, aval, order, items, sbits, hcnt, bytes;
-    __host__ __device__ NumLayout(bool cl, int S, int T)
+    int keys, vidx, masks, vals, aval, order, items, sbits, hcnt, bytes;
+    __host__ __device__ NumLayout(bool cl, int S, int T, int vcap)
     {
         const int TX = T + num_tail(T);
         cl = cl && S > 1;
         const int mb = cl ? (S <= 8 ? 1 : 2) : 0;
+        const int nv = cl ? vcap + 1 : TX + 1;  // value entries incl. the dummy
         keys = 0;
-        masks = keys + 4 * (TX + 1);
-        vals = (masks + mask_region(mb, TX + 1) + 15) & ~15;
-        aval = vals + 8 * S * (TX + 1);
+        vidx = keys + 4 * (TX + 1);
+        masks = vidx + (cl ? (2 * (TX + 1) + 3) & ~3 : 0);
+        vals = (masks + mask_region(mb, nv) + 15) & ~15;
+        aval = vals + 8 * S * nv;
         const int end = aval + (cl && !a_in_regs(S) ? 8 * S * 64 : 0);
         items = (end + 15) & ~15;
         sbits = items + 16 * 64;
@@ -153,7 +159,10 @@ struct NumLayout {
 };
 
 int64_t sym_wave_bytes(int mask_bytes, int T) { return SymLayout(mask_bytes, T).bytes; }
-int64_t num_wave_bytes(bool cl, int sclass, int T) { return NumLayout(cl, 1 << sclass, T).bytes; }
+int64_t num_wave_bytes(bool cl, int sclass, int T, int load_pct)
+{
+    return NumLayout(cl, 1 << sclass, T, num_vcap(T, load_pct)).bytes;
+}
 
 // ---------------------------------------------------------------- rounds
 // Loads the next round of items into LDS: lane i takes column q0+i of the
@@ -417,8 +426,9 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     if (u < a.unit_lo || u >= a.unit_hi) return;
 
     const int T = a.T, TX = a.T + num_tail(a.T);
-    const NumLayout L(MS, S, T);
+    const NumLayout L(MS, S, T, a.vcap);
     int *keys = (int *)(base + L.keys);
+    uint16_t *vidx = (uint16_t *)(base + L.vidx);  // MS: slot -> value entry
     MaskT<S> *masks = (MaskT<S> *)(base + L.masks);
     double *vals = (double *)(base + L.vals);
     double *aval = (double *)(base + L.aval);
@@ -430,15 +440,20 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     // passes are done (the array may share the item area)
     uint16_t *hcnt = (uint16_t *)(base + L.hcnt);
 
-    const int VS = TX + 1;  // value column stride (slots incl. the dummy)
+    // value column stride: entries incl. the dummy (MS: one per key, else one per slot)
+    const int VS = MS ? a.vcap + 1 : TX + 1;
     const UnitView v = unit_view<CL>(a, u);
     for (int i = lane; i <= TX; i += 64) {
         keys[i] = i == TX ? kDummyKey : kEmpty;
+        if (MS) vidx[i] = (uint16_t)a.vcap;  // the dummy entry until a key takes the slot
+    }
+    for (int i = lane; i < VS; i += 64) {
         if (MS) masks[i] = 0;
 #pragma unroll
         for (int l = 0; l < S; ++l)
             if (l < v.s) vals[l * VS + i] = 0.0;
     }
+    int nkeys = 0;  // MS: value entries handed out (wave-uniform)
     const int lo = a.keylo[u], hi = a.keyhi[u];
     const float scale = __fdividef((float)T, (float)(uint32_t)(hi - lo + 1));
     const uint64_t le = lanemask_le(lane);
@@ -453,7 +468,9 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         return h < T ? h : T - 1;
     };
     bool full = false;  // PRED: a key found no free slot
+    bool fresh = false;  // MS: this lane's last probe inserted its key
     auto probe = [&](int j, auto full_t) -> int {
+        fresh = false;
         if (!decltype(full_t)::value && j == kDummyKey) return TX;
         const int h0 = home(j);
         int h = h0;
@@ -467,7 +484,21 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             if (++h == TX) h = 0;
             old = atomicCAS(&keys[h], kEmpty, j);
         }
+        fresh = old == kEmpty;
         return h;
+    };
+    // MS: the value entry of slot h; keys inserted by this pass get the next
+    // entries in lane order.  A lane that found its key may read the entry
+    // another lane has just written: the fence keeps every write before every
+    // read (the compiler would otherwise be free to run the reading lanes'
+    // branch first).
+    auto entry = [&](int h) -> int {
+        if (!MS) return h;
+        const uint64_t fb = __ballot(fresh);
+        if (fresh) vidx[h] = (uint16_t)min(nkeys + __popcll(fb & lanemask_lt(lane)), a.vcap);
+        nkeys += __popcll(fb);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        return vidx[h];
     };
     // products of one pass, applied item by item (ascending k)
     auto apply = [&](const Pass<MS, true> &d, int h, int tf, int tl) {
@@ -511,7 +542,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
                 cum += __popcll(w);
             }
 #pragma unroll
-            for (int rr = 0; rr < kR; ++rr) apply(d[rr], probe(d[rr].j, full_t), tf[rr], tl[rr]);
+            for (int rr = 0; rr < kR; ++rr) apply(d[rr], entry(probe(d[rr].j, full_t)), tf[rr], tl[rr]);
         };
         for (; p + kR <= npass; p += kR) {
             if (((p + kR) << 6) <= E) batch(std::true_type{});
@@ -524,7 +555,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             const int tl = cum + __popcll(w & lanemask_le(last)) - 1;
             const Pass<MS, true> d = fetch_pass<MS, true>(a, items, w, cum, (p << 6) + lane, E, le);
             cum += __popcll(w);
-            apply(d, probe(d.j, std::false_type{}), tf, tl);
+            apply(d, entry(probe(d.j, std::false_type{})), tf, tl);
         }
     }
 
@@ -605,6 +636,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     }
 
     // ---- each member row's entries, in column order
+    if (lane == 0 && nkeys > a.vcap) atomicOr(a.err, kErrCount);  // more keys than the bin allows
     int64_t my_off = 0, my_want = 0;
     if (lane < v.s) {
         const int64_t row = member_row<CL>(a, v, lane);
@@ -617,14 +649,15 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         for (int c0 = 0; c0 < U; c0 += 64) {
             const int i = c0 + lane;
             const int sl = i < U ? (int)order[i] : TX;
-            const bool has = (masks[sl] >> l) & 1u && i < U;
+            const int id = vidx[sl];
+            const bool has = (masks[id] >> l) & 1u && i < U;
             const uint64_t bal = __ballot(has);
             if (has) {
                 const int64_t pos = w + __popcll(bal & lanemask_lt(lane));
                 const int64_t dst = roff + pos;
                 if (dst >= 0 && dst < a.cap && pos < rwant) {
                     a.c_col[dst] = keys[sl];
-                    a.c_val[dst] = vals[l * VS + sl];
+                    a.c_val[dst] = vals[l * VS + id];
                 } else {
                     atomicOr(a.err, kErrCapacity);
                 }

@@ -41,6 +41,9 @@ constexpr int kNumGlobal = kNumBins - 1;
 // numeric probe tail past the hashed range: short for small tables (space),
 // longer for large ones, whose runs near the end would otherwise wrap
 __host__ __device__ constexpr int num_tail(int T) { return T <= 256 ? 16 : 32; }
+// keys a numeric table of T slots holds at most: a unit goes to the smallest
+// table with U * 100 <= T * load_pct
+__host__ __device__ constexpr int num_vcap(int T, int load_pct) { return (int)((int64_t)T * load_pct / 100); }
 constexpr int kBinBlocks = 4096;            // blocks of the binning kernels
 static_assert(kSymBins <= HCSP_MAX_BINS && kNumBins <= HCSP_MAX_BINS, "bin count");
 
@@ -59,7 +62,7 @@ __host__ __device__ inline int sclass_of(int s)
 int64_t sym_wave_bytes(int mask_bytes, int T);  // mask bytes per slot: 0 for one-row units
 // mask bytes per slot of a member-count class (0: one row, 1: up to 8 rows, 2: 16)
 inline int mask_bytes_of_class(int sc) { return sc == 0 ? 0 : (sc <= 3 ? 1 : 2); }
-int64_t num_wave_bytes(bool cl, int sclass, int T);
+int64_t num_wave_bytes(bool cl, int sclass, int T, int load_pct);
 
 // Tuning derived from hcsp_opts.
 struct Tune {
@@ -151,6 +154,7 @@ struct SpArgs {
     uint32_t *err;
     // geometry
     int G, T, log2T, group_bytes;
+    int vcap;  // numeric, clusters of several rows: value entries per table (keys at most)
     // dense path
     uint32_t *dense_bits;
     double *dense_vals;
