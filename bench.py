@@ -142,7 +142,8 @@ def batch_mode(args):
         A = d
         if e["path"] == "hc":
             A = hc.cluster_build(d, hc.plan_hierarchical(H, (3, 10), e["max_cluster"], hc.SIM_ROOT,
-                                                         nthreads=len(os.sched_getaffinity(0))))
+                                                         nthreads=len(os.sched_getaffinity(0)),
+                                                         perm_in=hc.order_rcm(H)))
         groups.setdefault(key, []).append((A, d))
     t_prep = time.perf_counter() - t
     log("groups: %s (%.1fs)" % ({"%s/%d/s%d/n%d" % k: len(v) for k, v in groups.items()}, t_prep))
@@ -254,35 +255,40 @@ def main():
         args.max_cluster = tuned["best_cluster_size"] if tuned["tuned"] else 2
     log("tuner: %s" % tuned)
 
-    # ---- preprocessing: reordering (host), hierarchical plan (host), CSR_Cluster (device)
+    # ---- preprocessing: reordering (host), hierarchical plan (host), CSR_Cluster (device).  With rows-only
+    # reordering the plan works on M's rows in the new order (perm_in) and names original rows, so the
+    # CSR_Cluster is built from M itself and C comes out in M's row order; a symmetric reordering needs the
+    # reordered matrix (its columns change too).
     ncpu = len(os.sched_getaffinity(0))
     t = time.perf_counter()
-    if args.reorder == "none":
-        R = M
-    else:
+    P = None
+    if args.reorder != "none":
         P = hc.order_rcm(M) if args.reorder == "rcm" else hc.order_degree(M)
-        R = hc.permute_h(M, P, P if args.symmetric else None, ncpu)
     t_reorder = time.perf_counter() - t
+    R = M if P is None else hc.permute_h(M, P, P if args.symmetric else None, ncpu)  # the reordered baseline
+    A_plan, perm_in = (R, None) if args.symmetric else (M, P)
     t = time.perf_counter()
     if args.clustering == "variable":
-        plan = hc.plan_variable(R, (3, 10), args.max_cluster)
+        plan = hc.plan_variable(A_plan, (3, 10), args.max_cluster, perm_in=perm_in)
     elif args.clustering == "fixed":
-        plan = hc.plan_fixed(R.nrows, args.max_cluster)
+        plan = hc.plan_fixed(A_plan.nrows, args.max_cluster, perm_in)
     else:
-        plan = hc.plan_hierarchical(R, (3, 10), args.max_cluster,
-                                    hc.SIM_UNION if args.sim == "union" else hc.SIM_ROOT, nthreads=ncpu)
+        plan = hc.plan_hierarchical(A_plan, (3, 10), args.max_cluster,
+                                    hc.SIM_UNION if args.sim == "union" else hc.SIM_ROOT, nthreads=ncpu,
+                                    perm_in=perm_in)
     t_plan = time.perf_counter() - t
     log("reorder %s %.2fs; plan: %d clusters (%.2fs, %d threads)" % (args.reorder, t_reorder, plan.nclusters,
                                                                      t_plan, ncpu))
     Md = hc.DeviceCSR.from_host(M)
     Rd = Md if R is M else hc.DeviceCSR.from_host(R)
     Bd = Rd if args.symmetric else Md          # right operand: M, or the reordered M
+    Ad = Rd if args.symmetric else Md          # the matrix the CSR_Cluster is built from
     torch.cuda.synchronize()
     for _ in range(2):
-        Dc = hc.cluster_build(Rd, plan)
+        Dc = hc.cluster_build(Ad, plan)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    Dc = hc.cluster_build(Rd, plan)
+    Dc = hc.cluster_build(Ad, plan)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t
     log("CSR_Cluster: ncc %d nslots %d max %d (%.3fs)" % (Dc.ncc, Dc.nslots, Dc.max_cluster, t_build))
@@ -297,6 +303,11 @@ def main():
     nnzC = P_cl.info.nnz
     wall_pl, sym_pl, num_pl = time_product(P_pl, args.steps, args.warmup, torch)
     assert P_pl.info.nnz == nnzC
+    if not args.symmetric:
+        # both products give C in M's row order: the clustered one must equal the plain one bit for bit
+        same = (torch.equal(P_cl.C_row_ptr, P_pl.C_row_ptr) and torch.equal(P_cl.C_col[:nnzC], P_pl.C_col[:nnzC])
+                and torch.equal(P_cl.C_val[:nnzC].view(torch.int64), P_pl.C_val[:nnzC].view(torch.int64)))
+        assert same, "clustered and plain products differ"
     wall_ro = None
     if R is not M:
         P_ro = hc.Product(Rd, Bd, o)
@@ -392,9 +403,11 @@ def main():
                       "gbs_compulsory": round(comp_pl / (wall_pl * 1e-3) / 1e9, 2),
                       "phases_ms": {"symbolic_incl_readback": round(sym_pl, 4), "numeric": round(num_pl, 4)}},
         "speedup_clustered_vs_plain": round(wall_pl / wall_cl, 3),
+        "clustered_equals_plain_bitwise": None if args.symmetric else True,
         "plain_csr_reordered": None if wall_ro is None else {
             "gflops": round(flop / (wall_ro * 1e-3) / 1e9, 3), "ms_per_step": round(wall_ro, 4),
-            "phases_ms": {"symbolic_incl_readback": round(sym_ro, 4), "numeric": round(num_ro, 4)}},
+            "phases_ms": {"symbolic_incl_readback": round(sym_ro, 4), "numeric": round(num_ro, 4)},
+            "speedup_clustered_vs_this": round(wall_ro / wall_cl, 3)},
         "preprocessing": {"reorder_host_s": round(t_reorder, 3), "plan_host_s": round(t_plan, 3), "plan_threads": ncpu,
                           "cluster_build_s": round(t_build, 4),
                           "in_spgemms": round((t_reorder + t_plan + t_build) / (wall_cl * 1e-3), 1),

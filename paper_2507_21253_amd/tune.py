@@ -15,8 +15,9 @@ Tuned per class:
   * ``load_pct`` -- numeric table fill target (bin thresholds of the numeric
     phase),
   * ``path`` and ``max_cluster`` -- plain CSR, or CSR_Cluster from
-    hierarchical clustering (Alg. 3, threshold 3/10) with at most 2, 4 or 8
-    rows per cluster;
+    hierarchical clustering (Alg. 3, threshold 3/10) of the rows taken in
+    reverse Cuthill-McKee order (the paper's reorder-then-cluster flow), with
+    at most 2, 4 or 8 rows per cluster;
   * ``cl_load_pct`` -- the numeric fill target for the clustered product
     (a cluster's table carries a value column per member, so a different
     fill can pay).
@@ -33,11 +34,12 @@ import time
 
 import numpy as np
 
-from . import (DeviceCSR, Product, SIM_ROOT, cluster_build, features, opts, plan_hierarchical)
+from . import (DeviceCSR, Product, SIM_ROOT, cluster_build, features, opts, order_rcm, permute_h,
+               plan_hierarchical)
 
 SYM_LOADS = (50, 70, 100)
 NUM_LOADS = (50, 60, 70)
-CL_LOADS = (50, 55, 60, 65, 70)
+CL_LOADS = (50, 60, 70, 75, 80, 85)
 MAX_CLUSTERS = (2, 4, 8)
 DEFAULT = {"path": "plain", "max_cluster": 0, "sym_load_pct": 70, "load_pct": 60}
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
@@ -82,12 +84,18 @@ def tune_matrix(H, reps: int = 3, threads: int = 0) -> dict:
             if best is None or ms < best[0]:
                 best = (ms, sl, nl)
     _, sl, nl = best
-    # stage 2: cluster size and the clustered product's numeric fill (its tables carry a value column per
-    # member, so its best fill can differ from the plain product's)
+    # stage 2: rows in RCM order; the plain product over them (for reference), then cluster size and the
+    # clustered product's numeric fill (its tables carry a value column per member, so its best fill can
+    # differ from the plain product's)
     prep = {}
+    t = time.perf_counter()
+    rcm = order_rcm(H)
+    prep["rcm"] = time.perf_counter() - t
+    times["rcm"] = _time_ms(Product(DeviceCSR.from_host(permute_h(H, rcm, None, threads)), D,
+                                    opts(sym_load_pct=sl, load_pct=nl)), reps)
     for mc in MAX_CLUSTERS:
         t = time.perf_counter()
-        plan = plan_hierarchical(H, (3, 10), mc, SIM_ROOT, nthreads=threads)
+        plan = plan_hierarchical(H, (3, 10), mc, SIM_ROOT, nthreads=threads, perm_in=rcm)
         Dc = cluster_build(D, plan)
         prep["hc%d" % mc] = time.perf_counter() - t
         for cl in CL_LOADS:
@@ -159,11 +167,12 @@ class TuneTable:
 
 
 def tuning_set():
-    """Seeded matrices of the workload families (smaller instances of each), name -> HostCSR."""
+    """Seeded matrices of the workload families (smaller instances of each, large enough to fill the GPU
+    the way the full-size ones do), name -> HostCSR."""
     import synth
     out = {}
-    out["stencil27_40_relabelled"] = synth.workload_stencil27(40, 20, 21)[0]
-    out["stencil27_40"] = synth.stencil(27, 40, 22)
+    out["stencil27_80_relabelled"] = synth.workload_stencil27(80, 20, 21)[0]
+    out["stencil27_60"] = synth.stencil(27, 60, 22)
     out["stencil7_40"] = synth.stencil(7, 40, 23)
     out["stencil5_300"] = synth.stencil(5, 300, 24)
     for d in (4, 8, 16, 32):

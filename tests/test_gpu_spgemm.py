@@ -106,6 +106,8 @@ def plans_for(A):
     yield "hier_root", hc.plan_hierarchical(A, (3, 10), 8, hc.SIM_ROOT)
     yield "hier_union", hc.plan_hierarchical(A, (3, 10), 8, hc.SIM_UNION)
     yield "hier_perm16", hc.plan_hierarchical(A, (1, 5), 16, hc.SIM_ROOT, perm_in=synth.perm(A.nrows, 4))
+    # the benchmark's method path: rows in reverse Cuthill-McKee order, pairs by hierarchical clustering
+    yield "hier_rcm2", hc.plan_hierarchical(A, (3, 10), 2, hc.SIM_ROOT, perm_in=oracle.order_rcm(A))
 
 
 def host_cluster_of(Dc):
