@@ -242,11 +242,16 @@ static BinArgs bin_args(const hcsp_operand *A, const hcsp_csr *B, const Workspac
 // Launch geometry for one bin: one wavefront per unit, one to four per block,
 // whichever lets the most wavefronts share a compute unit's 160 KiB of LDS
 // (ties go to the larger block).
-static void geometry(int64_t wave_bytes, int64_t count, int *blocks, int *threads, size_t *lds)
+// Wavefronts per block: the most resident wavefronts per compute unit, ties
+// to the larger block; one wavefront per block (single) when units take
+// uneven time, so that a finished wavefront frees its shared memory at once
+// instead of when the slowest of its block ends.
+static void geometry(int64_t wave_bytes, int64_t count, int *blocks, int *threads, size_t *lds,
+                     bool single = false)
 {
     const int64_t cu_lds = 160 * 1024, wb = std::max<int64_t>(wave_bytes, 1);
     int64_t wpb = 1, best = -1;
-    for (int64_t w = 4; w >= 1; w >>= 1) {
+    for (int64_t w = single ? 1 : 4; w >= 1; w >>= 1) {
         const int64_t resident = std::min<int64_t>(32, cu_lds / (w * wb) * w);
         if (w * wb <= cu_lds && resident > best) {
             best = resident;
@@ -577,7 +582,7 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                 a.group_bytes = (int)gb;
                 int blocks, threads;
                 size_t lds;
-                geometry(gb, c, &blocks, &threads, &lds);
+                geometry(gb, c, &blocks, &threads, &lds, true);
                 rc = ensure_lds(lds, tu.lds_budget);
                 if (rc) return rc;
                 HCSP_HIP(launch_num(sc, v.cluster, false, a, blocks, threads, lds, s));
@@ -733,7 +738,7 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
             a.group_bytes = (int)gb;
             int blocks, threads;
             size_t lds;
-            geometry(gb, c, &blocks, &threads, &lds);
+            geometry(gb, c, &blocks, &threads, &lds, true);
             rc = ensure_lds(lds, tu.lds_budget);
             if (rc) return rc;
             HCSP_HIP(launch_num_pred(a, blocks, threads, lds, s));
