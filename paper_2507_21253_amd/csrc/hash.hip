@@ -125,15 +125,17 @@ struct SymLayout {
     }
 };
 
-// The arrays of the final sweep (the per-home key counts and, for a cluster,
-// the rank-ordered slot list, 2 bytes per entry) reuse the item and start-bit
-// area, which is free once the passes are done, when they fit there.
+// The arrays of the final sweep (an occupancy bitmap of the slots with a
+// prefix count per 64-slot word, the per-home key counts of the general
+// ranking and, for a cluster, the rank-ordered slot list, 2 bytes per entry)
+// reuse the item and start-bit area, which is free once the passes are done,
+// when they fit there.
 // A cluster of several rows keeps its member values (and masks) compactly:
 // one entry per distinct key, numbered in insertion order (at most vcap keys,
 // plus a dummy entry), found through a 16-bit index per slot.  A CSR row
 // keeps its value in the key's slot.
 struct NumLayout {
-    int keys, vidx, masks, vals, aval, order, items, sbits, hcnt, bytes;
+    int keys, vidx, masks, vals, aval, order, items, sbits, hcnt, obits, opre, bytes;
     __host__ __device__ NumLayout(bool cl, int S, int T, int vcap)
     {
         const int TX = T + num_tail(T);
@@ -149,12 +151,16 @@ struct NumLayout {
         items = (end + 15) & ~15;
         sbits = items + 16 * 64;
         const int top = sbits + 8 * kRoundPasses;
+        const int nw = (TX + 63) >> 6;
         const int ord_b = cl ? (2 * TX + 3) & ~3 : 0;
         const int hc_b = 2 * (T + 1);  // 16-bit counts, read through aligned 32-bit words
-        const int at = ord_b + hc_b <= top - items ? items : top;
-        order = at;
-        hcnt = at + ord_b;
-        bytes = (at == items ? top : hcnt + hc_b + 15) & ~15;
+        const int need = 12 * nw + ord_b + hc_b;
+        const int at = need <= top - items ? items : top;
+        obits = at;
+        opre = at + 8 * nw;
+        order = opre + 4 * nw;
+        hcnt = order + ord_b;
+        bytes = (at == items ? top : at + need + 15) & ~15;
     }
 };
 
@@ -559,26 +565,50 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         }
     }
 
-    // ---- rank every key.  h never decreases with j, so the keys smaller than
-    // x are exactly those with a lower home slot plus the smaller ones sharing
-    // x's home; the latter sit on x's probe path from that home on.
-    for (int i = lane; 2 * i < T; i += 64) ((uint32_t *)hcnt)[i] = 0u;  // T is even
+    // ---- rank every key.  h never decreases with j, so a key x with home hx
+    // is larger than every key homed below hx and smaller than every key homed
+    // above it.  With linear probing every slot from a key's home to the key
+    // is occupied, and a key stored below hx is homed below hx.  Hence, when
+    // no probe run reaches the table's last slot (no run wrapped around):
+    //   rank(x) = (occupied slots below hx) + (keys smaller than x from hx up
+    //             to the end of the run),
+    // the first term from an occupancy bitmap.  Otherwise (and for predicted
+    // tables, which may fill up) the general form: keys homed below hx (a
+    // prefix sum of per-home counts) plus the smaller keys sharing hx, which
+    // lie on the probe path from hx.
+    uint64_t *obits = (uint64_t *)(base + L.obits);
+    int *opre = (int *)(base + L.opre);
+    int U = 0;
     for (int c0 = 0; c0 < TX; c0 += 64) {
         const int sidx = c0 + lane;
-        const int key = sidx < TX ? keys[sidx] : kEmpty;
-        if (key == kEmpty) continue;
-        const int h0 = home(key);
-        atomicAdd((uint32_t *)(hcnt + (h0 & ~1)), 1u << (16 * (h0 & 1)));
+        const uint64_t occ = __ballot(sidx < TX && keys[sidx] != kEmpty);
+        if (lane == 0) {
+            obits[c0 >> 6] = occ;
+            opre[c0 >> 6] = U;
+        }
+        U += __popcll(occ);
     }
-    int U = 0;
-    for (int c0 = 0; c0 < T; c0 += 64) {
-        const int i = c0 + lane;
-        const int cnt = i < T ? hcnt[i] : 0;
-        const int incl = wave_incl_scan(cnt);
-        if (i < T) hcnt[i] = (uint16_t)(U + incl - cnt);
-        U += __shfl(incl, 63);
+    const bool runs_end = PRED || uniform(keys[TX - 1]) != kEmpty;
+    if (runs_end) {
+        for (int i = lane; 2 * i < T; i += 64) ((uint32_t *)hcnt)[i] = 0u;  // T is even
+        for (int c0 = 0; c0 < TX; c0 += 64) {
+            const int sidx = c0 + lane;
+            const int key = sidx < TX ? keys[sidx] : kEmpty;
+            if (key == kEmpty) continue;
+            const int h0 = home(key);
+            atomicAdd((uint32_t *)(hcnt + (h0 & ~1)), 1u << (16 * (h0 & 1)));
+        }
+        int V = 0;
+        for (int c0 = 0; c0 < T; c0 += 64) {
+            const int i = c0 + lane;
+            const int cnt = i < T ? hcnt[i] : 0;
+            const int incl = wave_incl_scan(cnt);
+            if (i < T) hcnt[i] = (uint16_t)(V + incl - cnt);
+            V += __shfl(incl, 63);
+        }
+        if (lane == 0) hcnt[T] = (uint16_t)V;
     }
-    if (lane == 0) hcnt[T] = (uint16_t)U;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     int64_t o0 = 0, want = 0;
     const int64_t row0 = member_row<CL>(a, v, 0);
     int32_t *ccol = nullptr;
@@ -606,12 +636,22 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         const int key = sidx < TX ? keys[sidx] : kEmpty;
         if (key == kEmpty) continue;
         const int hx = home(key);
-        int rank = hcnt[hx];
-        if ((int)hcnt[hx + 1] - rank > 1) {
-            for (int x = hx;; x = x + 1 == TX ? 0 : x + 1) {
+        int rank;
+        if (!runs_end) {
+            rank = opre[hx >> 6] + __popcll(obits[hx >> 6] & lanemask_lt(hx & 63));
+            for (int x = hx;; ++x) {  // ends at an empty slot below TX - 1
                 const int kx = keys[x];
                 if (kx == kEmpty) break;
-                rank += kx < key && home(kx) == hx;
+                rank += kx < key;
+            }
+        } else {
+            rank = hcnt[hx];
+            if ((int)hcnt[hx + 1] - rank > 1) {
+                for (int x = hx;; x = x + 1 == TX ? 0 : x + 1) {
+                    const int kx = keys[x];
+                    if (kx == kEmpty) break;
+                    rank += kx < key && home(kx) == hx;
+                }
             }
         }
         if (MS) {
