@@ -241,3 +241,31 @@ def test_run_twice_bitwise_identical():
     C1 = P.run().to_host()
     C2 = P.run().to_host()
     assert_same(C1, C2)
+
+
+def _clumped_case(n=300, seed=11):
+    """Output rows whose columns crowd at the top of their range: the order-preserving numeric hash sends
+    them all to the last home slots, so probe runs pass the end of the table and wrap around (the general
+    ranking), next to rows that do not wrap (the occupancy-bitmap ranking)."""
+    rng = np.random.default_rng(seed)
+    brows = [np.array([0]), np.arange(10000, 10100), np.arange(20000, 20150),
+             np.concatenate([[5000], np.arange(29990, 30000)]), np.sort(rng.choice(30000, 120, replace=False))]
+    bvals = [rng.uniform(-1, 1, len(c)) for c in brows]
+    B = synth.HostCSR(np.concatenate([[0], np.cumsum([len(c) for c in brows])]).astype(np.int64),
+                      np.concatenate(brows).astype(np.int32), np.concatenate(bvals), len(brows), 30000)
+    acols = [np.array(sorted({0, 1 + i % 4} | ({4} if i % 5 == 0 else set()))) for i in range(n)]
+    A = synth.HostCSR(np.concatenate([[0], np.cumsum([len(c) for c in acols])]).astype(np.int64),
+                      np.concatenate(acols).astype(np.int32), rng.uniform(-1, 1, sum(len(c) for c in acols)),
+                      n, len(brows))
+    return A, B
+
+
+@pytest.mark.parametrize("load", [50, 60, 90])
+def test_wrapped_probe_runs_bitwise(load):
+    A, B = _clumped_case()
+    ref = oracle.spgemm(A, B)
+    Ad, Bd = to_dev(A), to_dev(B)
+    assert_same(gpu_product(Ad, Bd, hc.opts(load_pct=load)), ref, "csr load %d" % load)
+    for K in (2, 3):
+        Dc = hc.cluster_build(Ad, hc.plan_fixed(A.nrows, K))
+        assert_same(gpu_product(Dc, Bd, hc.opts(load_pct=load)), ref, "clusters of %d, load %d" % (K, load))
