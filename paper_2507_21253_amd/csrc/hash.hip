@@ -572,10 +572,11 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     // no probe run reaches the table's last slot (no run wrapped around):
     //   rank(x) = (occupied slots below hx) + (keys smaller than x from hx up
     //             to the end of the run),
-    // the first term from an occupancy bitmap.  Otherwise (and for predicted
-    // tables, which may fill up) the general form: keys homed below hx (a
-    // prefix sum of per-home counts) plus the smaller keys sharing hx, which
-    // lie on the probe path from hx.
+    // the first term from an occupancy bitmap.  Otherwise the general form:
+    // keys homed below hx (a prefix sum of per-home counts) plus the smaller
+    // keys sharing hx, which lie on the probe path from hx.  (A predicted
+    // table that filled up, or holds more keys than the row's capacity, is
+    // given up before ranking.)
     uint64_t *obits = (uint64_t *)(base + L.obits);
     int *opre = (int *)(base + L.opre);
     int U = 0;
@@ -588,7 +589,12 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         }
         U += __popcll(occ);
     }
-    const bool runs_end = PRED || uniform(keys[TX - 1]) != kEmpty;
+    const int64_t row0 = member_row<CL>(a, v, 0);
+    if (PRED && (__ballot(full) != 0ull || U > a.ucount[u])) {
+        if (lane == 0) a.c_rp[row0] = -1;
+        return;
+    }
+    const bool runs_end = uniform(keys[TX - 1]) != kEmpty;
     if (runs_end) {
         for (int i = lane; 2 * i < T; i += 64) ((uint32_t *)hcnt)[i] = 0u;  // T is even
         for (int c0 = 0; c0 < TX; c0 += 64) {
@@ -610,14 +616,9 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     int64_t o0 = 0, want = 0;
-    const int64_t row0 = member_row<CL>(a, v, 0);
     int32_t *ccol = nullptr;
     double *cval = nullptr;
     if (PRED) {
-        if (__ballot(full) != 0ull || U > a.ucount[u]) {
-            if (lane == 0) a.c_rp[row0] = -1;
-            return;
-        }
         o0 = a.pad_off[row0];
         want = U;
     } else if (!MS) {
