@@ -8,8 +8,10 @@ small network does it from the library's 32 structure features:
       ``plain``     row-wise product in the given order,
       ``rcm``       rows of A reordered by reverse Cuthill-McKee first
                     (Sec. "Matrix Reordering"), B unchanged,
-      ``hc2``       CSR_Cluster from hierarchical clustering (Alg. 3,
-                    threshold 3/10, at most 2 rows per cluster),
+      ``rcm_hc2``   CSR_Cluster from hierarchical clustering (Alg. 3,
+                    threshold 3/10, at most 2 rows per cluster) of the rows
+                    taken in reverse Cuthill-McKee order (reorder, then
+                    cluster),
       ``variable``  CSR_Cluster from variable-length clustering (Alg. 2,
                     threshold 3/10, at most 8 rows) in the given order;
     the label is the path with the least time per product once its
@@ -35,7 +37,7 @@ import numpy as np
 from . import (DeviceCSR, MLP_NACT, MLP_NDELTA, MLP_NPARAMS, Product, SIM_ROOT, cluster_build, features,
                mlp_adam, mlp_backward, mlp_forward, order_rcm, permute_h, plan_hierarchical, plan_variable)
 
-PATHS = ("plain", "rcm", "hc2", "variable")
+PATHS = ("plain", "rcm", "rcm_hc2", "variable")
 HORIZON = 1000
 NIN, NH, NOUT = 32, 64, 5
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "learned_set.npz")
@@ -67,16 +69,19 @@ def label(H, reps: int = 3, threads: int = 0) -> dict:
     nnz = int(P.info.nnz)
     del P
     t = time.perf_counter()
-    R = permute_h(H, order_rcm(H), None, threads)
+    rcm = order_rcm(H)
+    t_order = time.perf_counter() - t
+    R = permute_h(H, rcm, None, threads)
     prep["rcm"] = time.perf_counter() - t
     Rd = DeviceCSR.from_host(R)
     times["rcm"] = _time_ms(Product(Rd, D), reps)
     del Rd
-    for name, mk in (("hc2", lambda: plan_hierarchical(H, (3, 10), 2, SIM_ROOT, nthreads=threads)),
-                     ("variable", lambda: plan_variable(H, (3, 10), 8))):
+    for name, mk, base in (("rcm_hc2", lambda: plan_hierarchical(H, (3, 10), 2, SIM_ROOT, nthreads=threads,
+                                                                 perm_in=rcm), t_order),
+                           ("variable", lambda: plan_variable(H, (3, 10), 8), 0.0)):
         t = time.perf_counter()
         Dc = cluster_build(D, mk())
-        prep[name] = time.perf_counter() - t
+        prep[name] = base + time.perf_counter() - t
         times[name] = _time_ms(Product(Dc, D), reps)
         del Dc
     rl = np.diff(H.rp)
@@ -113,7 +118,7 @@ def gen(lo: int, hi: int, out: str, reps: int = 3):
         print("%d %-24s n=%7d best=%-8s %s (%.0fs)" % (s, name, H.nrows, PATHS[int(np.argmin(costs(r["times"], r["prep"])))],
                                                      " ".join("%.3f" % x for x in r["times"]), time.perf_counter() - t0),
               flush=True)
-    np.savez(out, seed=np.array(rows["seed"], np.int64), name=np.array(rows["name"]),
+    np.savez_compressed(out, seed=np.array(rows["seed"], np.int64), name=np.array(rows["name"]),
              features=np.array(rows["features"], np.float32), times=np.array(rows["times"]),
              prep=np.array(rows["prep"]), nnz=np.array(rows["nnz"], np.int64),
              products=np.array(rows["products"], np.int64), nrows=np.array(rows["nrows"], np.int64))

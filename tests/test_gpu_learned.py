@@ -110,7 +110,7 @@ def test_selector_gains_on_held_out_matrices():
     print(ev)
     # no worse than always clustering (the method without the network), and never worse than 5% above
     # the per-matrix best
-    assert ev["selector_ms"] <= ev["always_hc2_ms"]
+    assert ev["selector_ms"] <= ev["always_rcm_hc2_ms"]
     assert ev["selector_ms"] <= ev["always_variable_ms"]
     assert ev["selector_ms"] <= 1.05 * ev["best_ms"]
     assert ev["log_ratio_abs_err_median"] < 0.25
