@@ -87,6 +87,82 @@ static int64_t lds_limit()
     return cache[dev];
 }
 
+// Side streams for the bins of a phase.  The bin with the most work runs on
+// the caller's stream, the others on side streams forked from it and joined
+// back before the phase's next step, so that the few long units of a small
+// bin overlap the large bin instead of running alone after it.  Created once
+// per device (default priority, non-blocking); where they cannot be created
+// every bin runs on the caller's stream.  The lock keeps one call's fork and
+// join events from being re-recorded by another host thread in between.
+constexpr int kSide = 3;
+struct SideStreams {
+    hipStream_t st[kSide];
+    hipEvent_t fork, join[kSide];
+    bool ok;
+};
+
+static std::mutex g_side_mu;
+
+static SideStreams *side_streams()
+{
+    static SideStreams cache[64];
+    static bool tried[64] = {false};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    SideStreams &x = cache[dev];
+    if (!tried[dev]) {
+        tried[dev] = true;
+        x.ok = hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; i < kSide && x.ok; ++i)
+            x.ok = hipStreamCreateWithFlags(&x.st[i], hipStreamNonBlocking) == hipSuccess &&
+                   hipEventCreateWithFlags(&x.join[i], hipEventDisableTiming) == hipSuccess;
+    }
+    return x.ok ? &x : nullptr;
+}
+
+// Runs launch(b, stream) for every bin b with work[b] > 0: the largest on s
+// (last), the others on the side streams (first).  The side streams are
+// joined back into s also when a launch fails; returns the first error.
+template <class F>
+static int run_bins(hipStream_t s, const std::vector<int64_t> &work, F launch)
+{
+    int big = -1, nb = 0;
+    for (int b = 0; b < (int)work.size(); ++b) {
+        if (work[b] <= 0) continue;
+        ++nb;
+        if (big < 0 || work[b] > work[big]) big = b;
+    }
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideStreams *x = nb > 1 ? side_streams() : nullptr;
+    if (x && hipEventRecord(x->fork, s) != hipSuccess) x = nullptr;
+    bool used[kSide] = {false, false, false};
+    int k = 0, rc = HCSP_OK;
+    for (int b = 0; b < (int)work.size() && rc == HCSP_OK; ++b) {
+        if (work[b] <= 0 || b == big) continue;
+        hipStream_t t = s;
+        if (x) {
+            const int i = k++ % kSide;
+            if (!used[i]) {
+                if (hipStreamWaitEvent(x->st[i], x->fork, 0) != hipSuccess) {
+                    rc = fail(HCSP_E_HIP, "hipStreamWaitEvent failed");
+                    break;
+                }
+                used[i] = true;
+            }
+            t = x->st[i];
+        }
+        rc = launch(b, t);
+    }
+    if (rc == HCSP_OK && big >= 0) rc = launch(big, s);
+    for (int i = 0; i < kSide; ++i) {
+        if (!used[i]) continue;
+        if ((hipEventRecord(x->join[i], x->st[i]) != hipSuccess || hipStreamWaitEvent(s, x->join[i], 0) != hipSuccess) &&
+            rc == HCSP_OK)
+            rc = fail(HCSP_E_HIP, "joining a side stream failed");
+    }
+    return rc;
+}
+
 static int make_tune(const hcsp_opts *o, const hcsp_csr *B, bool need_device, Tune *t)
 {
     hcsp_opts z;
@@ -475,34 +551,40 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     SpArgs a = base_args(A, B, ws, tu);
     a.order = ws.order_sym;
     a.c_rp = C_row_ptr_d;
+    std::vector<int64_t> begin(kSymBins), work(kSymBins, 0);
     int64_t start = 0;
     for (int b = 0; b < kSymBins; ++b) {
-        const int64_t c = cnt[b];
-        info->sym_bin_count[b] = c;
-        if (c > 0 && b != kBinEmpty) {
-            a.bin_begin = start;
-            a.count = c;
-            if (b == kSymGlobal) {
-                const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
-                HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, s));
-                HCSP_HIP(launch_sym_dense(v.cluster, false, a, waves / 4, s));
-            } else {
-                const int sc = (b - 1) / kSymT;
-                const int l2 = (b - 1) % kSymT + kSymLog2Min;
-                a.T = 1 << l2;
-                a.log2T = l2;
-                const int64_t gb = sym_wave_bytes(v.cluster ? mask_bytes_of_class(sc) : 0, a.T);
-                a.group_bytes = (int)gb;
-                int blocks, threads;
-                size_t lds;
-                geometry(gb, c, &blocks, &threads, &lds);
-                rc = ensure_lds(lds, tu.lds_budget);
-                if (rc) return rc;
-                HCSP_HIP(launch_sym(sc, v.cluster, false, a, blocks, threads, lds, s));
-            }
-        }
-        start += c;
+        info->sym_bin_count[b] = cnt[b];
+        begin[b] = start;
+        start += cnt[b];
+        if (cnt[b] > 0 && b != kBinEmpty)
+            work[b] = b == kSymGlobal ? INT64_MAX / 2 : cnt[b] << ((b - 1) % kSymT + kSymLog2Min);
     }
+    rc = run_bins(s, work, [&](int b, hipStream_t t) -> int {
+        const int64_t c = cnt[b];
+        a.bin_begin = begin[b];
+        a.count = c;
+        if (b == kSymGlobal) {
+            const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
+            HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, t));
+            HCSP_HIP(launch_sym_dense(v.cluster, false, a, waves / 4, t));
+            return HCSP_OK;
+        }
+        const int sc = (b - 1) / kSymT;
+        const int l2 = (b - 1) % kSymT + kSymLog2Min;
+        a.T = 1 << l2;
+        a.log2T = l2;
+        const int64_t gb = sym_wave_bytes(v.cluster ? mask_bytes_of_class(sc) : 0, a.T);
+        a.group_bytes = (int)gb;
+        int blocks, threads;
+        size_t lds;
+        geometry(gb, c, &blocks, &threads, &lds);
+        const int e = ensure_lds(lds, tu.lds_budget);
+        if (e) return e;
+        HCSP_HIP(launch_sym(sc, v.cluster, false, a, blocks, threads, lds, t));
+        return HCSP_OK;
+    });
+    if (rc) return rc;
     HCSP_HIP(launch_scan_exclusive(C_row_ptr_d, v.nrows + 1, ws.scan_tmp, s));
     HCSP_HIP(launch_numbin(v.cluster, ba, s));
     HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.bin_hist, kNumBins, ws.num_count, ws.order_num, s));
@@ -563,33 +645,39 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
     a.out_base = o->out_base;
     a.unit_lo = o->unit_lo;
     a.unit_hi = o->unit_hi > 0 ? o->unit_hi : INT64_MAX;
+    std::vector<int64_t> begin(kNumBins), work(kNumBins, 0);
     int64_t start = 0;
     for (int b = 0; b < kNumBins; ++b) {
         const int64_t c = info->num_bin_count[b];
-        if (c > 0 && b != kBinEmpty) {
-            a.bin_begin = start;
-            a.count = c;
-            if (b == kNumGlobal) {
-                const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
-                HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, s));
-                HCSP_HIP(launch_num_dense(v.cluster, false, a, waves / 4, s));
-            } else {
-                const int sc = (b - 1) / kNumT;
-                const int t = (b - 1) % kNumT;
-                a.T = num_table(t);
-                a.vcap = num_vcap(a.T, tu.load_pct);
-                const int64_t gb = num_wave_bytes(v.cluster, sc, a.T, tu.load_pct);
-                a.group_bytes = (int)gb;
-                int blocks, threads;
-                size_t lds;
-                geometry(gb, c, &blocks, &threads, &lds, true);
-                rc = ensure_lds(lds, tu.lds_budget);
-                if (rc) return rc;
-                HCSP_HIP(launch_num(sc, v.cluster, false, a, blocks, threads, lds, s));
-            }
-        }
+        begin[b] = start;
         start += c;
+        if (c > 0 && b != kBinEmpty) work[b] = b == kNumGlobal ? INT64_MAX / 2 : c * num_table((b - 1) % kNumT);
     }
+    rc = run_bins(s, work, [&](int b, hipStream_t st) -> int {
+        const int64_t c = info->num_bin_count[b];
+        a.bin_begin = begin[b];
+        a.count = c;
+        if (b == kNumGlobal) {
+            const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
+            HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, st));
+            HCSP_HIP(launch_num_dense(v.cluster, false, a, waves / 4, st));
+            return HCSP_OK;
+        }
+        const int sc = (b - 1) / kNumT;
+        const int t = (b - 1) % kNumT;
+        a.T = num_table(t);
+        a.vcap = num_vcap(a.T, tu.load_pct);
+        const int64_t gb = num_wave_bytes(v.cluster, sc, a.T, tu.load_pct);
+        a.group_bytes = (int)gb;
+        int blocks, threads;
+        size_t lds;
+        geometry(gb, c, &blocks, &threads, &lds, true);
+        const int e = ensure_lds(lds, tu.lds_budget);
+        if (e) return e;
+        HCSP_HIP(launch_num(sc, v.cluster, false, a, blocks, threads, lds, st));
+        return HCSP_OK;
+    });
+    if (rc) return rc;
     if (o->flags & HCSP_F_SYNC_CHECK) {
         uint32_t e = 0;
         HCSP_HIP(hipMemcpyAsync(&e, ws.err, 4, hipMemcpyDeviceToHost, s));
