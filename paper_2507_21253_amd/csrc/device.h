@@ -21,10 +21,22 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Pointers to global memory (device buffers the caller passed in) that were
+// read from memory: marked as global-address-space pointers, so loads through
+// them are global loads instead of generic ones.
+template <class T>
+__device__ __forceinline__ T *global_ptr(T *p)
+{
+    typedef __attribute__((address_space(1))) T GT;
+    return (T *)(GT *)(uintptr_t)p;
+}
+
+// The same for a wave-uniform pointer, moved to scalar registers.
 template <class T>
 __device__ __forceinline__ T *uniform_ptr(T *p)
 {
-    return (T *)(uintptr_t)uniform64((uint64_t)(uintptr_t)p);
+    typedef __attribute__((address_space(1))) T GT;
+    return (T *)(GT *)(uintptr_t)uniform64((uint64_t)(uintptr_t)p);
 }
 
 // A group of G consecutive lanes (G a power of two, 1 <= G <= 64) of one

@@ -101,12 +101,16 @@ using MaskT = typename std::conditional<(S <= 8), uint8_t, uint16_t>::type;
 
 // Atomic OR of m into the mask of slot h (through the aligned 32-bit word
 // that holds it); returns the mask before.
+// The word is found by pointer arithmetic from the (4-byte aligned) mask
+// array, never through an integer, so the compiler keeps the access in shared
+// memory (a DS atomic rather than a generic one that also waits for every
+// outstanding global load).
 template <int S>
 __device__ __forceinline__ uint32_t mask_or(MaskT<S> *masks, uint32_t h, uint32_t m)
 {
-    const uintptr_t p = (uintptr_t)(masks + h);
-    const int sh = 8 * (int)(p & 3u);
-    const uint32_t old = atomicOr((uint32_t *)(p & ~(uintptr_t)3), m << sh);
+    const uint32_t byte = h * (uint32_t)sizeof(MaskT<S>);
+    const int sh = 8 * (int)(byte & 3u);
+    const uint32_t old = atomicOr(reinterpret_cast<uint32_t *>(masks) + (byte >> 2), m << sh);
     return (old >> sh) & (S <= 8 ? 0xffu : 0xffffu);
 }
 

@@ -86,12 +86,12 @@ __device__ __forceinline__ WorkView work_view(const BinArgs &a, int64_t g)
     if (BATCH) {
         const int p = batch_find(a.batch_units, a.nprob, g);
         const BatchProb &bp = a.batch[p];
-        a_rp = bp.a_rp;
-        cl_row_ptr = bp.cl_row_ptr;
-        cl_col_ptr = bp.cl_col_ptr;
-        w.b_rp = bp.b_rp;
-        w.col = CL ? bp.cl_col : bp.a_col;
-        w.perm = bp.perm;
+        a_rp = global_ptr(bp.a_rp);
+        cl_row_ptr = global_ptr(bp.cl_row_ptr);
+        cl_col_ptr = global_ptr(bp.cl_col_ptr);
+        w.b_rp = global_ptr(bp.b_rp);
+        w.col = global_ptr(CL ? bp.cl_col : bp.a_col);
+        w.perm = global_ptr(bp.perm);
         w.c_rp = a.c_rp + bp.seg_base;
         w.u = g - bp.unit_base;
     }
@@ -405,12 +405,16 @@ template <bool CL>
 __global__ void __launch_bounds__(256) k_batch_bound(const BatchProb *batch, int64_t *ub)
 {
     const BatchProb &bp = batch[blockIdx.x];
-    const int64_t n = CL ? (bp.nunits > 0 ? bp.cl_col_ptr[bp.nunits] : 0) : (bp.nrows > 0 ? bp.a_rp[bp.nrows] : 0);
+    const int64_t *b_rp = global_ptr(bp.b_rp);
+    const int32_t *col = global_ptr(CL ? bp.cl_col : bp.a_col);
+    const uint16_t *mask = global_ptr(bp.cl_mask);
+    const int64_t n = CL ? (bp.nunits > 0 ? global_ptr(bp.cl_col_ptr)[bp.nunits] : 0)
+                         : (bp.nrows > 0 ? global_ptr(bp.a_rp)[bp.nrows] : 0);
     int64_t s = 0;
     for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.y * blockDim.x) {
-        const int k = CL ? bp.cl_col[q] : bp.a_col[q];
-        const int64_t len = bp.b_rp[k + 1] - bp.b_rp[k];
-        s += CL ? len * __popc((uint32_t)bp.cl_mask[q]) : len;
+        const int k = col[q];
+        const int64_t len = b_rp[k + 1] - b_rp[k];
+        s += CL ? len * __popc((uint32_t)mask[q]) : len;
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ub[blockIdx.x], (unsigned long long)s);
