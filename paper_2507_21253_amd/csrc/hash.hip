@@ -114,16 +114,30 @@ __device__ __forceinline__ uint32_t mask_or(MaskT<S> *masks, uint32_t h, uint32_
     return (old >> sh) & (S <= 8 ? 0xffu : 0xffffu);
 }
 
+// Fills n bytes (rounded up to 16; the region is padded to 16) at a
+// 16-byte aligned shared-memory address with a 4-byte pattern, 16 bytes per
+// lane and store.
+__device__ __forceinline__ void lds_fill(void *p, int n, uint32_t w)
+{
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+    const uint4 v = make_uint4(w, w, w, w);
+    for (int i = (int)__lane_id(); 16 * i < n; i += 64) q[i] = v;
+}
+
 // sizes of the cluster mask region (rounded to whole 32-bit words)
 __host__ __device__ constexpr int mask_region(int mb, int slots) { return (mb * slots + 3) & ~3; }
+
+// Regions start on 16-byte boundaries so that they are cleared with 16-byte
+// stores.
+__host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
 
 struct SymLayout {
     int keys, masks, items, sbits, bytes;
     __host__ __device__ SymLayout(int mb, int T)  // mb: mask bytes per slot, 0 for one-row units
     {
         keys = 0;
-        masks = keys + 4 * (T + 1);
-        items = (masks + mask_region(mb, T + 1) + 15) & ~15;
+        masks = align16(keys + 4 * (T + 1));
+        items = align16(masks + mb * (T + 1));
         sbits = items + 16 * 64;
         bytes = (sbits + 8 * kRoundPasses + 15) & ~15;
     }
@@ -147,9 +161,9 @@ struct NumLayout {
         const int mb = cl ? (S <= 8 ? 1 : 2) : 0;
         const int nv = cl ? vcap + 1 : TX + 1;  // value entries incl. the dummy
         keys = 0;
-        vidx = keys + 4 * (TX + 1);
-        masks = vidx + (cl ? (2 * (TX + 1) + 3) & ~3 : 0);
-        vals = (masks + mask_region(mb, nv) + 15) & ~15;
+        vidx = align16(keys + 4 * (TX + 1));
+        masks = align16(vidx + (cl ? 2 * (TX + 1) : 0));
+        vals = align16(masks + mb * nv);
         aval = vals + 8 * S * nv;
         const int end = aval + (cl && !a_in_regs(S) ? 8 * S * 64 : 0);
         items = (end + 15) & ~15;
@@ -311,10 +325,9 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
     MaskT<S> *masks = (MaskT<S> *)(base + L.masks);
     ItemRec *items = (ItemRec *)(base + L.items);
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
-    for (int i = lane; i <= T; i += 64) {
-        keys[i] = i == T ? kDummyKey : kEmpty;
-        if (MS) masks[i] = 0;
-    }
+    lds_fill(keys, 4 * T, (uint32_t)kEmpty);
+    if (MS) lds_fill(masks, (S <= 8 ? 1 : 2) * (T + 1), 0u);
+    if (lane == 0) keys[T] = kDummyKey;
     int mcnt[S];  // wave-uniform per-member counts
 #pragma unroll
     for (int l = 0; l < S; ++l) mcnt[l] = 0;
@@ -453,16 +466,13 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     // value column stride: entries incl. the dummy (MS: one per key, else one per slot)
     const int VS = MS ? a.vcap + 1 : TX + 1;
     const UnitView v = unit_view<CL>(a, u);
-    for (int i = lane; i <= TX; i += 64) {
-        keys[i] = i == TX ? kDummyKey : kEmpty;
-        if (MS) vidx[i] = (uint16_t)a.vcap;  // the dummy entry until a key takes the slot
+    lds_fill(keys, 4 * TX, (uint32_t)kEmpty);
+    if (MS) {
+        lds_fill(vidx, 2 * (TX + 1), (uint32_t)a.vcap * 0x10001u);  // the dummy entry until a key takes the slot
+        lds_fill(masks, (int)sizeof(MaskT<S>) * VS, 0u);
     }
-    for (int i = lane; i < VS; i += 64) {
-        if (MS) masks[i] = 0;
-#pragma unroll
-        for (int l = 0; l < S; ++l)
-            if (l < v.s) vals[l * VS + i] = 0.0;
-    }
+    lds_fill(vals, 8 * S * VS, 0u);
+    if (lane == 0) keys[TX] = kDummyKey;
     int nkeys = 0;  // MS: value entries handed out (wave-uniform)
     const int lo = a.keylo[u], hi = a.keyhi[u];
     const float scale = __fdividef((float)T, (float)(uint32_t)(hi - lo + 1));
