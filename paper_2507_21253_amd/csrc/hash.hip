@@ -114,6 +114,15 @@ __device__ __forceinline__ uint32_t mask_or(MaskT<S> *masks, uint32_t h, uint32_
     return (old >> sh) & (S <= 8 ? 0xffu : 0xffffu);
 }
 
+// The same without reading the mask back: an atomic OR that returns nothing
+// (nothing to wait for).
+template <int S>
+__device__ __forceinline__ void mask_set(MaskT<S> *masks, uint32_t h, uint32_t m)
+{
+    const uint32_t byte = h * (uint32_t)sizeof(MaskT<S>);
+    atomicOr(reinterpret_cast<uint32_t *>(masks) + (byte >> 2), m << (8 * (byte & 3u)));
+}
+
 // Fills n bytes (rounded up to 16; the region is padded to 16) at a
 // 16-byte aligned shared-memory address with a 4-byte pattern, 16 bytes per
 // lane and store.
@@ -515,8 +524,8 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     auto entry = [&](int h) -> int {
         if (!MS) return h;
         const uint64_t fb = __ballot(fresh);
-        if (fresh) vidx[h] = (uint16_t)min(nkeys + __popcll(fb & lanemask_lt(lane)), a.vcap);
-        nkeys += __popcll(fb);
+        if (fresh) vidx[h] = (uint16_t)min(nkeys + (int)__popcll(fb & lanemask_lt(lane)), a.vcap);
+        nkeys += (int)__popcll(fb);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         return vidx[h];
     };
@@ -527,7 +536,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             if (MS) {
                 const uint32_t mt = (uint32_t)uniform((int)items[tt].x);
                 const int src = uniform((int)items[tt].y);
-                masks[h] = (MaskT<S>)(masks[h] | mt);  // lanes of one sub-step hold distinct slots
+                mask_set<S>(masks, (uint32_t)h, mt);
 #pragma unroll
                 for (int l = 0; l < S; ++l) {
                     if ((mt >> l) & 1u) {
