@@ -51,9 +51,12 @@ def _bucket(x: float, edges) -> int:
 
 def matrix_class(f: np.ndarray) -> str:
     """Class key from the structure features: mean row length, spread of the per-row work, compression of
-    products into output entries, and the best similarity a row finds (what clustering can exploit)."""
-    return "rl%d_cv%d_cr%d_sim%d" % (_bucket(f[2], (6, 16, 40)), _bucket(f[12], (0.5, 2.0)),
-                                     _bucket(f[22], (1.3, 3.0)), _bucket(f[21], (0.3, 0.6)))
+    products into output entries, the best similarity a row finds (what clustering can exploit), and
+    whether columns lie near the diagonal (mean |col - row| / ncols: a row's output columns then come in
+    runs, which changes the best hash-table fill)."""
+    return "rl%d_cv%d_cr%d_sim%d_loc%d" % (_bucket(f[2], (6, 16, 40)), _bucket(f[12], (0.5, 2.0)),
+                                           _bucket(f[22], (1.3, 3.0)), _bucket(f[21], (0.3, 0.6)),
+                                           _bucket(f[14], (0.05,)))
 
 
 def _time_ms(P: Product, reps: int) -> float:
@@ -171,8 +174,9 @@ def tuning_set():
     the way the full-size ones do), name -> HostCSR."""
     import synth
     out = {}
-    out["stencil27_80_relabelled"] = synth.workload_stencil27(80, 20, 21)[0]
-    out["stencil27_60"] = synth.stencil(27, 60, 22)
+    out["stencil27_90_relabelled"] = synth.workload_stencil27(90, 20, 21)[0]
+    out["stencil27_80_relabelled"] = synth.workload_stencil27(80, 23, 24)[0]
+    out["stencil27_70"] = synth.stencil(27, 70, 22)
     out["stencil7_40"] = synth.stencil(7, 40, 23)
     out["stencil5_300"] = synth.stencil(5, 300, 24)
     for d in (4, 8, 16, 32):
@@ -185,7 +189,7 @@ def main():
     import argparse
     p = argparse.ArgumentParser(description="tune the library's options per matrix class on this GPU")
     p.add_argument("--out", default=TABLE_PATH)
-    p.add_argument("--reps", type=int, default=3)
+    p.add_argument("--reps", type=int, default=10)
     a = p.parse_args()
     table = TuneTable()
     for name, H in tuning_set().items():

@@ -80,5 +80,7 @@ def test_tune_table_choice_rule_and_roundtrip(tmp_path):
 
 def test_matrix_class_buckets():
     f = np.zeros(32, np.float32)
-    f[2], f[12], f[22], f[21] = 27.0, 0.2, 5.0, 0.5
-    assert tune.matrix_class(f) == "rl2_cv0_cr2_sim1"
+    f[2], f[12], f[22], f[21], f[14] = 27.0, 0.2, 5.0, 0.5, 0.3
+    assert tune.matrix_class(f) == "rl2_cv0_cr2_sim1_loc1"
+    f[14] = 0.001                                          # columns near the diagonal
+    assert tune.matrix_class(f) == "rl2_cv0_cr2_sim1_loc0"
