@@ -59,9 +59,12 @@ def parse():
     p.add_argument("--symmetric", action="store_true",
                    help="permute M symmetrically (rows and columns; B reordered too) instead of A's rows only")
     p.add_argument("--lanes", type=int, default=0)
-    p.add_argument("--mode", choices=["bench", "copy", "batch"], default="bench",
+    p.add_argument("--mode", choices=["bench", "copy", "batch", "tallskinny"], default="bench",
                    help="bench: the stencil workload (the headline line); batch: 512 uneven products replayed "
-                        "as one captured graph; copy: device copy for counter calibration")
+                        "as one captured graph; tallskinny: the stencil times 10 BFS frontier matrices; copy: "
+                        "device copy for counter calibration")
+    p.add_argument("--sources", type=int, default=512, help="tallskinny: BFS sources (columns of B)")
+    p.add_argument("--iterations", type=int, default=10, help="tallskinny: frontier matrices (BFS levels 1..)")
     p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--load-pct", type=int, default=0, help="numeric table fill target (0: autotuned)")
     p.add_argument("--sym-load-pct", type=int, default=0, help="symbolic table fill bound (0: autotuned)")
@@ -110,6 +113,73 @@ def copy_mode(args):
     ms = e0.elapsed_time(e1) / 5
     print(json.dumps({"mode": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "ms": ms,
                       "gbs": 16 * n / ms / 1e6}), flush=True)
+
+
+def tallskinny_mode(args):
+    """Square x tall-skinny products (the paper's second workload): A = the relabelled 27-point stencil,
+    B_L = its multi-source BFS frontier matrix after L steps (one column per source), L = 1..iterations.
+    A is reordered (RCM rows) and clustered (hierarchical, the tuned size) once and reused for every B_L;
+    each product is timed plain and clustered (symbolic, read-back, numeric), with library default table
+    fills; the clustered C must equal the plain C bit for bit, and one iteration is checked against the
+    oracle in full."""
+    import torch
+    import paper_2507_21253_amd as hc
+    import synth
+    m = args.m
+    M, _, _ = synth.workload_stencil27(m, 2, 3)
+    t = time.perf_counter()
+    Bs = [synth.frontiers(M, args.sources, L, 12) for L in range(1, args.iterations + 1)]
+    log("frontiers: %d sources, nnz %s (%.1fs)" % (args.sources, [B.nnz for B in Bs], time.perf_counter() - t))
+    from paper_2507_21253_amd import tune
+    tuned = (tune.TuneTable() if args.untuned else tune.TuneTable.load()).lookup(hc.features(M))
+    mc = args.max_cluster or (tuned["best_cluster_size"] if tuned["tuned"] else 2)
+    ncpu = len(os.sched_getaffinity(0))
+    t = time.perf_counter()
+    plan = hc.plan_hierarchical(M, (3, 10), mc, hc.SIM_ROOT, nthreads=ncpu, perm_in=hc.order_rcm(M))
+    t_prep = time.perf_counter() - t
+    Md = hc.DeviceCSR.from_host(M)
+    Dc = hc.cluster_build(Md, plan)
+    torch.cuda.synchronize()
+    rl = np.diff(M.rp)
+    rows = []
+    tot = {"plain": 0.0, "clustered": 0.0}
+    flops = 0
+    for L, B in enumerate(Bs, 1):
+        Bd = hc.DeviceCSR.from_host(B)
+        products = int(np.diff(B.rp)[M.col].sum())
+        flops += 2 * products
+        P_pl, P_cl = hc.Product(Md, Bd), hc.Product(Dc, Bd)
+        w_pl = time_product(P_pl, args.steps, args.warmup, torch)[0]
+        w_cl = time_product(P_cl, args.steps, args.warmup, torch)[0]
+        nnz = P_pl.info.nnz
+        assert P_cl.info.nnz == nnz
+        assert (torch.equal(P_cl.C_row_ptr, P_pl.C_row_ptr) and torch.equal(P_cl.C_col[:nnz], P_pl.C_col[:nnz])
+                and torch.equal(P_cl.C_val[:nnz].view(torch.int64), P_pl.C_val[:nnz].view(torch.int64)))
+        if L == min(3, len(Bs)) and not args.no_cpu:
+            import oracle
+            ref = oracle.spgemm_mt(M, B, ncpu)
+            got = P_cl.run().to_host()
+            assert (np.array_equal(got.rp, ref.rp) and np.array_equal(got.col, ref.col)
+                    and np.array_equal(got.val, ref.val)), "tall-skinny product differs from the oracle"
+            log("iteration %d equals the oracle bit for bit" % L)
+        tot["plain"] += w_pl
+        tot["clustered"] += w_cl
+        rows.append({"iteration": L, "nnz_B": B.nnz, "products": products, "nnz_C": int(nnz),
+                     "plain_ms": round(w_pl, 4), "clustered_ms": round(w_cl, 4)})
+        log("L=%d nnz(B)=%d products=%d: plain %.3f ms, clustered %.3f ms" % (L, B.nnz, products, w_pl, w_cl))
+        del P_pl, P_cl, Bd
+    out = {"metric": "tall-skinny SpGEMM GFLOP/s (A x %d BFS frontier matrices)" % len(Bs),
+           "value": round(flops / (tot["clustered"] * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tot["clustered"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "stencil27_%d^3_relabelled_x_bfs_frontiers" % m, "sources": args.sources,
+                      "iterations": len(Bs), "max_cluster": mc, "reorder": "rcm rows of A",
+                      "clustering": "hierarchical"},
+           "plain_ms_total": round(tot["plain"], 4), "speedup_clustered_vs_plain": round(tot["plain"] / tot["clustered"], 3),
+           "preprocessing_host_s": round(t_prep, 3),
+           "preprocessing_in_products": round(t_prep * 1e3 / (tot["clustered"] / len(Bs)), 1),
+           "per_iteration": rows}
+    print(json.dumps(out), flush=True)
 
 
 def batch_mode(args):
@@ -236,6 +306,9 @@ def main():
         return
     if args.mode == "batch":
         batch_mode(args)
+        return
+    if args.mode == "tallskinny":
+        tallskinny_mode(args)
         return
     import paper_2507_21253_amd as hc
     import synth

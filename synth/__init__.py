@@ -60,6 +60,8 @@ def _load():
         lib.synth_relabel.restype = ctypes.c_int
         lib.synth_rmat.argtypes = [ctypes.c_int, i64, dbl, dbl, dbl, u64, vp, vp, i64]
         lib.synth_rmat.restype = i64
+        lib.synth_frontiers.argtypes = [i64, vp, vp, i32, i32, u64, vp, vp, vp, i64]
+        lib.synth_frontiers.restype = i64
         _lib = lib
     return _lib
 
@@ -174,6 +176,26 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
         raise RuntimeError("rmat generation failed (%d)" % nnz)
     col = col[:nnz].copy()
     return HostCSR(rp, col, np.ones(nnz, np.float64), n, n)
+
+
+def frontiers(A: HostCSR, nsrc: int, level: int, seed: int) -> HostCSR:
+    """Multi-source BFS frontier matrix (n x nsrc) of the square graph A: column s holds the vertices at
+    distance exactly ``level`` from source s (sources: a seeded sample of the vertices), values U(-1,1)."""
+    n = A.nrows
+    rp_a = np.ascontiguousarray(A.rp, np.int64)
+    col_a = np.ascontiguousarray(A.col, np.int32)
+    rp = np.empty(n + 1, np.int64)
+    cap = max(1 << 20, 4 * nsrc)
+    while True:
+        col = np.empty(cap, np.int32)
+        val = np.empty(cap, np.float64)
+        nnz = int(_load().synth_frontiers(n, _p(rp_a), _p(col_a), nsrc, level, seed, _p(rp), _p(col), _p(val), cap))
+        if nnz == -2:
+            cap *= 4
+            continue
+        if nnz < 0:
+            raise ValueError("bad frontiers() arguments")
+        return HostCSR(rp, col[:nnz].copy(), val[:nnz].copy(), n, nsrc)
 
 
 def identity(n: int) -> HostCSR:

@@ -59,7 +59,7 @@ static inline uint64_t below(uint64_t key, uint64_t n, uint64_t m)
     return (uint64_t)(((unsigned __int128)synth_u64(key, n) * m) >> 64);
 }
 
-enum { TAG_COL = 1, TAG_VAL = 2, TAG_PERM = 3, TAG_RMAT = 4 };
+enum { TAG_COL = 1, TAG_VAL = 2, TAG_PERM = 3, TAG_RMAT = 4, TAG_FRONTIER = 5 };  /* 5 and 6 */
 
 static void isort_i32(int32_t *a, int64_t n)
 {
@@ -304,4 +304,82 @@ int64_t synth_rmat(int scale, int64_t nedges, double a, double b, double c, uint
     }
     free(tmp); free(deg);
     return rc ? rc : out;
+}
+
+static int cmp_u64(const void *x, const void *y)
+{
+    const uint64_t a = *(const uint64_t *)x, b = *(const uint64_t *)y;
+    return a < b ? -1 : a > b;
+}
+
+/*
+ * Multi-source BFS frontier matrix of a square graph A (CSR pattern, values
+ * ignored): nsrc sources (the first nsrc entries of a seeded permutation of
+ * the vertices); column s of the n x nsrc result holds the vertices at
+ * distance exactly `level` from source s (the frontier of a breadth-first
+ * search after `level` steps), values U(-1,1).  Writes out_rp[n+1] and up to
+ * `cap` entries; returns the entry count, -1 on bad arguments or -2 when cap
+ * is too small (call again with a larger one).
+ */
+int64_t synth_frontiers(int64_t n, const int64_t *rp, const int32_t *col, int32_t nsrc, int32_t level,
+                        uint64_t seed, int64_t *out_rp, int32_t *out_col, double *out_val, int64_t cap)
+{
+    if (n <= 0 || nsrc <= 0 || nsrc > n || level < 0 || !rp || !col || !out_rp) return -1;
+    int32_t *src = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *nxt = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t pcap = 1 << 16, np_ = 0;
+    uint64_t *pairs = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)pcap);
+    if (!src || !dist || !cur || !nxt || !seen || !pairs || synth_perm(n, synth_key(seed, TAG_FRONTIER), src) != 0) {
+        free(src); free(dist); free(cur); free(nxt); free(seen); free(pairs);
+        return -1;
+    }
+    for (int64_t v = 0; v < n; ++v) dist[v] = -1;
+    for (int32_t s = 0; s < nsrc; ++s) {
+        int64_t ncur = 1, nseen = 1;
+        cur[0] = src[s];
+        seen[0] = src[s];
+        dist[src[s]] = 0;
+        for (int32_t d = 1; d <= level && ncur > 0; ++d) {
+            int64_t nn = 0;
+            for (int64_t t = 0; t < ncur; ++t) {
+                const int32_t u = cur[t];
+                for (int64_t q = rp[u]; q < rp[u + 1]; ++q) {
+                    const int32_t w = col[q];
+                    if (dist[w] >= 0) continue;
+                    dist[w] = d;
+                    nxt[nn++] = w;
+                    seen[nseen++] = w;
+                }
+            }
+            int32_t *tmp = cur; cur = nxt; nxt = tmp;
+            ncur = nn;
+        }
+        if (np_ + ncur > pcap) {
+            while (np_ + ncur > pcap) pcap *= 2;
+            uint64_t *p2 = (uint64_t *)realloc(pairs, sizeof(uint64_t) * (size_t)pcap);
+            if (!p2) { free(src); free(dist); free(cur); free(nxt); free(seen); free(pairs); return -1; }
+            pairs = p2;
+        }
+        for (int64_t t = 0; t < ncur; ++t) pairs[np_++] = (uint64_t)cur[t] * (uint64_t)nsrc + (uint64_t)s;
+        for (int64_t t = 0; t < nseen; ++t) dist[seen[t]] = -1;
+    }
+    int64_t rc = np_;
+    if (np_ <= cap) {
+        qsort(pairs, (size_t)np_, sizeof(uint64_t), cmp_u64);
+        const uint64_t kv = synth_key(seed, TAG_FRONTIER + 1);
+        for (int64_t v = 0; v <= n; ++v) out_rp[v] = 0;
+        for (int64_t t = 0; t < np_; ++t) {
+            out_rp[pairs[t] / (uint64_t)nsrc + 1]++;
+            out_col[t] = (int32_t)(pairs[t] % (uint64_t)nsrc);
+            out_val[t] = uval(kv, pairs[t]);
+        }
+        for (int64_t v = 0; v < n; ++v) out_rp[v + 1] += out_rp[v];
+    } else {
+        rc = -2;
+    }
+    free(src); free(dist); free(cur); free(nxt); free(seen); free(pairs);
+    return rc;
 }
