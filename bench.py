@@ -54,7 +54,7 @@ def parse():
     p.add_argument("--sim", choices=["root", "union"], default="root")
     p.add_argument("--clustering", choices=["hierarchical", "variable", "fixed"], default="hierarchical",
                    help="plan: Alg. 3 (default), Alg. 2 (threshold 3/10) or fixed-length blocks")
-    p.add_argument("--reorder", choices=["rcm", "degree", "none"], default="rcm",
+    p.add_argument("--reorder", choices=["rcm", "degree", "random", "none"], default="rcm",
                    help="row order of A before clustering (A = M with rows permuted, B = M)")
     p.add_argument("--symmetric", action="store_true",
                    help="permute M symmetrically (rows and columns; B reordered too) instead of A's rows only")
@@ -336,7 +336,8 @@ def main():
     t = time.perf_counter()
     P = None
     if args.reorder != "none":
-        P = hc.order_rcm(M) if args.reorder == "rcm" else hc.order_degree(M)
+        P = (hc.order_rcm(M) if args.reorder == "rcm" else hc.order_degree(M) if args.reorder == "degree"
+             else synth.perm(M.nrows, 17))  # random: a seeded uniform permutation
     t_reorder = time.perf_counter() - t
     R = M if P is None else hc.permute_h(M, P, P if args.symmetric else None, ncpu)  # the reordered baseline
     A_plan, perm_in = (R, None) if args.symmetric else (M, P)
