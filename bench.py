@@ -417,6 +417,24 @@ def main():
         log("learned: %s" % learned_out)
         del PP
 
+    # ---- C written in CSR_Cluster form on A's clusters (Alg. 1's output), same operands and options
+    clout = None
+    if not args.symmetric:
+        CP = hc.ClusterProduct(Dc, Bd, o_cl)
+        for _ in range(args.warmup):
+            CP.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            Ccl = CP.run()
+        torch.cuda.synchronize()
+        wall_co = (time.perf_counter() - t) * 1e3 / args.steps
+        clout = {"ms_per_step": round(wall_co, 4), "gflops": round(flop / (wall_co * 1e-3) / 1e9, 3),
+                 "ncc": int(Ccl.ncc), "nslots": int(Ccl.nslots), "bytes_over_csr": round(Ccl.bytes() /
+                                                                                        csr_bytes(M.nrows, nnzC), 3)}
+        log("CSR_Cluster output: %s" % clout)
+        del CP, Ccl
+
     log("clustered: %.3f ms/step (sym %.3f, num %.3f); plain: %.3f ms/step (sym %.3f, num %.3f); "
         "plain reordered: %s" % (wall_cl, sym_cl, num_cl, wall_pl, sym_pl, num_pl,
                                  "-" if wall_ro is None else "%.3f ms/step (sym %.3f, num %.3f)" % (wall_ro, sym_ro,
@@ -478,6 +496,7 @@ def main():
                       "phases_ms": {"symbolic_incl_readback": round(sym_pl, 4), "numeric": round(num_pl, 4)}},
         "speedup_clustered_vs_plain": round(wall_pl / wall_cl, 3),
         "clustered_equals_plain_bitwise": None if args.symmetric else True,
+        "clustered_output_csr_cluster": clout,
         "plain_csr_reordered": None if wall_ro is None else {
             "gflops": round(flop / (wall_ro * 1e-3) / 1e9, 3), "ms_per_step": round(wall_ro, 4),
             "phases_ms": {"symbolic_incl_readback": round(sym_ro, 4), "numeric": round(num_ro, 4)},

@@ -248,6 +248,35 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                         double *C_val_d, int64_t capacity, void *ws_d, size_t ws_bytes,
                         void *stream);
 
+/*
+ * C in CSR_Cluster form (paper, Alg. 1, which writes C cluster by cluster):
+ * for a CSR_Cluster A, C keeps A's clusters (cl_row_ptr and perm are A's),
+ * and per cluster holds the sorted union of its member rows' output columns,
+ * a member mask per union column and the member values column by column
+ * (+0.0 where a member lacks the column), the layout of hcsp_csr_cluster.
+ * Such a C can be the left operand of a further product without a new plan.
+ *
+ * hcsp_cluster_output_layout: after hcsp_spgemm_symbolic on the same A, B,
+ * opts and workspace, writes cl_col_ptr_d[nclusters+1] and
+ * cl_val_ptr_d[nclusters+1] (device) and returns ncc and nslots (host) so
+ * the caller can allocate cl_col (int32 [ncc]), cl_mask (uint16 [ncc]) and
+ * cl_val (double [nslots]).  Synchronizes.  HCSP_E_UNSUPPORTED when a
+ * cluster's union did not fit a shared-memory table (global-memory path).
+ *
+ * hcsp_spgemm_numeric_cluster: the numeric phase writing C as CSR_Cluster.
+ * C: nrows, nclusters as A's, ncols = B.ncols, ncc and nslots from the
+ * layout call (the capacities of its arrays), cl_col_ptr/cl_val_ptr as the
+ * layout call wrote them; cl_row_ptr/perm are not read.  Same info and
+ * workspace rules as hcsp_spgemm_numeric.  Synchronizes; HCSP_E_CAPACITY if
+ * the arrays are too small, HCSP_E_INVALID if the counts changed.
+ */
+int hcsp_cluster_output_layout(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
+                               const hcsp_sym_info *info, int64_t *cl_col_ptr_d, int64_t *cl_val_ptr_d,
+                               int64_t *ncc_h, int64_t *nslots_h, void *ws_d, size_t ws_bytes, void *stream);
+int hcsp_spgemm_numeric_cluster(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
+                                const hcsp_sym_info *info, const hcsp_csr_cluster *C, void *ws_d,
+                                size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------- predicted sizes
  * A product without a symbolic phase in front: every row's output count is
  * predicted as capacity_i = min(p_i, ceil(p_i * ratio)), p_i the row's

@@ -96,6 +96,12 @@ _SIGS = {
                               ctypes.POINTER(c_sym_info), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "hcsp_spgemm_numeric": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
                              ctypes.POINTER(c_sym_info), vp, vp, vp, i64, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_cluster_output_layout": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
+                                    ctypes.POINTER(c_sym_info), vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
+                                    ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_spgemm_numeric_cluster": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
+                                     ctypes.POINTER(c_sym_info), ctypes.POINTER(c_csr_cluster), vp, ctypes.c_size_t,
+                                     vp], ctypes.c_int),
     "hcsp_batch_plan_init": ([i32, ctypes.POINTER(c_batch_item), ctypes.POINTER(c_opts),
                               ctypes.POINTER(c_batch_plan)], ctypes.c_int),
     "hcsp_batch_prepare": ([ctypes.POINTER(c_batch_plan), ctypes.POINTER(c_batch_item), vp, ctypes.c_size_t, vp, vp,
@@ -481,6 +487,51 @@ class Product:
 def spgemm(A, B: DeviceCSR, o: c_opts | None = None, stream=None) -> DeviceCSR:
     """C = A x B (A: DeviceCSR or DeviceCluster) with C in A's original row order."""
     return Product(A, B, o).run(stream)
+
+
+class ClusterProduct:
+    """Buffers for repeated C = A x B with a CSR_Cluster A and C in CSR_Cluster form on A's clusters (Alg. 1's
+    output).  ``run()`` does the symbolic phase, the output layout (one read-back) and the numeric phase."""
+
+    def __init__(self, A: DeviceCluster, B: DeviceCSR, o: c_opts | None = None):
+        import torch
+        self.P = Product(A, B, o)
+        self.A, self.B = A, B
+        dev = B.row_ptr.device
+        self.colp = torch.empty(A.nclusters + 1, dtype=torch.int64, device=dev)
+        self.valp = torch.empty(A.nclusters + 1, dtype=torch.int64, device=dev)
+        self.col = torch.empty(0, dtype=torch.int32, device=dev)
+        self.mask = torch.empty(0, dtype=torch.int16, device=dev)
+        self.val = torch.empty(0, dtype=torch.float64, device=dev)
+
+    def run(self, stream=None) -> DeviceCluster:
+        import torch
+        P, A, B = self.P, self.A, self.B
+        P.symbolic(stream)
+        ncc, nslots = i64(), i64()
+        opa, opb = operand(A), B.c()
+        _check(lib().hcsp_cluster_output_layout(ctypes.byref(opa), ctypes.byref(opb), ctypes.byref(P.o),
+                                                ctypes.byref(P.info), _tp(self.colp), _tp(self.valp),
+                                                ctypes.byref(ncc), ctypes.byref(nslots), _tp(P.ws), P.ws.numel(),
+                                                _stream(stream)), "cluster_output_layout")
+        if self.col.numel() < ncc.value:
+            self.col = torch.empty(ncc.value, dtype=torch.int32, device=self.colp.device)
+            self.mask = torch.empty(ncc.value, dtype=torch.int16, device=self.colp.device)
+        if self.val.numel() < nslots.value:
+            self.val = torch.empty(nslots.value, dtype=torch.float64, device=self.colp.device)
+        C = DeviceCluster(A.nrows, B.ncols, A.nclusters, ncc.value, nslots.value, A.max_cluster, A.cl_row_ptr,
+                          A.perm, self.colp, self.col[:ncc.value], self.mask[:ncc.value], self.valp,
+                          self.val[:nslots.value])
+        cc = C.c()
+        _check(lib().hcsp_spgemm_numeric_cluster(ctypes.byref(opa), ctypes.byref(opb), ctypes.byref(P.o),
+                                                 ctypes.byref(P.info), ctypes.byref(cc), _tp(P.ws), P.ws.numel(),
+                                                 _stream(stream)), "spgemm_numeric_cluster")
+        return C
+
+
+def spgemm_cluster_out(A: DeviceCluster, B: DeviceCSR, o: c_opts | None = None, stream=None) -> DeviceCluster:
+    """C = A x B for a CSR_Cluster A, with C in CSR_Cluster form on A's clusters (Alg. 1's output)."""
+    return ClusterProduct(A, B, o).run(stream)
 
 
 # ------------------------------------------------------------------ batches

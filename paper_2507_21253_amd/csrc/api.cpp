@@ -403,6 +403,9 @@ static BinArgs batch_bin_args(const hcsp_batch_plan &plan, const BatchWs &ws, co
 
 using namespace hcsp;
 
+static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, const Tune &tu, const Workspace &ws,
+                        hipStream_t s);
+
 extern "C" {
 
 const char *hcsp_version(void) { return "hcsp 0.1 (gfx950)"; }
@@ -645,38 +648,7 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
     a.out_base = o->out_base;
     a.unit_lo = o->unit_lo;
     a.unit_hi = o->unit_hi > 0 ? o->unit_hi : INT64_MAX;
-    std::vector<int64_t> begin(kNumBins), work(kNumBins, 0);
-    int64_t start = 0;
-    for (int b = 0; b < kNumBins; ++b) {
-        const int64_t c = info->num_bin_count[b];
-        begin[b] = start;
-        start += c;
-        if (c > 0 && b != kBinEmpty) work[b] = b == kNumGlobal ? INT64_MAX / 2 : c * num_table((b - 1) % kNumT);
-    }
-    rc = run_bins(s, work, [&](int b, hipStream_t st) -> int {
-        const int64_t c = info->num_bin_count[b];
-        a.bin_begin = begin[b];
-        a.count = c;
-        if (b == kNumGlobal) {
-            const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
-            HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, st));
-            HCSP_HIP(launch_num_dense(v.cluster, false, a, waves / 4, st));
-            return HCSP_OK;
-        }
-        const int sc = (b - 1) / kNumT;
-        const int t = (b - 1) % kNumT;
-        a.T = num_table(t);
-        a.vcap = num_vcap(a.T, tu.load_pct);
-        const int64_t gb = num_wave_bytes(v.cluster, sc, a.T, tu.load_pct);
-        a.group_bytes = (int)gb;
-        int blocks, threads;
-        size_t lds;
-        geometry(gb, c, &blocks, &threads, &lds, true);
-        const int e = ensure_lds(lds, tu.lds_budget);
-        if (e) return e;
-        HCSP_HIP(launch_num(sc, v.cluster, false, a, blocks, threads, lds, st));
-        return HCSP_OK;
-    });
+    rc = numeric_bins(a, info, v.cluster, tu, ws, s);
     if (rc) return rc;
     if (o->flags & HCSP_F_SYNC_CHECK) {
         uint32_t e = 0;
@@ -685,6 +657,133 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
         if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "output capacity too small for the requested units");
         if (e & kErrCount) return fail(HCSP_E_INVALID, "row counts differ from the symbolic phase (inputs changed?)");
     }
+    return HCSP_OK;
+}
+
+}  // extern "C"
+
+// The numeric launches of every bin the symbolic phase filled (a: the
+// product's arguments and outputs).
+static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, const Tune &tu, const Workspace &ws,
+                        hipStream_t s)
+{
+    std::vector<int64_t> begin(kNumBins), work(kNumBins, 0);
+    int64_t start = 0;
+    for (int b = 0; b < kNumBins; ++b) {
+        const int64_t c = info->num_bin_count[b];
+        begin[b] = start;
+        start += c;
+        if (c > 0 && b != kBinEmpty) work[b] = b == kNumGlobal ? INT64_MAX / 2 : c * num_table((b - 1) % kNumT);
+    }
+    return run_bins(s, work, [&](int b, hipStream_t st) -> int {
+        const int64_t c = info->num_bin_count[b];
+        a.bin_begin = begin[b];
+        a.count = c;
+        if (b == kNumGlobal) {
+            const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
+            HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, st));
+            HCSP_HIP(launch_num_dense(cluster, false, a, waves / 4, st));
+            return HCSP_OK;
+        }
+        const int sc = (b - 1) / kNumT;
+        const int t = (b - 1) % kNumT;
+        a.T = num_table(t);
+        a.vcap = num_vcap(a.T, tu.load_pct);
+        const int64_t gb = num_wave_bytes(cluster, sc, a.T, tu.load_pct);
+        a.group_bytes = (int)gb;
+        int blocks, threads;
+        size_t lds;
+        geometry(gb, c, &blocks, &threads, &lds, true);
+        const int e = ensure_lds(lds, tu.lds_budget);
+        if (e) return e;
+        HCSP_HIP(launch_num(sc, cluster, false, a, blocks, threads, lds, st));
+        return HCSP_OK;
+    });
+}
+
+// Checks shared by the numeric entry points: operands, info, options and
+// workspace; fills v, tu and ws.
+static int numeric_setup(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, const hcsp_sym_info *info,
+                         void *ws_d, size_t ws_bytes, OpView *v, Tune *tu, Workspace *ws)
+{
+    int rc = check_operands(A, B, v);
+    if (rc) return rc;
+    if (!info || !info->valid || info->units != v->nunits)
+        return fail(HCSP_E_INVALID, "info is not from a matching symbolic call");
+    rc = make_tune(opts, B, true, tu);
+    if (rc) return rc;
+    if (tu->G != info->lanes || tu->load_pct != info->load_pct)
+        return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
+    const size_t need = layout_workspace(v->nunits, v->nrows, B->ncols, tu->dense_slots, (char *)ws_d, ws);
+    if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
+    return HCSP_OK;
+}
+
+extern "C" {
+
+int hcsp_cluster_output_layout(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
+                               const hcsp_sym_info *info, int64_t *cl_col_ptr_d, int64_t *cl_val_ptr_d,
+                               int64_t *ncc_h, int64_t *nslots_h, void *ws_d, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (!A || A->kind != HCSP_OP_CLUSTER) return fail(HCSP_E_INVALID, "CSR_Cluster output needs a CSR_Cluster A");
+    if (!cl_col_ptr_d || !cl_val_ptr_d || !ncc_h || !nslots_h) return fail(HCSP_E_INVALID, "null output");
+    OpView v;
+    Tune tu;
+    Workspace ws;
+    int rc = numeric_setup(A, B, opts, info, ws_d, ws_bytes, &v, &tu, &ws);
+    if (rc) return rc;
+    if (info->num_bin_count[kNumGlobal] > 0)
+        return fail(HCSP_E_UNSUPPORTED, "clusters too large for shared-memory tables cannot be written as CSR_Cluster");
+    hipStream_t s = (hipStream_t)stream;
+    HCSP_HIP(launch_fill_u32(ws.err, 1, 0u, s));
+    HCSP_HIP(launch_cl_out_counts(ws.ucount, A->cl.cl_row_ptr, v.nunits, cl_col_ptr_d, cl_val_ptr_d, ws.err, s));
+    HCSP_HIP(launch_scan_exclusive(cl_col_ptr_d, v.nunits + 1, ws.scan_tmp, s));
+    HCSP_HIP(launch_scan_exclusive(cl_val_ptr_d, v.nunits + 1, ws.scan_tmp, s));
+    uint32_t e = 0;
+    HCSP_HIP(hipMemcpyAsync(ncc_h, cl_col_ptr_d + v.nunits, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipMemcpyAsync(nslots_h, cl_val_ptr_d + v.nunits, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipMemcpyAsync(&e, ws.err, 4, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    if (e) return fail(HCSP_E_UNSUPPORTED, "a cluster's union exceeds shared memory (no CSR_Cluster output)");
+    return HCSP_OK;
+}
+
+int hcsp_spgemm_numeric_cluster(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
+                                const hcsp_sym_info *info, const hcsp_csr_cluster *C, void *ws_d, size_t ws_bytes,
+                                void *stream)
+{
+    clear_error();
+    if (!A || A->kind != HCSP_OP_CLUSTER) return fail(HCSP_E_INVALID, "CSR_Cluster output needs a CSR_Cluster A");
+    OpView v;
+    Tune tu;
+    Workspace ws;
+    int rc = numeric_setup(A, B, opts, info, ws_d, ws_bytes, &v, &tu, &ws);
+    if (rc) return rc;
+    if (!C || C->nclusters != A->cl.nclusters || C->nrows != A->cl.nrows || C->ncols != B->ncols || C->ncc < 0 ||
+        C->nslots < 0 || !C->cl_col_ptr || !C->cl_val_ptr || (C->ncc > 0 && (!C->cl_col || !C->cl_mask)) ||
+        (C->nslots > 0 && !C->cl_val))
+        return fail(HCSP_E_INVALID, "bad CSR_Cluster output");
+    if (info->num_bin_count[kNumGlobal] > 0)
+        return fail(HCSP_E_UNSUPPORTED, "clusters too large for shared-memory tables cannot be written as CSR_Cluster");
+    hipStream_t s = (hipStream_t)stream;
+    HCSP_HIP(launch_fill_u32(ws.err, 1, 0u, s));
+    SpArgs a = base_args(A, B, ws, tu);
+    a.order = ws.order_num;
+    a.oc_col_ptr = C->cl_col_ptr;
+    a.oc_val_ptr = C->cl_val_ptr;
+    a.oc_col = C->cl_col;
+    a.oc_mask = C->cl_mask;
+    a.oc_val = C->cl_val;
+    a.oc_ncc = C->ncc;
+    a.oc_nslots = C->nslots;
+    rc = numeric_bins(a, info, true, tu, ws, s);
+    if (rc) return rc;
+    uint32_t e = 0;
+    HCSP_HIP(hipMemcpyAsync(&e, ws.err, 4, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "CSR_Cluster output arrays too small");
+    if (e & kErrCount) return fail(HCSP_E_INVALID, "cluster counts differ from the symbolic phase (inputs changed?)");
     return HCSP_OK;
 }
 

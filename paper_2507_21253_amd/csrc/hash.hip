@@ -638,22 +638,29 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         if (lane == 0) hcnt[T] = (uint16_t)V;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    int64_t o0 = 0, want = 0;
+    const bool cl_out = CL && !PRED && a.oc_col != nullptr;  // C in CSR_Cluster form
+    int64_t o0 = 0, want = 0, vo = 0;
     int32_t *ccol = nullptr;
     double *cval = nullptr;
     if (PRED) {
         o0 = a.pad_off[row0];
         want = U;
+    } else if (cl_out) {
+        o0 = a.oc_col_ptr[u];
+        want = a.oc_col_ptr[u + 1] - o0;
+        vo = a.oc_val_ptr[u];
     } else if (!MS) {
         o0 = a.c_rp[row0] - a.out_base;
         want = a.c_rp[row0 + 1] - a.c_rp[row0];
     }
     // a CSR row's place in C (uniform): the whole row must fit, else every
     // entry is reported and none written
-    const bool row_fits = o0 >= 0 && o0 + want <= a.cap;
+    const bool row_fits = cl_out ? o0 >= 0 && o0 + want <= a.oc_ncc && vo >= 0 &&
+                                       vo + want * v.s <= a.oc_nslots && a.oc_val_ptr[u + 1] - vo == want * v.s
+                                 : o0 >= 0 && o0 + want <= a.cap;
     if (!MS && row_fits) {
-        ccol = a.c_col + o0;
-        cval = a.c_val + o0;
+        ccol = (cl_out ? a.oc_col : a.c_col) + o0;
+        cval = cl_out ? a.oc_val + vo : a.c_val + o0;
     }
     for (int c0 = 0; c0 < TX; c0 += 64) {
         const int sidx = c0 + lane;
@@ -685,6 +692,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             if (row_fits && rank < want) {
                 ccol[rank] = key;
                 cval[rank] = vals[sidx];
+                if (cl_out) a.oc_mask[o0 + rank] = 1;  // a one-row cluster
             } else {
                 atomicOr(a.err, kErrCapacity);
             }
@@ -699,8 +707,29 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         return;
     }
 
-    // ---- each member row's entries, in column order
+    // ---- C in CSR_Cluster form: the union columns in order, their masks and
+    // the member values (the accumulator of a member that lacks a column was
+    // never touched and holds +0.0)
     if (lane == 0 && nkeys > a.vcap) atomicOr(a.err, kErrCount);  // more keys than the bin allows
+    if (cl_out) {
+        if (!row_fits) {
+            if (lane == 0) atomicOr(a.err, kErrCapacity);
+            return;
+        }
+        if (lane == 0 && U != want) atomicOr(a.err, kErrCount);
+        for (int i = lane; i < U && i < want; i += 64) {
+            const int sl = order[i];
+            const int id = vidx[sl];
+            a.oc_col[o0 + i] = keys[sl];
+            a.oc_mask[o0 + i] = (uint16_t)masks[id];
+#pragma unroll
+            for (int l = 0; l < S; ++l)
+                if (l < v.s) a.oc_val[vo + (int64_t)i * v.s + l] = vals[l * VS + id];
+        }
+        return;
+    }
+
+    // ---- each member row's entries, in column order
     int64_t my_off = 0, my_want = 0;
     if (lane < v.s) {
         const int64_t row = member_row<CL>(a, v, lane);

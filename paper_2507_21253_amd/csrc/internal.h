@@ -170,6 +170,14 @@ struct SpArgs {
     // predicted sizes: padded row starts (numeric writes there and stores its
     // row count, or -1 when the prediction was too small, into c_rp)
     const int64_t *pad_off;
+    // numeric output in CSR_Cluster form with A's clusters (null oc_col: CSR
+    // output): per cluster its sorted union columns, their member masks and
+    // the member values column by column (+0.0 where a member lacks the column)
+    const int64_t *oc_col_ptr, *oc_val_ptr;
+    int32_t *oc_col;
+    uint16_t *oc_mask;
+    double *oc_val;
+    int64_t oc_ncc, oc_nslots;  // capacities of oc_col/oc_mask and oc_val
 };
 
 // error flag bits
@@ -220,6 +228,11 @@ hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s);
 hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
 // batches
+// CSR_Cluster output layout: per cluster its union count and union count x
+// members, [nunits] = 0 (exclusive scans then give the offsets and totals);
+// a unit of the global-memory path (count INT32_MAX) sets *err.
+hipError_t launch_cl_out_counts(const int32_t *ucount, const int64_t *cl_row_ptr, int64_t nunits, int64_t *colp,
+                                int64_t *valp, uint32_t *err, hipStream_t s);
 hipError_t launch_max_i64(const int64_t *x, int64_t n, int64_t *out, hipStream_t s);
 // predicted sizes
 hipError_t launch_products(const hcsp_csr &A, const hcsp_csr &B, int64_t *out, hipStream_t s);

@@ -654,4 +654,32 @@ hipError_t launch_csr_check(const hcsp_csr &A, uint32_t *flags, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------- CSR_Cluster output
+__global__ void __launch_bounds__(256) k_cl_out_counts(const int32_t *ucount, const int64_t *cl_row_ptr, int64_t n,
+                                                       int64_t *colp, int64_t *valp, uint32_t *err)
+{
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n; u += (int64_t)gridDim.x * blockDim.x) {
+        if (u == n) {
+            colp[n] = 0;
+            valp[n] = 0;
+            continue;
+        }
+        const int32_t U = ucount[u];
+        if (U == INT32_MAX) atomicOr(err, 1u);
+        const int64_t c = U == INT32_MAX ? 0 : U;
+        colp[u] = c;
+        valp[u] = c * (cl_row_ptr[u + 1] - cl_row_ptr[u]);
+    }
+}
+
+hipError_t launch_cl_out_counts(const int32_t *ucount, const int64_t *cl_row_ptr, int64_t nunits, int64_t *colp,
+                                int64_t *valp, uint32_t *err, hipStream_t s)
+{
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(4096, (nunits + 256) / 256));
+    hipLaunchKernelGGL(k_cl_out_counts, dim3((unsigned)blocks), dim3(256), 0, s, ucount, cl_row_ptr, nunits, colp,
+                       valp, err);
+    return hipGetLastError();
+}
+
 }  // namespace hcsp
+

@@ -269,3 +269,38 @@ def test_wrapped_probe_runs_bitwise(load):
     for K in (2, 3):
         Dc = hc.cluster_build(Ad, hc.plan_fixed(A.nrows, K))
         assert_same(gpu_product(Dc, Bd, hc.opts(load_pct=load)), ref, "clusters of %d, load %d" % (K, load))
+
+
+def _ref_cluster_out(A, B, plan):
+    """The oracle's C = A*B put into CSR_Cluster form on the plan's clusters."""
+    return oracle.cluster_build(oracle.spgemm(A, B), oracle.Plan(plan.perm, plan.cl_row_ptr))
+
+
+@pytest.mark.parametrize("which", ["stencil_relabel", "ragged"])
+def test_cluster_output_bitwise(which):
+    # C written in CSR_Cluster form (Alg. 1's output) equals the oracle's C clustered on A's clusters
+    if which == "stencil_relabel":
+        A, _, _ = synth.workload_stencil27(9, 2, 3)
+        B = A
+    else:
+        A, B = ragged(21, 300, 250, 280)
+    Ad, Bd = to_dev(A), to_dev(B)
+    for name, plan in plans_for(A):
+        Dc = hc.cluster_build(Ad, plan)
+        C = hc.spgemm_cluster_out(Dc, Bd)
+        torch.cuda.synchronize()
+        ref = _ref_cluster_out(A, B, plan)
+        got = host_cluster_of(C)
+        for k in got:
+            np.testing.assert_array_equal(got[k], getattr(ref, k), err_msg="%s %s %s" % (which, name, k))
+
+
+def test_cluster_output_chains():
+    # a clustered C is the left operand of the next product as it stands: (A*A)*A with A*A kept clustered
+    A, _, _ = synth.workload_stencil27(8, 2, 3)
+    Ad = to_dev(A)
+    plan = hc.plan_hierarchical(A, (3, 10), 4, hc.SIM_ROOT, perm_in=oracle.order_rcm(A))
+    C2 = hc.spgemm_cluster_out(hc.cluster_build(Ad, plan), Ad)
+    C3 = hc.spgemm(C2, Ad)
+    torch.cuda.synchronize()
+    assert_same(C3.to_host(), oracle.spgemm(oracle.spgemm(A, A), A))
