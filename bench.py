@@ -356,6 +356,20 @@ def main():
     Md = hc.DeviceCSR.from_host(M)
     Rd = Md if R is M else hc.DeviceCSR.from_host(R)
     Bd = Rd if args.symmetric else Md          # right operand: M, or the reordered M
+    # the same plan with the candidate search (SpGEMM_TopK) on the GPU and only the merge loop on the host
+    t_plan_gpu = None
+    if args.clustering == "hierarchical" and not args.symmetric:
+        hc.plan_hierarchical_gpu(M, Md, (3, 10), args.max_cluster, hc.SIM_UNION if args.sim == "union"
+                                 else hc.SIM_ROOT, perm_in=perm_in)  # warm-up (allocations, code load)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan_g = hc.plan_hierarchical_gpu(M, Md, (3, 10), args.max_cluster, hc.SIM_UNION if args.sim == "union"
+                                          else hc.SIM_ROOT, perm_in=perm_in)
+        t_plan_gpu = time.perf_counter() - t
+        assert np.array_equal(plan_g.perm, plan.perm) and np.array_equal(plan_g.cl_row_ptr, plan.cl_row_ptr)
+        log("plan with GPU candidate search: %.3fs (host plan %.3fs), same plan" % (t_plan_gpu, t_plan))
+        del plan_g
+        torch.cuda.empty_cache()
     Ad = Rd if args.symmetric else Md          # the matrix the CSR_Cluster is built from
     torch.cuda.synchronize()
     for _ in range(2):
@@ -502,6 +516,7 @@ def main():
             "phases_ms": {"symbolic_incl_readback": round(sym_ro, 4), "numeric": round(num_ro, 4)},
             "speedup_clustered_vs_this": round(wall_ro / wall_cl, 3)},
         "preprocessing": {"reorder_host_s": round(t_reorder, 3), "plan_host_s": round(t_plan, 3), "plan_threads": ncpu,
+                          "plan_gpu_candidates_s": None if t_plan_gpu is None else round(t_plan_gpu, 3),
                           "cluster_build_s": round(t_build, 4),
                           "in_spgemms": round((t_reorder + t_plan + t_build) / (wall_cl * 1e-3), 1),
                           "nclusters": plan.nclusters, "ncc": Dc.ncc, "nslots": Dc.nslots,

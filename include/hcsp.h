@@ -330,6 +330,31 @@ int hcsp_order_degree(const hcsp_csr *A_h, int32_t *perm_out_h);
 int hcsp_permute_h(const hcsp_csr *A_h, const int32_t *rperm_h, const int32_t *cperm_h, hcsp_csr *out_h,
                    int32_t nthreads);
 
+/*
+ * hcsp_topk_candidates: the candidate search of the hierarchical plan
+ * (paper, Alg. 3, SpGEMM_TopK) on the GPU.  O (device CSR, n x n) is the
+ * overlap matrix A A^T of A's pattern: O_ij = number of columns rows i and j
+ * share, e.g. the library's own product of A with all values 1 and A^T (A
+ * itself for a structurally symmetric A).  a_rp_d: A's row offsets (row
+ * lengths |S_i|).  pos_d[n]: position of each row in the plan order (the
+ * inverse of perm_in; NULL = identity).  For every row i, the partners j != i
+ * with J = O_ij / (|S_i| + |S_j| - O_ij) strictly above jacc_th, best first
+ * by (J descending, position ascending), at most topk (1..15) of them, go to
+ * position p = pos(i): cnt_d[p] partners, their positions in
+ * nbr_d[p*topk ..] and overlaps in ov_d[p*topk ..] (int64).  Exact integer
+ * comparisons.  Asynchronous.
+ *
+ * hcsp_plan_hierarchical_candidates: hcsp_plan_hierarchical with the
+ * candidate lists given (host copies of hcsp_topk_candidates' outputs, topk =
+ * max_cluster - 1): only the merge loop runs on the host; same result.
+ */
+int hcsp_topk_candidates(const hcsp_csr *O, const int64_t *a_rp_d, const int32_t *pos_d, hcsp_ratio jacc_th,
+                         int32_t topk, int32_t *cnt_d, int32_t *nbr_d, int64_t *ov_d, void *stream);
+int hcsp_plan_hierarchical_candidates(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_cluster,
+                                      uint32_t sim_flags, const int32_t *perm_in_h, const int32_t *cnt_h,
+                                      const int32_t *nbr_h, const int64_t *ov_h, int32_t *perm_out_h,
+                                      int64_t *cl_row_ptr_h, int64_t *ncl);
+
 /* ---------------------------------------------------------------- features
  * HCSP_NFEATURES structure-only features of the product A x B from host
  * copies of the patterns (A_h, B_h: host arrays; values are not read), for

@@ -86,6 +86,9 @@ _SIGS = {
     "hcsp_plan_variable": ([ctypes.POINTER(c_csr), c_ratio, i32, vp, vp, vp, ctypes.POINTER(i64)], ctypes.c_int),
     "hcsp_plan_hierarchical": ([ctypes.POINTER(c_csr), c_ratio, i32, u32, i32, vp, vp, vp, ctypes.POINTER(i64)],
                                ctypes.c_int),
+    "hcsp_plan_hierarchical_candidates": ([ctypes.POINTER(c_csr), c_ratio, i32, u32, vp, vp, vp, vp, vp, vp,
+                                          ctypes.POINTER(i64)], ctypes.c_int),
+    "hcsp_topk_candidates": ([ctypes.POINTER(c_csr), vp, vp, c_ratio, i32, vp, vp, vp, vp], ctypes.c_int),
     "hcsp_cluster_workspace": ([i64, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hcsp_cluster_count": ([ctypes.POINTER(c_csr), vp, vp, i64, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                             ctypes.POINTER(i32), vp, ctypes.c_size_t, vp], ctypes.c_int),
@@ -330,6 +333,57 @@ def plan_hierarchical(A_host, jacc_th=(3, 10), max_cluster: int = 8, sim=SIM_ROO
     _check(lib().hcsp_plan_hierarchical(ctypes.byref(m), _ratio(jacc_th), max_cluster, sim, nthreads, _np(pi),
                                         _np(perm), _np(crp), ctypes.byref(ncl)), "plan_hierarchical")
     return Plan(perm[:A_host.nrows], crp[:ncl.value + 1].copy())
+
+
+def topk_candidates_gpu(A: "DeviceCSR", jacc_th=(3, 10), topk: int = 7, perm_in=None, stream=None):
+    """SpGEMM_TopK (Alg. 3) on the GPU for a structurally symmetric A: the overlap matrix A A^T is the
+    library's own product of A's pattern (all values 1) with itself, then one wavefront per row keeps its topk
+    best partners.  Returns host arrays in plan positions: (cnt[n], nbr[n, topk], ov[n, topk])."""
+    import torch
+    dev = A.row_ptr.device
+    ones = DeviceCSR(A.row_ptr, A.col, torch.ones(A.nnz, dtype=torch.float64, device=dev), A.nrows, A.ncols)
+    O = spgemm(ones, ones, stream=stream)
+    n = A.nrows
+    pos = None
+    if perm_in is not None:
+        pi = torch.from_numpy(np.ascontiguousarray(perm_in, np.int32)).to(dev)
+        pos = torch.empty(n, dtype=torch.int32, device=dev)
+        pos[pi.long()] = torch.arange(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(n, dtype=torch.int32, device=dev)
+    nbr = torch.full((max(n, 1) * topk,), -1, dtype=torch.int32, device=dev)
+    ov = torch.zeros(max(n, 1) * topk, dtype=torch.int64, device=dev)
+    oc = O.c()
+    _check(lib().hcsp_topk_candidates(ctypes.byref(oc), _tp(A.row_ptr), _tp(pos) if pos is not None else None,
+                                      _ratio(jacc_th), topk, _tp(cnt), _tp(nbr), _tp(ov), _stream(stream)),
+           "topk_candidates")
+    return cnt.cpu().numpy(), nbr.cpu().numpy()[:n * topk].reshape(n, topk), ov.cpu().numpy()[:n * topk].reshape(n, topk)
+
+
+def plan_hierarchical_candidates(A_host, jacc_th, max_cluster: int, sim, cnt, nbr, ov, perm_in=None) -> Plan:
+    """hierarchical plan (Alg. 3) from given candidate lists (positions; topk = max_cluster - 1): only the
+    merge loop runs on the host."""
+    m = _host_csr(A_host)
+    pi = None if perm_in is None else np.ascontiguousarray(perm_in, np.int32)
+    perm = np.empty(max(A_host.nrows, 1), np.int32)
+    crp = np.empty(A_host.nrows + 1, np.int64)
+    ncl = i64()
+    cnt = np.ascontiguousarray(cnt, np.int32)
+    nbr = np.ascontiguousarray(nbr, np.int32)
+    ov = np.ascontiguousarray(ov, np.int64)
+    _check(lib().hcsp_plan_hierarchical_candidates(ctypes.byref(m), _ratio(jacc_th), max_cluster, sim, _np(pi),
+                                                   _np(cnt), _np(nbr), _np(ov), _np(perm), _np(crp),
+                                                   ctypes.byref(ncl)), "plan_hierarchical_candidates")
+    return Plan(perm[:A_host.nrows], crp[:ncl.value + 1].copy())
+
+
+def plan_hierarchical_gpu(A_host, A: "DeviceCSR", jacc_th=(3, 10), max_cluster: int = 8, sim=SIM_ROOT,
+                          perm_in=None) -> Plan:
+    """hierarchical plan with the candidate search on the GPU (structurally symmetric A) and the merge loop
+    on the host; the same plan as plan_hierarchical."""
+    if max_cluster <= 1:
+        return plan_hierarchical(A_host, jacc_th, max_cluster, sim, perm_in=perm_in)
+    cnt, nbr, ov = topk_candidates_gpu(A, jacc_th, max_cluster - 1, perm_in)
+    return plan_hierarchical_candidates(A_host, jacc_th, max_cluster, sim, cnt, nbr, ov, perm_in)
 
 
 def order_rcm(A_host) -> np.ndarray:

@@ -721,6 +721,21 @@ static int numeric_setup(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
 
 extern "C" {
 
+int hcsp_topk_candidates(const hcsp_csr *O, const int64_t *a_rp_d, const int32_t *pos_d, hcsp_ratio jacc_th,
+                         int32_t topk, int32_t *cnt_d, int32_t *nbr_d, int64_t *ov_d, void *stream)
+{
+    clear_error();
+    if (!O || O->nrows < 0 || O->nrows != O->ncols || (O->nrows > 0 && !O->row_ptr) ||
+        (O->nnz > 0 && (!O->col || !O->val)))
+        return fail(HCSP_E_INVALID, "topk: bad overlap matrix");
+    if (jacc_th.den <= 0 || jacc_th.num < 0 || topk < 1 || topk > 15)
+        return fail(HCSP_E_INVALID, "topk: bad threshold or topk (1..15)");
+    if (O->nrows > 0 && (!a_rp_d || !cnt_d || !nbr_d || !ov_d)) return fail(HCSP_E_INVALID, "topk: null array");
+    HCSP_HIP(launch_topk(O->row_ptr, O->col, O->val, a_rp_d, pos_d, O->nrows, jacc_th.num, jacc_th.den, topk, cnt_d,
+                         nbr_d, ov_d, (hipStream_t)stream));
+    return HCSP_OK;
+}
+
 int hcsp_cluster_output_layout(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
                                const hcsp_sym_info *info, int64_t *cl_col_ptr_d, int64_t *cl_val_ptr_d,
                                int64_t *ncc_h, int64_t *nslots_h, void *ws_d, size_t ws_bytes, void *stream)

@@ -233,6 +233,11 @@ hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
 // a unit of the global-memory path (count INT32_MAX) sets *err.
 hipError_t launch_cl_out_counts(const int32_t *ucount, const int64_t *cl_row_ptr, int64_t nunits, int64_t *colp,
                                 int64_t *valp, uint32_t *err, hipStream_t s);
+// SpGEMM_TopK: per row of the overlap matrix O (rows: original ids) the
+// topk best partners above num/den; outputs at the row's position
+hipError_t launch_topk(const int64_t *o_rp, const int32_t *o_col, const double *o_val, const int64_t *a_rp,
+                       const int32_t *pos, int64_t n, int64_t num, int64_t den, int topk, int32_t *cnt, int32_t *nbr,
+                       int64_t *nov, hipStream_t s);
 hipError_t launch_max_i64(const int64_t *x, int64_t n, int64_t *out, hipStream_t s);
 // predicted sizes
 hipError_t launch_products(const hcsp_csr &A, const hcsp_csr &B, int64_t *out, hipStream_t s);

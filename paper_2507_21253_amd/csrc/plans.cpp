@@ -295,6 +295,24 @@ int hcsp_plan_variable(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_clus
     return HCSP_OK;
 }
 
+}  // extern "C"
+
+namespace hcsp {
+namespace {
+
+// The merge loop of Alg. 3 over per-position candidate lists (cnt[p]
+// partners in nbr[p*topk ..] with similarities nsim[p*topk ..]): candidate
+// pairs go into the heap once each, then pairs are popped best first and
+// merged, lifted to their roots, rescored and pushed again.
+int merge_phase(const Pattern &P, int64_t num, int64_t den, int32_t max_cluster, uint32_t sim_flags, int topk,
+                const std::vector<int32_t> &cnt, const std::vector<int32_t> &nbr, const std::vector<Sim> &nsim,
+                int32_t *perm_out_h, int64_t *cl_row_ptr_h, int64_t *ncl);
+
+}  // namespace
+}  // namespace hcsp
+
+extern "C" {
+
 int hcsp_plan_hierarchical(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_cluster, uint32_t sim_flags,
                            int32_t nthreads, const int32_t *perm_in_h, int32_t *perm_out_h, int64_t *cl_row_ptr_h,
                            int64_t *ncl)
@@ -310,10 +328,8 @@ int hcsp_plan_hierarchical(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_
     const int64_t n = P.n, num = jacc_th.num, den = jacc_th.den;
     const int topk = max_cluster - 1;
     try {
-        std::vector<int32_t> parent((size_t)n), size((size_t)n, 1), next((size_t)n, -1), tail((size_t)n);
-        for (int64_t i = 0; i < n; ++i) parent[i] = tail[i] = (int32_t)i;
-        std::priority_queue<Cand, std::vector<Cand>, CandLess> heap;
-        PairSet cand((size_t)n * (size_t)std::max(topk, 1));
+        std::vector<int32_t> cnt((size_t)n, 0), nbr((size_t)n * std::max(topk, 1), -1);
+        std::vector<Sim> nsim((size_t)n * std::max(topk, 1));
         if (topk > 0 && n > 0) {
             // transpose of the pattern in plan order: column -> positions holding it
             std::vector<int64_t> tp((size_t)P.ncols + 1, 0);
@@ -326,8 +342,6 @@ int hcsp_plan_hierarchical(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_
                 for (int64_t p = 0; p < n; ++p)
                     for (int64_t q = 0; q < P.len(p); ++q) tr[fill[P.cols(p)[q]]++] = (int32_t)p;
             }
-            std::vector<int32_t> cnt((size_t)n, 0), nbr((size_t)n * topk, -1);
-            std::vector<Sim> nsim((size_t)n * topk);
             int nt = nthreads > 0 ? nthreads : (int)std::thread::hardware_concurrency();
             nt = std::max(1, std::min<int>(nt, 64));
             if (n < 4096) nt = 1;
@@ -337,13 +351,73 @@ int hcsp_plan_hierarchical(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_
                 th.emplace_back([&, lo, hi] { topk_rows(P, tp, tr, num, den, topk, lo, hi, cnt, nbr, nsim); });
             }
             for (auto &x : th) x.join();
-            for (int64_t i = 0; i < n; ++i)
-                for (int x = 0; x < cnt[i]; ++x) {
-                    int32_t a = (int32_t)i, b = nbr[(size_t)i * topk + x];
-                    if (a > b) std::swap(a, b);
-                    if (cand.insert(pair_key(a, b))) heap.push(Cand{nsim[(size_t)i * topk + x], a, b});
-                }
         }
+        return merge_phase(P, num, den, max_cluster, sim_flags, topk, cnt, nbr, nsim, perm_out_h, cl_row_ptr_h, ncl);
+    } catch (const std::bad_alloc &) {
+        return fail(HCSP_E_NOMEM, "hierarchical plan: host allocation failed");
+    }
+}
+
+int hcsp_plan_hierarchical_candidates(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_cluster,
+                                      uint32_t sim_flags, const int32_t *perm_in_h, const int32_t *cnt_h,
+                                      const int32_t *nbr_h, const int64_t *ov_h, int32_t *perm_out_h,
+                                      int64_t *cl_row_ptr_h, int64_t *ncl)
+{
+    clear_error();
+    if (jacc_th.den <= 0 || jacc_th.num < 0 || max_cluster < 1 || max_cluster > 16 || !cl_row_ptr_h || !ncl ||
+        sim_flags > HCSP_SIM_UNION)
+        return fail(HCSP_E_INVALID, "hierarchical plan: bad arguments");
+    Pattern P;
+    int rc = make_pattern(A_h, perm_in_h, &P);
+    if (rc) return rc;
+    if (P.n > 0 && !perm_out_h) return fail(HCSP_E_INVALID, "null perm_out");
+    const int64_t n = P.n;
+    const int topk = max_cluster - 1;
+    if (topk > 0 && n > 0 && (!cnt_h || !nbr_h || !ov_h)) return fail(HCSP_E_INVALID, "null candidate lists");
+    try {
+        std::vector<int32_t> cnt((size_t)n, 0), nbr((size_t)n * std::max(topk, 1), -1);
+        std::vector<Sim> nsim((size_t)n * std::max(topk, 1));
+        for (int64_t i = 0; i < n && topk > 0; ++i) {
+            if (cnt_h[i] < 0 || cnt_h[i] > topk) return fail(HCSP_E_INVALID, "candidate count out of range");
+            cnt[i] = cnt_h[i];
+            for (int x = 0; x < cnt[i]; ++x) {
+                const size_t k = (size_t)i * topk + x;
+                const int32_t j = nbr_h[k];
+                if (j < 0 || j >= n || j == i) return fail(HCSP_E_INVALID, "candidate partner out of range");
+                const int64_t ov = ov_h[k];
+                if (ov < 0 || ov > std::min(P.len(i), P.len(j))) return fail(HCSP_E_INVALID, "overlap out of range");
+                nbr[k] = j;
+                nsim[k] = Sim{ov, P.len(i) + P.len(j) - ov};
+            }
+        }
+        return merge_phase(P, jacc_th.num, jacc_th.den, max_cluster, sim_flags, topk, cnt, nbr, nsim, perm_out_h,
+                           cl_row_ptr_h, ncl);
+    } catch (const std::bad_alloc &) {
+        return fail(HCSP_E_NOMEM, "hierarchical plan: host allocation failed");
+    }
+}
+
+}  // extern "C"
+
+namespace hcsp {
+namespace {
+
+int merge_phase(const Pattern &P, int64_t num, int64_t den, int32_t max_cluster, uint32_t sim_flags, int topk,
+                const std::vector<int32_t> &cnt, const std::vector<int32_t> &nbr, const std::vector<Sim> &nsim,
+                int32_t *perm_out_h, int64_t *cl_row_ptr_h, int64_t *ncl)
+{
+    const int64_t n = P.n;
+    try {
+        std::vector<int32_t> parent((size_t)n), size((size_t)n, 1), next((size_t)n, -1), tail((size_t)n);
+        for (int64_t i = 0; i < n; ++i) parent[i] = tail[i] = (int32_t)i;
+        std::priority_queue<Cand, std::vector<Cand>, CandLess> heap;
+        PairSet cand((size_t)n * (size_t)std::max(topk, 1));
+        for (int64_t i = 0; i < n && topk > 0; ++i)
+            for (int x = 0; x < cnt[i]; ++x) {
+                int32_t a = (int32_t)i, b = nbr[(size_t)i * topk + x];
+                if (a > b) std::swap(a, b);
+                if (cand.insert(pair_key(a, b))) heap.push(Cand{nsim[(size_t)i * topk + x], a, b});
+            }
         std::vector<int64_t> mark;
         int64_t stamp = 0;
         if (sim_flags == HCSP_SIM_UNION) mark.assign((size_t)std::max<int64_t>(P.ncols, 1), -1);
@@ -399,4 +473,5 @@ int hcsp_plan_hierarchical(const hcsp_csr *A_h, hcsp_ratio jacc_th, int32_t max_
     }
 }
 
-}  // extern "C"
+}  // namespace
+}  // namespace hcsp

@@ -681,5 +681,77 @@ hipError_t launch_cl_out_counts(const int32_t *ucount, const int64_t *cl_row_ptr
     return hipGetLastError();
 }
 
+// ------------------------------------------------------- SpGEMM_TopK (Alg. 3)
+// One wavefront per row i of the overlap matrix O = A A^T (values: the
+// number of columns rows i and j share): among the j != i with
+// J = ov / (|S_i| + |S_j| - ov) strictly above num/den it picks the topk best
+// by (J descending, position of j ascending), one per round: every lane
+// takes the best of its strided share that comes after the previous pick,
+// then the wavefront keeps the best of the lanes.  Comparisons are exact
+// (cross-multiplied 64-bit integers).  Results go to row i's position.
+struct TkCand {
+    int64_t ov, un;
+    int32_t p;  // -1: none
+};
+
+__device__ __forceinline__ bool tk_better(const TkCand &a, const TkCand &b)  // a before b
+{
+    if (a.p < 0) return false;
+    if (b.p < 0) return true;
+    const int64_t l = a.ov * b.un, r = b.ov * a.un;
+    return l > r || (l == r && a.p < b.p);
+}
+
+__global__ void __launch_bounds__(256) k_topk(const int64_t *o_rp, const int32_t *o_col, const double *o_val,
+                                              const int64_t *a_rp, const int32_t *pos, int64_t n, int64_t num,
+                                              int64_t den, int topk, int32_t *cnt, int32_t *nbr, int64_t *nov)
+{
+    const int lane = (int)__lane_id();
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= n) return;
+    const int64_t b0 = o_rp[i], b1 = o_rp[i + 1];
+    const int64_t li = a_rp[i + 1] - a_rp[i];
+    const int64_t pi = pos ? pos[i] : i;
+    TkCand last{0, 1, -1};
+    int k = 0;
+    for (; k < topk; ++k) {
+        TkCand best{0, 1, -1};
+        for (int64_t e = b0 + lane; e < b1; e += 64) {
+            const int32_t j = o_col[e];
+            if (j == i) continue;
+            const int64_t ov = (int64_t)o_val[e];
+            const TkCand c{ov, li + (a_rp[j + 1] - a_rp[j]) - ov, pos ? pos[j] : j};
+            if (ov * den <= c.un * num) continue;  // J not above the threshold
+            if (last.p >= 0 && !tk_better(last, c)) continue;
+            if (tk_better(c, best)) best = c;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            TkCand x;
+            x.ov = __shfl_xor(best.ov, o);
+            x.un = __shfl_xor(best.un, o);
+            x.p = __shfl_xor(best.p, o);
+            if (tk_better(x, best)) best = x;
+        }
+        if (best.p < 0) break;
+        if (lane == 0) {
+            nbr[pi * topk + k] = best.p;
+            nov[pi * topk + k] = best.ov;
+        }
+        last = best;
+    }
+    if (lane == 0) cnt[pi] = k;
+}
+
+hipError_t launch_topk(const int64_t *o_rp, const int32_t *o_col, const double *o_val, const int64_t *a_rp,
+                       const int32_t *pos, int64_t n, int64_t num, int64_t den, int topk, int32_t *cnt, int32_t *nbr,
+                       int64_t *nov, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 3) / 4;
+    hipLaunchKernelGGL(k_topk, dim3((unsigned)blocks), dim3(256), 0, s, o_rp, o_col, o_val, a_rp, pos, n, num, den,
+                       topk, cnt, nbr, nov);
+    return hipGetLastError();
+}
+
 }  // namespace hcsp
 

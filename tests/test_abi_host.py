@@ -24,7 +24,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     L = hc.lib()
     names = declared_symbols()
-    assert len(names) == 29
+    assert len(names) == 31
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(hc._SIGS), "binding and header disagree"
@@ -70,6 +70,30 @@ def test_plan_hierarchical_matches_oracle(sim, t, maxc):
             same_plan(hc.plan_hierarchical(A, t, maxc, sim, nthreads), ref)
         pi = synth.perm(A.nrows, 12)
         same_plan(hc.plan_hierarchical(A, t, maxc, sim, 2, pi), oracle.plan_hierarchical(A, t, maxc, sim, pi))
+
+
+@pytest.mark.parametrize("sim", [hc.SIM_ROOT, hc.SIM_UNION])
+@pytest.mark.parametrize("t,maxc", [((3, 10), 8), ((1, 5), 4), ((1, 2), 2)])
+def test_plan_from_given_candidates_matches_oracle(sim, t, maxc):
+    # the merge loop alone, fed with the oracle's SpGEMM_TopK lists, gives the oracle's plan
+    for name, A in inputs():
+        for pi in (None, synth.perm(A.nrows, 13)):
+            cnt, nbr, ov, _ = oracle.topk_candidates(A, t, maxc - 1, pi)
+            same_plan(hc.plan_hierarchical_candidates(A, t, maxc, sim, cnt, nbr, ov, pi),
+                      oracle.plan_hierarchical(A, t, maxc, sim, pi))
+
+
+def test_plan_from_candidates_rejects_bad_lists():
+    A = synth.stencil(27, 4, 2)
+    cnt, nbr, ov, _ = oracle.topk_candidates(A, (3, 10), 3)
+    bad = nbr.copy()
+    bad[0, 0] = A.nrows                                   # partner out of range
+    cnt1 = cnt.copy()
+    cnt1[0] = max(cnt1[0], 1)
+    with pytest.raises(hc.HcspError):
+        hc.plan_hierarchical_candidates(A, (3, 10), 4, hc.SIM_ROOT, cnt1, bad, ov)
+    with pytest.raises(hc.HcspError):
+        hc.plan_hierarchical_candidates(A, (3, 10), 4, hc.SIM_ROOT, np.full_like(cnt, 4), nbr, ov)
 
 
 def test_plan_hierarchical_larger_multithreaded():
