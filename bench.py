@@ -71,6 +71,9 @@ def parse():
     p.add_argument("--untuned", action="store_true", help="ignore the autotuner's table")
     p.add_argument("--margin", type=float, default=0.1, help="margin on the predicted compression ratio")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-extras", action="store_true",
+                   help="only the three timed products (no GPU-assisted plan, CSR_Cluster output or learned legs; "
+                        "for counter runs that attribute launches by their order)")
     p.add_argument("--cpu-threads", type=int, default=0)
     return p.parse_args()
 
@@ -358,7 +361,7 @@ def main():
     Bd = Rd if args.symmetric else Md          # right operand: M, or the reordered M
     # the same plan with the candidate search (SpGEMM_TopK) on the GPU and only the merge loop on the host
     t_plan_gpu = None
-    if args.clustering == "hierarchical" and not args.symmetric:
+    if args.clustering == "hierarchical" and not args.symmetric and not args.no_extras:
         hc.plan_hierarchical_gpu(M, Md, (3, 10), args.max_cluster, hc.SIM_UNION if args.sim == "union"
                                  else hc.SIM_ROOT, perm_in=perm_in)  # warm-up (allocations, code load)
         torch.cuda.synchronize()
@@ -407,7 +410,7 @@ def main():
     # ---- the learned selector and nnz predictor, when a trained model is in the tree
     learned_out = None
     from paper_2507_21253_amd import learned
-    if os.path.exists(learned.MODEL):
+    if os.path.exists(learned.MODEL) and not args.no_extras:
         sel = learned.Selector.load()
         f = hc.features(M)[None, :]
         z = sel.logits(f)[0]
@@ -433,7 +436,7 @@ def main():
 
     # ---- C written in CSR_Cluster form on A's clusters (Alg. 1's output), same operands and options
     clout = None
-    if not args.symmetric:
+    if not args.symmetric and not args.no_extras:
         CP = hc.ClusterProduct(Dc, Bd, o_cl)
         for _ in range(args.warmup):
             CP.run()
