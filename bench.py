@@ -300,7 +300,7 @@ def time_product(P, steps, warmup, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (sharding is a design note); "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (sharding is a design note); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

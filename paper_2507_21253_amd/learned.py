@@ -20,7 +20,7 @@ small network does it from the library's 32 structure features:
   * predictor: log(nnz(C) / products), from which output and accumulator
     sizes can be estimated before the symbolic phase
     (``capacity = products * exp(prediction) * (1 + margin)``); the exact
-    symbolic phase remains the fallback and the judge of its error.
+    symbolic phase remains the fallback and the measure of its error.
 
 The network is trained on the GPU by the library's own forward,
 back-propagation and Adam kernels (``hcsp_mlp_*``); labels are the library's
