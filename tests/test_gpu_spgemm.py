@@ -304,3 +304,34 @@ def test_cluster_output_chains():
     C3 = hc.spgemm(C2, Ad)
     torch.cuda.synchronize()
     assert_same(C3.to_host(), oracle.spgemm(oracle.spgemm(A, A), A))
+
+
+def test_concurrent_host_threads_on_own_streams():
+    # two host threads, each with its own stream, run products at once: the library's side streams for
+    # small bins are shared, so their fork/join must stay per call (results bitwise, no hang)
+    import threading
+    cases = [synth.workload_stencil27(10, 2, 3)[0], synth.rmat(11, 16, 0.57, 0.19, 0.19, 6)]
+    refs = [oracle.spgemm(A, A) for A in cases]
+    devs = [to_dev(A) for A in cases]
+    errors = []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(4):
+                    C = hc.Product(devs[k], devs[k]).run(s)
+                    s.synchronize()
+                    got = C.to_host()
+                    assert np.array_equal(got.rp, refs[k].rp) and np.array_equal(got.col, refs[k].col)
+                    assert np.array_equal(got.val, refs[k].val)
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(repr(e))
+
+    th = [threading.Thread(target=work, args=(k,)) for k in (0, 1)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in th), "a thread did not finish"
+    assert not errors, errors
