@@ -57,13 +57,13 @@ class c_ratio(ctypes.Structure):
 class c_opts(ctypes.Structure):
     _fields_ = [("lanes", i32), ("flags", i32), ("unit_lo", i64), ("unit_hi", i64), ("out_base", i64),
                 ("dense_slots", i32), ("load_pct", i32), ("sym_tmax_log2", i32), ("num_tmax", i32),
-                ("sym_load_pct", i32), ("reserved", i32)]
+                ("sym_load_pct", i32), ("win_chunk_log2", i32)]
 
 
 class c_sym_info(ctypes.Structure):
     _fields_ = [("nnz", i64), ("units", i64), ("sym_bin_count", i64 * MAX_BINS),
                 ("num_bin_count", i64 * MAX_BINS), ("lanes", i32), ("valid", i32), ("load_pct", i32),
-                ("reserved", i32)]
+                ("win_chunk_log2", i32)]
 
 
 class c_batch_item(ctypes.Structure):

@@ -24,7 +24,8 @@ int fail(int code, const std::string &msg)
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, char *base, Workspace *ws)
+size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, bool windows, char *base,
+                        Workspace *ws)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> void * {
@@ -47,9 +48,11 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->err = (uint32_t *)take(256);
     ws->scan_tmp = (int64_t *)take(8 * scan_tmp_elems(std::max(nrows, nunits) + 1));
     ws->dense_words = (std::max<int64_t>(ncols, 1) + 31) / 32;
-    ws->dense_slots = dense_slots;
-    ws->dense_bits = (uint32_t *)take(4 * (size_t)ws->dense_words * dense_slots);
-    ws->dense_vals = (double *)take(8 * (size_t)std::max<int64_t>(ncols, 1) * dense_slots);
+    ws->dense_slots = windows ? 0 : dense_slots;
+    ws->dense_bits = (uint32_t *)take(4 * (size_t)ws->dense_words * ws->dense_slots);
+    ws->dense_vals = (double *)take(8 * (size_t)std::max<int64_t>(ncols, 1) * ws->dense_slots);
+    ws->chunk_cnt = (int32_t *)take(windows ? 4 * (size_t)kWinChunksMax * nu : 0);
+    ws->win_base = (int64_t *)take(windows ? 8 * (nu + 1) : 0);
     ws->bytes = align_up(off, 256);
     return ws->bytes;
 }
@@ -186,6 +189,8 @@ static int make_tune(const hcsp_opts *o, const hcsp_csr *B, bool need_device, Tu
                                     : (int)std::max<int64_t>(32, std::min<int64_t>(1024, (4ll << 30) / per_slot));
     if (t->dense_slots < 4) t->dense_slots = 4;
     t->dense_slots &= ~3;
+    t->win_log2 = o->win_chunk_log2 ? o->win_chunk_log2 : kWinLog2Default;
+    if (t->win_log2 < 4 || t->win_log2 > 30) return fail(HCSP_E_INVALID, "opts.win_chunk_log2 must be 0 or in 4..30");
     // and never more than 16 GiB
     while (t->dense_slots > 4 && (int64_t)t->dense_slots * per_slot > (16ll << 30)) t->dense_slots -= 4;
     return HCSP_OK;
@@ -283,6 +288,10 @@ static SpArgs base_args(const hcsp_operand *A, const hcsp_csr *B, const Workspac
     a.dense_bits = ws.dense_bits;
     a.dense_vals = ws.dense_vals;
     a.dense_words = ws.dense_words;
+    a.probes = ws.probes;
+    a.chunk_cnt = ws.chunk_cnt;
+    a.win_base = ws.win_base;
+    a.win_log2 = tu.win_log2;
     a.ncols = B->ncols;
     a.unit_lo = 0;
     a.unit_hi = INT64_MAX;
@@ -339,6 +348,14 @@ static void geometry(int64_t wave_bytes, int64_t count, int *blocks, int *thread
     *blocks = (int)((count + wpb - 1) / wpb);
 }
 
+// Blocks (one wavefront each) of a column-window launch: as many as the
+// compute units hold at once (the (row, chunk) pairs are counted on the GPU).
+static int win_blocks(int64_t wave_bytes)
+{
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(32, (160 * 1024) / std::max<int64_t>(wave_bytes, 1)));
+    return (int)(per_cu * cu_count());
+}
+
 static int ensure_lds(size_t lds, int64_t budget)
 {
     if ((int64_t)lds > budget) return fail(HCSP_E_UNSUPPORTED, "shared-memory table larger than the device allows");
@@ -378,7 +395,7 @@ static size_t layout_batch(int32_t count, int64_t units, int64_t row_ptr_len, in
     b->sym_begin = (int64_t *)take(8 * HCSP_MAX_BINS);
     b->num_begin = (int64_t *)take(8 * HCSP_MAX_BINS);
     off = align_up(off, 256);
-    const size_t rest = layout_workspace(units, row_ptr_len, max_ncols, dense_slots, base ? base + off : nullptr, &b->w);
+    const size_t rest = layout_workspace(units, row_ptr_len, max_ncols, dense_slots, false, base ? base + off : nullptr, &b->w);
     return off + rest;
 }
 
@@ -513,7 +530,7 @@ int hcsp_spgemm_workspace(const hcsp_operand *A, const hcsp_csr *B, const hcsp_o
     rc = make_tune(opts, B, false, &tu);
     if (rc) return rc;
     Workspace ws;
-    *bytes = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, nullptr, &ws);
+    *bytes = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, nullptr, &ws);
     return HCSP_OK;
 }
 
@@ -533,7 +550,7 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, (char *)ws_d, &ws);
+    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, (char *)ws_d, &ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     hipStream_t s = (hipStream_t)stream;
     std::memset(info, 0, sizeof *info);
@@ -567,6 +584,12 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
         const int64_t c = cnt[b];
         a.bin_begin = begin[b];
         a.count = c;
+        if (b == kSymGlobal && !v.cluster) {
+            HCSP_HIP(launch_win_prep(true, a, t));
+            HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, t));
+            HCSP_HIP(launch_sym_win(a, win_blocks(win_sym_wave_bytes()), t));
+            return HCSP_OK;
+        }
         if (b == kSymGlobal) {
             const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
             HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, t));
@@ -601,6 +624,7 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     for (int b = 0; b < kNumBins; ++b) info->num_bin_count[b] = ncnt[b];
     info->lanes = tu.G;
     info->load_pct = tu.load_pct;
+    info->win_chunk_log2 = tu.win_log2;
     info->valid = 1;
     return HCSP_OK;
 }
@@ -628,10 +652,10 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
     Tune tu;
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
-    if (tu.G != info->lanes || tu.load_pct != info->load_pct)
+    if (tu.G != info->lanes || tu.load_pct != info->load_pct || tu.win_log2 != info->win_chunk_log2)
         return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
     Workspace ws;
-    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, (char *)ws_d, &ws);
+    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, (char *)ws_d, &ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     hipStream_t s = (hipStream_t)stream;
     hcsp_opts z;
@@ -679,6 +703,12 @@ static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, cons
         const int64_t c = info->num_bin_count[b];
         a.bin_begin = begin[b];
         a.count = c;
+        if (b == kNumGlobal && !cluster) {
+            HCSP_HIP(launch_win_prep(false, a, st));
+            HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, st));
+            HCSP_HIP(launch_num_win(a, win_blocks(win_num_wave_bytes()), st));
+            return HCSP_OK;
+        }
         if (b == kNumGlobal) {
             const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
             HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, st));
@@ -712,9 +742,9 @@ static int numeric_setup(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
         return fail(HCSP_E_INVALID, "info is not from a matching symbolic call");
     rc = make_tune(opts, B, true, tu);
     if (rc) return rc;
-    if (tu->G != info->lanes || tu->load_pct != info->load_pct)
+    if (tu->G != info->lanes || tu->load_pct != info->load_pct || tu->win_log2 != info->win_chunk_log2)
         return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
-    const size_t need = layout_workspace(v->nunits, v->nrows, B->ncols, tu->dense_slots, (char *)ws_d, ws);
+    const size_t need = layout_workspace(v->nunits, v->nrows, B->ncols, tu->dense_slots, !v->cluster, (char *)ws_d, ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     return HCSP_OK;
 }
@@ -873,7 +903,7 @@ int hcsp_predicted_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_op
     rc = make_tune(opts, B, false, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, nullptr, &ws);
+    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, nullptr, &ws);
     PredWs p;
     *bytes = layout_pred(base, v.nrows, pred_entries(ratio, products, v.nrows), nullptr, &p);
     return HCSP_OK;
@@ -898,7 +928,7 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, (char *)ws_d, &ws);
+    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, (char *)ws_d, &ws);
     PredWs pw;
     const size_t need = layout_pred(base, v.nrows, pred_entries(ratio, products, v.nrows), (char *)ws_d, &pw);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "predicted-size workspace too small");

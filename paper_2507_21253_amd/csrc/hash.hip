@@ -198,12 +198,57 @@ int64_t num_wave_bytes(bool cl, int sclass, int T, int load_pct)
 }
 
 // ---------------------------------------------------------------- rounds
-// Loads the next round of items into LDS: lane i takes column q0+i of the
-// unit; the non-empty ones are compacted, their products laid out back to
-// back (positions P), and a start bit set at each P.  For a cluster's numeric
-// phase lane i also keeps the column's member values (areg, or aval[i*S ..]).  An item longer than
-// what fits is cut and resumed in the next round (q0, off0 advance).
-// Returns the number of products in the round.
+// Lays out one round from the items the lanes hold (lane i: column q0+i of
+// the unit, its first product bs in B, its product count bl and its record
+// words rx, ry): the non-empty ones are compacted, their products laid out
+// back to back (positions P), and a start bit set at each P.  An item longer
+// than what fits is cut and resumed in the next round (q0, off0 advance;
+// off0 products of the item at q0 were taken by earlier rounds).  Returns the
+// number of products in the round.
+__device__ __forceinline__ int flatten_round(int64_t it1, int64_t &q0, int &off0, ItemRec *items, uint64_t *sbits,
+                                             int64_t bs, int bl, uint32_t rx, uint32_t ry)
+{
+    const int lane = (int)__lane_id();
+    if (lane == 0) {
+        bs += off0;
+        bl -= off0;
+    }
+    const int blc = min(bl, kRoundW);
+    const int incl = wave_incl_scan(blc);
+    const int P = incl - blc;
+    const int E = uniform(min(__shfl(incl, 63), kRoundW));
+    const bool in = blc > 0 && P < kRoundW;
+    const uint64_t inb = __ballot(in);
+    if (in) {
+        ItemRec r;
+        r.bs = (uint32_t)bs;
+        r.P = P;
+        r.x = rx;
+        r.y = ry;
+        items[__popcll(inb & lanemask_lt(lane))] = r;
+        atomicOr((unsigned long long *)&sbits[P >> 6], 1ull << (P & 63));
+    }
+    const uint64_t cutb = __ballot(in && (int64_t)P + bl > kRoundW);
+    if (cutb) {
+        const int cl = __ffsll((unsigned long long)cutb) - 1;
+        const int used = kRoundW - __shfl(P, cl);
+        off0 = (cl == 0 ? off0 : 0) + used;
+        q0 += cl;
+    } else {
+        const uint64_t rest = __ballot(!in && blc > 0);
+        if (rest) {
+            q0 += __ffsll((unsigned long long)rest) - 1;
+        } else {
+            q0 = min(q0 + 64, it1);
+        }
+        off0 = 0;
+    }
+    return E;
+}
+
+// Loads the next round of a unit's items into LDS: lane i takes column q0+i
+// of the unit (every product of row k of B).  For a cluster's numeric phase
+// lane i also keeps the column's member values (areg, or aval[i*S ..]).
 template <bool CL, int S, bool NUM>
 __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, int64_t &q0, int &off0,
                                           ItemRec *items, uint64_t *sbits, double *aval, double *areg)
@@ -236,47 +281,12 @@ __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, in
             }
         }
     }
-    if (lane == 0) {
-        bs += off0;
-        bl -= off0;
-    }
-    const int blc = min(bl, kRoundW);
-    const int incl = wave_incl_scan(blc);
-    const int P = incl - blc;
-    const int E = uniform(min(__shfl(incl, 63), kRoundW));
-    const bool in = blc > 0 && P < kRoundW;
-    const uint64_t inb = __ballot(in);
-    if (in) {
-        ItemRec r;
-        r.bs = (uint32_t)bs;
-        r.P = P;
-        if (CL && S > 1) {
-            r.x = m;
-            r.y = (uint32_t)lane;
-        } else {
-            const uint64_t ab = (uint64_t)__double_as_longlong(a1);
-            r.x = (uint32_t)ab;
-            r.y = (uint32_t)(ab >> 32);
-        }
-        items[__popcll(inb & lanemask_lt(lane))] = r;
-        atomicOr((unsigned long long *)&sbits[P >> 6], 1ull << (P & 63));
-    }
-    const uint64_t cutb = __ballot(in && (int64_t)P + bl > kRoundW);
-    if (cutb) {
-        const int cl = __ffsll((unsigned long long)cutb) - 1;
-        const int used = kRoundW - __shfl(P, cl);
-        off0 = (cl == 0 ? off0 : 0) + used;
-        q0 += cl;
-    } else {
-        const uint64_t rest = __ballot(!in && blc > 0);
-        if (rest) {
-            q0 += __ffsll((unsigned long long)rest) - 1;
-        } else {
-            q0 = min(q0 + 64, v.it1);
-        }
-        off0 = 0;
-    }
-    return E;
+    // record words: a cluster's member mask and the lane holding its values,
+    // else the two halves of a_ik
+    const uint64_t ab = (uint64_t)__double_as_longlong(a1);
+    const uint32_t rx = CL && S > 1 ? m : (uint32_t)ab;
+    const uint32_t ry = CL && S > 1 ? (uint32_t)lane : (uint32_t)(ab >> 32);
+    return flatten_round(v.it1, q0, off0, items, sbits, bs, bl, rx, ry);
 }
 
 // One lane's share of one pass: its entry of the flattened product list.
@@ -946,6 +956,422 @@ hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int block
     else if (cluster) hipLaunchKernelGGL((k_num_gm<true, false>), dim3(blocks), dim3(256), lds, s, a);
     else if (batch) hipLaunchKernelGGL((k_num_gm<false, true>), dim3(blocks), dim3(256), lds, s, a);
     else hipLaunchKernelGGL((k_num_gm<false, false>), dim3(blocks), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+// ================================================================ column windows
+// CSR rows whose tables do not fit in shared memory.  A row's output columns
+// are cut into chunks of equal column range (more for rows with more
+// products, win_nchunks), and each chunk into
+// windows [w0, w1) that one wavefront takes one after another with a
+// shared-memory table.  A window's products are the entries of the rows of
+// B that fall inside it (found by binary search, the rows of B being sorted),
+// walked in ascending k as everywhere else, so every output entry still
+// receives its products in ascending k, one fma each from +0.0.  Window widths
+// follow the density of output columns seen so far; a window whose keys do
+// not fit is redone at half the width (a window of one column always fits).
+// The chunks of a row run on different wavefronts (neighbouring blocks, one
+// XCD): the symbolic phase counts each chunk's columns, and the numeric phase
+// writes a chunk's entries after those of the chunks before it.
+
+// First position in [lo, hi) of B's columns whose column is >= x (hi if none).
+__device__ __forceinline__ uint32_t lower_bound_col(const int32_t *col, uint32_t lo, uint32_t hi, int x)
+{
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ld_col(col, mid) < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Loads the next round of a CSR row's items for the window [w0, w1): lane i
+// takes column q0+i of the row and the part of row k of B inside the window.
+template <bool NUM>
+__device__ __forceinline__ int load_round_win(const SpArgs &a, int64_t it1, int64_t &q0, int &off0, ItemRec *items,
+                                              uint64_t *sbits, int w0, int w1)
+{
+    const int lane = (int)__lane_id();
+    sbits[lane] = 0ull;
+    const int64_t q = q0 + lane;
+    uint32_t lo = 0, hi = 0;
+    double a1 = 0.0;
+    if (q < it1) {
+        const int k = a.a_col[q];
+        lo = (uint32_t)a.b_rp[k];
+        hi = (uint32_t)a.b_rp[k + 1];
+        if (lo < hi && ld_col(a.b_col, lo) < w0) lo = lower_bound_col(a.b_col, lo + 1, hi, w0);
+        if (lo < hi && ld_col(a.b_col, hi - 1) >= w1) hi = lower_bound_col(a.b_col, lo, hi - 1, w1);
+        if (NUM) a1 = a.a_val[q];
+    }
+    const uint64_t ab = (uint64_t)__double_as_longlong(a1);
+    return flatten_round(it1, q0, off0, items, sbits, lo, (int)(hi - lo), (uint32_t)ab, (uint32_t)(ab >> 32));
+}
+
+// Window table sizes (slots, powers of two): keys only for the symbolic
+// phase, keys and values for the numeric one; a window aims at half a table
+// of keys.
+constexpr int kWinSymLog2T = 12;
+constexpr int kWinNumLog2T = 11;
+constexpr int kWinBuckets = 1 << (kWinNumLog2T - 1);  // rank buckets of a numeric window
+
+// Numeric window layout: the table (keys, values, a dummy slot each), the
+// rank buckets (bucket ends, then starts) and the keys in bucket order.
+struct WinNumLayout {
+    int keys, vals, bend, arr, items, sbits, bytes;
+    __host__ __device__ WinNumLayout()
+    {
+        constexpr int T = 1 << kWinNumLog2T;
+        keys = 0;
+        vals = align16(4 * (T + 1));
+        bend = align16(vals + 8 * (T + 1));
+        arr = align16(bend + 4 * (kWinBuckets + 1));
+        items = align16(arr + 4 * T);
+        sbits = items + 16 * 64;
+        bytes = align16(sbits + 8 * kRoundPasses);
+    }
+};
+
+int64_t win_sym_wave_bytes() { return SymLayout(0, 1 << kWinSymLog2T).bytes; }
+int64_t win_num_wave_bytes() { return WinNumLayout().bytes; }
+
+// Distinct output columns of CSR row [it0, it1) inside [w0, w1), or -1 when
+// the table got too full for another batch of passes (window too wide).
+__device__ __forceinline__ int sym_window(const SpArgs &a, int64_t it0, int64_t it1, int w0, int w1,
+                                          unsigned char *base)
+{
+    constexpr int T = 1 << kWinSymLog2T, kR = 8;
+    const int lane = (int)__lane_id();
+    const SymLayout L(0, T);
+    int *keys = (int *)(base + L.keys);
+    ItemRec *items = (ItemRec *)(base + L.items);
+    uint64_t *sbits = (uint64_t *)(base + L.sbits);
+    lds_fill(keys, 4 * T, (uint32_t)kEmpty);
+    if (lane == 0) keys[T] = kDummyKey;
+    const uint64_t le = lanemask_le(lane);
+    int total = 0;  // keys in the table (wave-uniform)
+    int64_t q0 = it0;
+    int off0 = 0;
+    // every probe finds a free slot while at most T - 1 keys are in
+    auto probe = [&](int j) {
+        uint32_t h = j == kDummyKey ? (uint32_t)T : ((uint32_t)j * 2654435761u) >> (32 - kWinSymLog2T);
+        int old = atomicCAS(&keys[h], kEmpty, j);
+        while (old != kEmpty && old != j) {
+            h = (h + 1u) & (uint32_t)(T - 1);
+            old = atomicCAS(&keys[h], kEmpty, j);
+        }
+        total += __popcll(__ballot(old == kEmpty && h != (uint32_t)T));
+    };
+    while (q0 < it1) {
+        const int E = load_round_win<false>(a, it1, q0, off0, items, sbits, w0, w1);
+        const int npass = (E + 63) >> 6;
+        int cum = 0;
+        for (int p = 0; p < npass; p += kR) {
+            if (total > T - 1 - 64 * kR) return -1;
+            Pass<false, false> d[kR];
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr) {
+                if (p + rr < npass) {
+                    const uint64_t w = uniform64(sbits[p + rr]);
+                    d[rr] = fetch_pass<false, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                    cum += __popcll(w);
+                } else {
+                    d[rr].j = kDummyKey;
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr)
+                if (p + rr < npass) probe(d[rr].j);
+        }
+    }
+    return total;
+}
+
+// Entries of CSR row [it0, it1) of C inside [w0, w1), written in column
+// order to ccol/cval; returns their number, -1 when the table got too full
+// for another batch of passes (window too wide, nothing written) or -2 when
+// there are more than room of them (nothing written).  Keys are placed by a
+// multiplicative hash; their ranks come from a counting sort over
+// kWinBuckets buckets of equal column range (a bucket's keys are compared
+// with each other only).
+__device__ __forceinline__ int num_window(const SpArgs &a, int64_t it0, int64_t it1, int w0, int w1,
+                                          unsigned char *base, int32_t *ccol, double *cval, int64_t room)
+{
+    constexpr int T = 1 << kWinNumLog2T, kR = 4, NB = kWinBuckets;
+    const int lane = (int)__lane_id();
+    const WinNumLayout L;
+    int *keys = (int *)(base + L.keys);
+    double *vals = (double *)(base + L.vals);
+    int *bend = (int *)(base + L.bend);
+    int *arr = (int *)(base + L.arr);
+    ItemRec *items = (ItemRec *)(base + L.items);
+    uint64_t *sbits = (uint64_t *)(base + L.sbits);
+    lds_fill(keys, 4 * T, (uint32_t)kEmpty);
+    lds_fill(vals, 8 * T, 0u);
+    if (lane == 0) {
+        keys[T] = kDummyKey;
+        vals[T] = 0.0;
+    }
+    const uint64_t le = lanemask_le(lane);
+    int total = 0;  // keys in the table (wave-uniform)
+    // every probe finds a free slot while at most T - 1 keys are in
+    // (idle lanes confirm the dummy key in the dummy slot)
+    auto probe = [&](int j) -> int {
+        uint32_t h = j == kDummyKey ? (uint32_t)T : ((uint32_t)j * 2654435761u) >> (32 - kWinNumLog2T);
+        int old = atomicCAS(&keys[h], kEmpty, j);
+        while (old != kEmpty && old != j) {
+            h = (h + 1u) & (uint32_t)(T - 1);
+            old = atomicCAS(&keys[h], kEmpty, j);
+        }
+        total += __popcll(__ballot(old == kEmpty && h != (uint32_t)T));
+        return (int)h;
+    };
+    auto apply = [&](const Pass<false, true> &d, int h, int tf, int tl) {
+        for (int tt = tf; tt <= tl; ++tt) {
+            if (d.t != tt) continue;
+            const double av = *(const double *)&items[tt].x;
+            vals[h] = __fma_rn(av, d.b, vals[h]);
+        }
+    };
+    int64_t q0 = it0;
+    int off0 = 0;
+    while (q0 < it1) {
+        const int E = load_round_win<true>(a, it1, q0, off0, items, sbits, w0, w1);
+        const int npass = (E + 63) >> 6;
+        int cum = 0;
+        for (int p = 0; p < npass; p += kR) {
+            if (total > T - 1 - 64 * kR) return -1;
+            Pass<false, true> d[kR];
+            int tf[kR], tl[kR];
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr) {
+                if (p + rr < npass) {
+                    const uint64_t w = uniform64(sbits[p + rr]);
+                    const int last = min(63, E - 1 - ((p + rr) << 6));
+                    tf[rr] = cum + (int)(w & 1ull) - 1;
+                    tl[rr] = cum + __popcll(w & lanemask_le(last)) - 1;
+                    d[rr] = fetch_pass<false, true>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                    cum += __popcll(w);
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < kR; ++rr)
+                if (p + rr < npass) apply(d[rr], probe(d[rr].j), tf[rr], tl[rr]);
+        }
+    }
+    if (total > room) return -2;
+    // counting sort by bucket: counts, inclusive prefix (bucket ends), keys
+    // placed from each bucket's end down (the ends become the starts)
+    const float bscale = __fdividef((float)NB, (float)(uint32_t)(w1 - w0));
+    auto bucket = [&](int j) -> int {
+        const int b = (int)((float)(uint32_t)(j - w0) * bscale);
+        return b < NB ? b : NB - 1;
+    };
+    lds_fill(bend, 4 * NB, 0u);
+    if (lane == 0) bend[NB] = total;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int c0 = 0; c0 < T; c0 += 64) {
+        const int key = keys[c0 + lane];
+        if (key != kEmpty) atomicAdd(&bend[bucket(key)], 1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    int run = 0;
+    for (int c0 = 0; c0 < NB; c0 += 64) {
+        const int cnt = bend[c0 + lane];
+        const int incl = wave_incl_scan(cnt);
+        bend[c0 + lane] = run + incl;
+        run += __shfl(incl, 63);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int c0 = 0; c0 < T; c0 += 64) {
+        const int key = keys[c0 + lane];
+        if (key != kEmpty) arr[atomicSub(&bend[bucket(key)], 1) - 1] = key;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int c0 = 0; c0 < T; c0 += 64) {
+        const int sidx = c0 + lane;
+        const int key = keys[sidx];
+        if (key == kEmpty) continue;
+        const int b = bucket(key);
+        const int s0 = bend[b], s1 = bend[b + 1];
+        int rank = s0;
+        for (int t = s0; t < s1; ++t) rank += arr[t] < key;
+        ccol[rank] = key;
+        cval[rank] = vals[sidx];
+    }
+    return total;
+}
+
+// Column range of chunk c of nch equal chunks of the output columns [0, ncols).
+__device__ __forceinline__ void win_chunk(int64_t ncols, int nch, int c, int *lo, int *hi)
+{
+    const int64_t cw = (ncols + nch - 1) / nch;
+    *lo = (int)min<int64_t>(ncols, c * cw);
+    *hi = (int)min<int64_t>(ncols, (c + 1) * cw);
+}
+
+// Next window width after a window of width w that held n keys, aiming at
+// tk keys (growing at most 8-fold), within [1, cap].
+__device__ __forceinline__ int64_t win_next(int64_t w, int64_t n, int64_t tk, int64_t cap)
+{
+    const int64_t x = w * tk / max<int64_t>(n, tk / 8);
+    return max<int64_t>(1, min<int64_t>(x, cap));
+}
+
+// Chunks per row of a window launch: rows counted by chunks get
+// win_nchunks(products), rows the shared-memory symbolic phase counted whole
+// (numeric only) one.  base[i] = chunks of the bin's i-th row, base[count] =
+// 0; an exclusive scan then gives each row's first (row, chunk) pair.
+template <bool SYM>
+__global__ void __launch_bounds__(256) k_win_prep(SpArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > a.count) return;
+    if (i == a.count) {
+        a.win_base[i] = 0;
+        return;
+    }
+    const int u = a.order[a.bin_begin + i];
+    a.win_base[i] = SYM || a.ucount[u] == INT32_MAX ? win_nchunks(a.probes[u], a.win_log2) : 1;
+}
+
+// The (row, chunk) pair i of a window launch: p = the largest position with
+// base[p] <= i (base strictly increasing over [0, count]), by a 64-way search
+// of the whole wavefront.
+__device__ __forceinline__ int64_t win_find(const int64_t *base, int64_t count, int64_t i)
+{
+    const int lane = (int)__lane_id();
+    int64_t lo = 0, hi = count;  // answer in [lo, hi)
+    while (hi - lo > 64) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t x = lo + lane * step;
+        const uint64_t b = __ballot(x < hi && base[x] <= i);
+        const int L = 63 - __clzll((long long)b);  // lane 0 always qualifies
+        lo += L * step;
+        hi = min(hi, lo + step);
+    }
+    const int64_t x = lo + lane;
+    const uint64_t b = __ballot(x < hi && base[x] <= i);
+    return lo + (63 - __clzll((long long)b));
+}
+
+// Symbolic: one wavefront per (row, chunk); the chunk's count goes to
+// chunk_cnt and is added to the row's count (zeroed by the binning kernel).
+__global__ void __launch_bounds__(64) k_sym_win(SpArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int64_t tk = (1 << kWinSymLog2T) / 2;
+    const int lane = (int)__lane_id();
+    const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
+    for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
+        const int64_t p = (int64_t)uniform64((uint64_t)win_find(a.win_base, a.count, i));
+        const int64_t b0 = (int64_t)uniform64((uint64_t)a.win_base[p]);
+        const int nch = (int)((int64_t)uniform64((uint64_t)a.win_base[p + 1]) - b0);
+        const int c = (int)(i - b0);
+        const int u = uniform(a.order[a.bin_begin + p]);
+        const int64_t it0 = (int64_t)uniform64((uint64_t)a.a_rp[u]);
+        const int64_t it1 = (int64_t)uniform64((uint64_t)a.a_rp[u + 1]);
+        int lo, hi;
+        win_chunk(a.ncols, nch, c, &lo, &hi);
+        // first width: as if the chunk's share of the products were distinct
+        const int64_t ub = max<int64_t>(1, min<int64_t>((int64_t)uniform64((uint64_t)a.probes[u]) / nch, hi - lo));
+        int64_t width = max<int64_t>(1, min<int64_t>(hi - lo, tk * (hi - lo) / ub));
+        int64_t n = 0;
+        for (int w0 = lo; w0 < hi;) {
+            const int w1 = (int)min<int64_t>(hi, w0 + width);
+            const int k = sym_window(a, it0, it1, w0, w1, smem);
+            if (k < 0) {
+                width = max<int64_t>(1, (w1 - w0) / 2);
+                continue;
+            }
+            n += k;
+            width = win_next(w1 - w0, k, tk, hi - lo);
+            w0 = w1;
+        }
+        if (lane == 0) {
+            a.chunk_cnt[(int64_t)u * kWinChunksMax + c] = (int32_t)n;
+            if (n) atomicAdd((unsigned long long *)&a.c_rp[u], (unsigned long long)n);
+            if (c == 0) a.ucount[u] = INT32_MAX;
+        }
+    }
+}
+
+// Numeric: one wavefront per (row, chunk) for rows counted by chunks (count
+// INT32_MAX); a row counted whole by the shared-memory symbolic phase is one
+// chunk over its column range [keylo, keyhi].
+__global__ void __launch_bounds__(64) k_num_win(SpArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int64_t tk = (1 << kWinNumLog2T) / 2;
+    const int lane = (int)__lane_id();
+    const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
+    for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
+        const int64_t p = (int64_t)uniform64((uint64_t)win_find(a.win_base, a.count, i));
+        const int64_t b0 = (int64_t)uniform64((uint64_t)a.win_base[p]);
+        const int nch = (int)((int64_t)uniform64((uint64_t)a.win_base[p + 1]) - b0);
+        const int c = (int)(i - b0);
+        const int u = uniform(a.order[a.bin_begin + p]);
+        if (u < a.unit_lo || u >= a.unit_hi) continue;
+        const bool chunked = uniform(a.ucount[u]) == INT32_MAX;
+        const int64_t it0 = (int64_t)uniform64((uint64_t)a.a_rp[u]);
+        const int64_t it1 = (int64_t)uniform64((uint64_t)a.a_rp[u + 1]);
+        int64_t off = (int64_t)uniform64((uint64_t)a.c_rp[u]) - a.out_base;
+        int64_t kc;
+        int lo, hi;
+        if (chunked) {
+            win_chunk(a.ncols, nch, c, &lo, &hi);
+            // this chunk's entries follow those of the chunks before it
+            const int32_t *cc = a.chunk_cnt + (int64_t)u * kWinChunksMax;
+            int64_t before = 0;
+            for (int x = lane; x < c; x += 64) before += cc[x];
+            for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o);
+            off += (int64_t)uniform64((uint64_t)before);
+            kc = uniform(cc[c]);
+        } else {
+            lo = uniform(a.keylo[u]);
+            hi = uniform(a.keyhi[u]) + 1;
+            kc = (int64_t)uniform64((uint64_t)(a.c_rp[u + 1] - a.c_rp[u]));
+        }
+        if (kc <= 0) continue;
+        if (off < 0 || off + kc > a.cap || lo < 0 || hi > a.ncols || lo >= hi) {
+            if (lane == 0) atomicOr(a.err, kErrCapacity);
+            continue;
+        }
+        int64_t width = max<int64_t>(1, min<int64_t>(hi - lo, (hi - lo) * tk / kc));
+        int64_t done = 0;
+        for (int w0 = lo; w0 < hi;) {
+            const int w1 = (int)min<int64_t>(hi, w0 + width);
+            const int k = num_window(a, it0, it1, w0, w1, smem, a.c_col + off + done, a.c_val + off + done, kc - done);
+            if (k == -1) {
+                width = max<int64_t>(1, (w1 - w0) / 2);
+                continue;
+            }
+            if (k < 0) break;
+            done += k;
+            width = win_next(w1 - w0, k, tk, hi - lo);
+            w0 = w1;
+        }
+        if (lane == 0 && done != kc) atomicOr(a.err, kErrCount);
+    }
+}
+
+hipError_t launch_win_prep(bool sym, const SpArgs &a, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((a.count + 1 + 255) / 256);
+    if (sym) hipLaunchKernelGGL(k_win_prep<true>, dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_win_prep<false>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_win(const SpArgs &a, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sym_win, dim3(blocks), dim3(64), (size_t)win_sym_wave_bytes(), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_num_win(const SpArgs &a, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_num_win, dim3(blocks), dim3(64), (size_t)win_num_wave_bytes(), s, a);
     return hipGetLastError();
 }
 

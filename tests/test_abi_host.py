@@ -126,6 +126,15 @@ def test_workspace_query_is_host_only():
     n = ctypes.c_size_t()
     rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b), None, ctypes.byref(n))
     assert rc == 0 and n.value > 0
+    # CSR rows too long for shared memory take the column-window path: per-row
+    # chunk counts in the workspace instead of dense accumulators
+    for bad in (3, 31, -1):
+        rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b),
+                                            ctypes.byref(hc.opts(win_chunk_log2=bad)), ctypes.byref(n))
+        assert rc == -1 and "win_chunk_log2" in hc.last_error()
+    rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b), ctypes.byref(hc.opts(win_chunk_log2=4)),
+                                        ctypes.byref(n))
+    assert rc == 0
     b.nrows = 49                                      # A.ncols != B.nrows
     rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b), None, ctypes.byref(n))
     assert rc == -1 and "B.nrows" in hc.last_error()

@@ -1,0 +1,140 @@
+"""GPU parity of the column-window path: CSR rows whose output is too large
+for one shared-memory table are cut into column chunks (one wavefront each)
+and every chunk into windows that fit a table; C must still equal the
+oracle bit for bit, since every output entry gets its products in ascending k.
+
+Cases: rows counted by chunks in the symbolic phase (products beyond the
+largest symbolic table), with one chunk or up to 256 (win_chunk_log2 sets
+the products per chunk); rows counted whole in shared memory but too large
+for the numeric tables (one chunk over the row's column range); output
+columns packed densely into part of a chunk, so that first windows overflow
+and are redone narrower in both phases; row panels; R-MAT rows; a numeric
+call whose chunking differs from its symbolic call's is refused."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2507_21253_amd as hc  # noqa: E402
+
+
+def product(A, B, o=None):
+    torch.cuda.synchronize()
+    C = hc.spgemm(hc.DeviceCSR.from_host(A), hc.DeviceCSR.from_host(B), o)
+    torch.cuda.synchronize()
+    return C.to_host()
+
+
+def assert_same(Cg, Cr, where=""):
+    np.testing.assert_array_equal(Cg.rp, Cr.rp, err_msg="row_ptr " + where)
+    np.testing.assert_array_equal(Cg.col, Cr.col, err_msg="col " + where)
+    np.testing.assert_array_equal(Cg.val, Cr.val, err_msg="val " + where)
+
+
+def csr_from_rows(rows, ncols, rng):
+    rp = np.zeros(len(rows) + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.concatenate([np.sort(r) for r in rows]).astype(np.int32) if rows else np.zeros(0, np.int32)
+    val = rng.uniform(-1, 1, len(col))
+    return synth.HostCSR(rp, col, val, len(rows), ncols)
+
+
+def packed_case(seed, dense_cols, ncols=80_000, m=30, n=40):
+    """B's rows hold most columns of [0, dense_cols) and a few spread ones, so
+    the output columns crowd into the start of the first chunk."""
+    rng = np.random.default_rng(seed)
+    brows = [np.concatenate([rng.choice(dense_cols, dense_cols - 100, replace=False),
+                             rng.choice(np.arange(dense_cols, ncols), 50, replace=False)]) for _ in range(m)]
+    arows = [rng.choice(m, int(rng.integers(0, 16)), replace=False) for _ in range(n)]
+    return csr_from_rows(arows, m, rng), csr_from_rows(brows, ncols, rng)
+
+
+@pytest.mark.parametrize("dense_cols", [2_300, 4_000])
+def test_packed_columns_force_narrower_windows(dense_cols):
+    A, B = packed_case(dense_cols, dense_cols)
+    assert_same(product(A, B), oracle.spgemm(A, B), "default tables")
+    # every row on the window path, through both phases, with one chunk per
+    # row and with many
+    for log2 in (30, 8):
+        o = hc.opts(sym_tmax_log2=7, num_tmax=96, win_chunk_log2=log2)
+        assert_same(product(A, B, o), oracle.spgemm(A, B), "forced, chunks of 2^%d products" % log2)
+
+
+def test_rows_counted_whole_then_windowed():
+    # symbolic tables large enough for every row, numeric tables too small:
+    # the numeric phase takes each row as one chunk over its column range
+    A = synth.uniform(400, 300, 24, 31)
+    B = synth.uniform(300, 5000, 40, 32)
+    o = hc.opts(num_tmax=96)
+    assert_same(product(A, B, o), oracle.spgemm(A, B))
+
+
+@pytest.mark.parametrize("scale", [11, 13])
+def test_rmat_window_path_bitwise(scale):
+    R = synth.rmat(scale, 16, 0.57, 0.19, 0.19, 5)
+    ref = oracle.spgemm(R, R)
+    assert_same(product(R, R), ref, "default")
+    assert_same(product(R, R, hc.opts(sym_tmax_log2=8, num_tmax=128)), ref, "small tables")
+    assert_same(product(R, R, hc.opts(sym_tmax_log2=8, num_tmax=128, win_chunk_log2=6)), ref, "many chunks")
+
+
+def test_window_rows_in_panels():
+    R = synth.rmat(11, 16, 0.57, 0.19, 0.19, 6)
+    D = hc.DeviceCSR.from_host(R)
+    o0 = hc.opts(sym_tmax_log2=7, num_tmax=96, win_chunk_log2=7)
+    P = hc.Product(D, D, o0)
+    nnz = P.symbolic()
+    rp = P.C_row_ptr.cpu().numpy()
+    col = np.empty(nnz, np.int32)
+    val = np.empty(nnz)
+    cuts = [0, 1, 700, 701, 1500, R.nrows]
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        base, end = int(rp[lo]), int(rp[hi])
+        bc = torch.empty(max(end - base, 1), dtype=torch.int32, device="cuda")
+        bv = torch.empty(max(end - base, 1), dtype=torch.float64, device="cuda")
+        o = hc.opts(sym_tmax_log2=7, num_tmax=96, win_chunk_log2=7, unit_lo=lo, unit_hi=hi, out_base=base,
+                    flags=hc.F_SYNC_CHECK)
+        hc.spgemm_numeric(D, D, P.info, P.C_row_ptr, bc, bv, P.ws, o, capacity=end - base)
+        col[base:end] = bc[:end - base].cpu().numpy()
+        val[base:end] = bv[:end - base].cpu().numpy()
+    ref = oracle.spgemm(R, R)
+    np.testing.assert_array_equal(rp, ref.rp)
+    np.testing.assert_array_equal(col, ref.col)
+    np.testing.assert_array_equal(val, ref.val)
+
+
+def test_window_capacity_too_small_is_reported():
+    A, B = packed_case(7, 2_300)
+    Ad, Bd = hc.DeviceCSR.from_host(A), hc.DeviceCSR.from_host(B)
+    P = hc.Product(Ad, Bd)
+    nnz = P.symbolic()
+    assert nnz > 10
+    small = nnz // 2
+    col = torch.zeros(small, dtype=torch.int32, device="cuda")
+    val = torch.zeros(small, dtype=torch.float64, device="cuda")
+    with pytest.raises(hc.HcspError):
+        hc.spgemm_numeric(Ad, Bd, P.info, P.C_row_ptr, col, val, P.ws, hc.opts(flags=hc.F_SYNC_CHECK),
+                          capacity=small)
+
+
+def test_numeric_with_other_chunking_is_refused():
+    A, B = packed_case(8, 2_300)
+    Ad, Bd = hc.DeviceCSR.from_host(A), hc.DeviceCSR.from_host(B)
+    P = hc.Product(Ad, Bd, hc.opts(win_chunk_log2=8))
+    nnz = P.symbolic()
+    col = torch.zeros(nnz, dtype=torch.int32, device="cuda")
+    val = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+    with pytest.raises(hc.HcspError):
+        hc.spgemm_numeric(Ad, Bd, P.info, P.C_row_ptr, col, val, P.ws, hc.opts(win_chunk_log2=9), capacity=nnz)
+    hc.spgemm_numeric(Ad, Bd, P.info, P.C_row_ptr, col, val, P.ws, hc.opts(win_chunk_log2=8, flags=hc.F_SYNC_CHECK),
+                      capacity=nnz)
+    ref = oracle.spgemm(A, B)
+    np.testing.assert_array_equal(col.cpu().numpy(), ref.col)
+    np.testing.assert_array_equal(val.cpu().numpy(), ref.val)
