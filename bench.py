@@ -15,7 +15,9 @@ comparison.  Clustering itself (host plan + device CSR_Cluster build) is
 preprocessing, timed once and reported in units of one SpGEMM.
 
 Prints one JSON line.  ``--mode copy`` runs only a plain device copy of known
-size (the calibration run for hardware byte counters).
+size (the calibration run for hardware byte counters); ``--mode batch``,
+``--mode tallskinny`` and ``--mode rmat`` measure the batched products, the
+square x tall-skinny products and the power-law R-MAT product.
 """
 from __future__ import annotations
 
@@ -59,13 +61,17 @@ def parse():
     p.add_argument("--symmetric", action="store_true",
                    help="permute M symmetrically (rows and columns; B reordered too) instead of A's rows only")
     p.add_argument("--lanes", type=int, default=0)
-    p.add_argument("--mode", choices=["bench", "copy", "batch", "tallskinny"], default="bench",
+    p.add_argument("--mode", choices=["bench", "copy", "batch", "tallskinny", "rmat"], default="bench",
                    help="bench: the stencil workload (the headline line); batch: 512 uneven products replayed "
                         "as one captured graph; tallskinny: the stencil times 10 BFS frontier matrices; copy: "
                         "device copy for counter calibration")
     p.add_argument("--sources", type=int, default=512, help="tallskinny: BFS sources (columns of B)")
     p.add_argument("--iterations", type=int, default=10, help="tallskinny: frontier matrices (BFS levels 1..)")
     p.add_argument("--batch-count", type=int, default=512)
+    p.add_argument("--rmat-scale", type=int, default=20, help="rmat: scale of the full product (numeric in panels)")
+    p.add_argument("--rmat-cluster-scale", type=int, default=18,
+                   help="rmat: scale of the plain vs clustered comparison (C held whole)")
+    p.add_argument("--panel-gb", type=float, default=32.0, help="rmat: C panel buffer size")
     p.add_argument("--load-pct", type=int, default=0, help="numeric table fill target (0: autotuned)")
     p.add_argument("--sym-load-pct", type=int, default=0, help="symbolic table fill bound (0: autotuned)")
     p.add_argument("--untuned", action="store_true", help="ignore the autotuner's table")
@@ -182,6 +188,109 @@ def tallskinny_mode(args):
            "preprocessing_host_s": round(t_prep, 3),
            "preprocessing_in_products": round(t_prep * 1e3 / (tot["clustered"] / len(Bs)), 1),
            "per_iteration": rows}
+    print(json.dumps(out), flush=True)
+
+def rmat_panels(D, hc, torch, panel_entries, steps, warmup):
+    """C = A*A for an A too large to hold C: symbolic over all rows, C's row offsets read back, then the
+    numeric phase in row panels of at most panel_entries entries written one after another into one
+    reused buffer.  Returns (ms per product, symbolic ms, numeric ms, nnz(C), panels)."""
+    ws = torch.empty(hc.spgemm_workspace(D, D), dtype=torch.uint8, device="cuda")
+    crp = torch.empty(D.nrows + 1, dtype=torch.int64, device="cuda")
+    info = hc.spgemm_symbolic(D, D, crp, ws)
+    nnz = int(info.nnz)
+    cap = int(min(panel_entries, max(nnz, 1)))
+    col = torch.empty(cap, dtype=torch.int32, device="cuda")
+    val = torch.empty(cap, dtype=torch.float64, device="cuda")
+
+    def one():
+        t0 = time.perf_counter()
+        inf = hc.spgemm_symbolic(D, D, crp, ws)
+        rp = crp.cpu().numpy()
+        t1 = time.perf_counter()
+        lo, np_ = 0, 0
+        while lo < D.nrows:
+            hi = int(np.searchsorted(rp, rp[lo] + cap, side="right")) - 1
+            hi = max(hi, lo + 1)
+            if rp[hi] - rp[lo] > cap:
+                raise RuntimeError("row %d alone exceeds the panel buffer" % lo)
+            hc.spgemm_numeric(D, D, inf, crp, col, val, ws, hc.opts(unit_lo=lo, unit_hi=hi, out_base=int(rp[lo])),
+                              capacity=cap)
+            lo, np_ = hi, np_ + 1
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return (t2 - t0) * 1e3, (t1 - t0) * 1e3, (t2 - t1) * 1e3, np_
+
+    for _ in range(warmup):
+        one()
+    runs = [one() for _ in range(steps)]
+    del col, val, ws
+    torch.cuda.empty_cache()
+    return (float(np.mean([r[0] for r in runs])), float(np.mean([r[1] for r in runs])),
+            float(np.mean([r[2] for r in runs])), nnz, runs[0][3])
+
+
+def rmat_mode(args):
+    """The power-law workload: R-MAT (edge factor 16, a=0.57, b=c=0.19, seed 4; self-loops dropped,
+    symmetrised, de-duplicated, values 1.0), C = A*A.  At the full scale C does not fit one GPU (about 2.4e10
+    entries), so the symbolic phase runs over all rows and the numeric phase in row panels (one reused
+    buffer): each step is symbolic + read-back + every panel.  At a smaller scale, where C fits, plain CSR is
+    compared with CSR_Cluster (rows in RCM order, hierarchical clusters with the candidate search on the GPU)."""
+    import torch
+    import paper_2507_21253_amd as hc
+    import synth
+    out = {}
+    R = synth.workload_rmat(args.rmat_scale, 4)
+    rl = np.diff(R.rp)
+    products = int(rl[R.col].sum())
+    D = hc.DeviceCSR.from_host(R)
+    panel_entries = int(args.panel_gb * 1e9 / 12)
+    ms, sym, num, nnz, npan = rmat_panels(D, hc, torch, panel_entries, max(1, min(args.steps, 3)),
+                                          min(args.warmup, 1))
+    log("rmat%d: %d rows, nnz %d, products %d, nnz(C) %d: %.1f ms (symbolic %.1f, numeric %.1f in %d panels)"
+        % (args.rmat_scale, R.nrows, R.nnz, products, nnz, ms, sym, num, npan))
+    out.update({"metric": "SpGEMM GFLOP/s, R-MAT C = A*A (numeric in row panels)",
+                "value": round(2 * products / (ms * 1e-3) / 1e9, 3), "unit": "GFLOP/s", "n_gpus": 1,
+                "steps": max(1, min(args.steps, 3)), "warmup": min(args.warmup, 1), "ms_per_step": round(ms, 2),
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                "data": "synthetic",
+                "config": {"workload": "rmat%d_ef16_A2" % args.rmat_scale, "nrows": R.nrows, "nnz_A": R.nnz,
+                           "products": products, "nnz_C": nnz, "panels": npan, "panel_gb": args.panel_gb},
+                "phases_ms": {"symbolic_incl_readback": round(sym, 2), "numeric_all_panels": round(num, 2)}})
+    del D
+    torch.cuda.empty_cache()
+    # plain vs clustered where C fits
+    sc = args.rmat_cluster_scale
+    R = synth.workload_rmat(sc, 4)
+    rl = np.diff(R.rp)
+    products = int(rl[R.col].sum())
+    D = hc.DeviceCSR.from_host(R)
+    P = hc.Product(D, D)
+    w_pl, s_pl, n_pl = time_product(P, max(1, min(args.steps, 3)), 1, torch)
+    nnz = P.info.nnz
+    ref_rp, ref_col = P.C_row_ptr.clone(), P.C_col[:nnz].clone()
+    ref_val = P.C_val[:nnz].view(torch.int64).clone()
+    del P
+    torch.cuda.empty_cache()
+    mc = args.max_cluster or 2
+    t = time.perf_counter()
+    perm = hc.order_rcm(R)
+    plan = hc.plan_hierarchical_gpu(R, D, (3, 10), mc, hc.SIM_ROOT, perm_in=perm)
+    t_prep = time.perf_counter() - t
+    Dc = hc.cluster_build(D, plan)
+    Pc = hc.Product(Dc, D)
+    w_cl, s_cl, n_cl = time_product(Pc, max(1, min(args.steps, 3)), 1, torch)
+    same = bool(Pc.info.nnz == nnz and torch.equal(Pc.C_row_ptr, ref_rp) and torch.equal(Pc.C_col[:nnz], ref_col)
+                and torch.equal(Pc.C_val[:nnz].view(torch.int64), ref_val))
+    log("rmat%d: plain %.1f ms (sym %.1f, num %.1f); clustered %.1f ms (sym %.1f, num %.1f), %d clusters, "
+        "equal %s, plan %.1f s" % (sc, w_pl, s_pl, n_pl, w_cl, s_cl, n_cl, plan.nclusters, same, t_prep))
+    out["clustered_comparison"] = {
+        "workload": "rmat%d_ef16_A2" % sc, "products": products, "nnz_C": int(nnz),
+        "plain_ms": round(w_pl, 2), "plain_gflops": round(2 * products / (w_pl * 1e-3) / 1e9, 3),
+        "plain_phases_ms": [round(s_pl, 2), round(n_pl, 2)],
+        "clustered_ms": round(w_cl, 2), "clustered_gflops": round(2 * products / (w_cl * 1e-3) / 1e9, 3),
+        "clustered_phases_ms": [round(s_cl, 2), round(n_cl, 2)],
+        "reorder": "rcm rows", "clustering": "hierarchical (candidates on the GPU)", "max_cluster": mc,
+        "nclusters": int(plan.nclusters), "plan_s": round(t_prep, 2), "clustered_equals_plain_bitwise": same}
     print(json.dumps(out), flush=True)
 
 
@@ -312,6 +421,9 @@ def main():
         return
     if args.mode == "tallskinny":
         tallskinny_mode(args)
+        return
+    if args.mode == "rmat":
+        rmat_mode(args)
         return
     import paper_2507_21253_amd as hc
     import synth

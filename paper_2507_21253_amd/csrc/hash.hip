@@ -1011,8 +1011,8 @@ __device__ __forceinline__ int load_round_win(const SpArgs &a, int64_t it1, int6
 // Window table sizes (slots, powers of two): keys only for the symbolic
 // phase, keys and values for the numeric one; a window aims at half a table
 // of keys.
-constexpr int kWinSymLog2T = 12;
-constexpr int kWinNumLog2T = 11;
+constexpr int kWinSymLog2T = 11;
+constexpr int kWinNumLog2T = 10;
 constexpr int kWinBuckets = 1 << (kWinNumLog2T - 1);  // rank buckets of a numeric window
 
 // Numeric window layout: the table (keys, values, a dummy slot each), the
