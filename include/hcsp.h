@@ -129,16 +129,17 @@ typedef struct hcsp_opts {
     int64_t unit_lo;        /* numeric: first unit (row of a CSR A, cluster of a CSR_Cluster A) */
     int64_t unit_hi;        /* numeric: one past the last unit; <= 0 means all units */
     int64_t out_base;       /* numeric: C_col_d/C_val_d point at global entry out_base of C */
-    int32_t dense_slots;    /* concurrent dense accumulators for very long units of a CSR_Cluster A or a
-                               batch: 0 = as many as fit in 4 GiB (32..1024) */
+    int32_t dense_slots;    /* concurrent dense accumulators for units of a batch too long for shared
+                               memory: 0 = as many as fit in 4 GiB (32..1024) */
     int32_t load_pct;       /* numeric hash-table fill target in percent: 0 = default (60) */
     int32_t sym_tmax_log2;  /* largest shared-memory symbolic table, log2 slots: 0 = default */
     int32_t num_tmax;       /* largest shared-memory numeric table, slots: 0 = default */
     int32_t sym_load_pct;   /* symbolic tables get >= products*100/sym_load_pct slots (products: the
                                unit's upper bound on distinct columns), 10..100: 0 = default (70) */
-    int32_t win_chunk_log2; /* CSR rows too long for shared memory are cut into about products / 2^this
-                               column chunks (1..256), one wavefront each: 0 = default (16), else 4..30;
-                               the numeric call must use the symbolic call's value */
+    int32_t win_chunk_log2; /* rows of units too long for shared memory (single products) are cut into
+                               about products / 2^this column chunks (1..256), one wavefront each:
+                               0 = default (16), else 4..30; the numeric call must use the symbolic
+                               call's value */
 } hcsp_opts;
 
 #define HCSP_MAX_BINS 96

@@ -51,7 +51,7 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->dense_slots = windows ? 0 : dense_slots;
     ws->dense_bits = (uint32_t *)take(4 * (size_t)ws->dense_words * ws->dense_slots);
     ws->dense_vals = (double *)take(8 * (size_t)std::max<int64_t>(ncols, 1) * ws->dense_slots);
-    ws->chunk_cnt = (int32_t *)take(windows ? 4 * (size_t)kWinChunksMax * nu : 0);
+    ws->chunk_cnt = (int32_t *)take(windows ? 4 * (size_t)kWinChunksMax * (size_t)std::max<int64_t>(nrows, nunits) : 0);
     ws->win_base = (int64_t *)take(windows ? 8 * (nu + 1) : 0);
     ws->bytes = align_up(off, 256);
     return ws->bytes;
@@ -530,7 +530,7 @@ int hcsp_spgemm_workspace(const hcsp_operand *A, const hcsp_csr *B, const hcsp_o
     rc = make_tune(opts, B, false, &tu);
     if (rc) return rc;
     Workspace ws;
-    *bytes = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, nullptr, &ws);
+    *bytes = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, nullptr, &ws);
     return HCSP_OK;
 }
 
@@ -550,7 +550,7 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, (char *)ws_d, &ws);
+    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, (char *)ws_d, &ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     hipStream_t s = (hipStream_t)stream;
     std::memset(info, 0, sizeof *info);
@@ -584,16 +584,10 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
         const int64_t c = cnt[b];
         a.bin_begin = begin[b];
         a.count = c;
-        if (b == kSymGlobal && !v.cluster) {
-            HCSP_HIP(launch_win_prep(true, a, t));
-            HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, t));
-            HCSP_HIP(launch_sym_win(a, win_blocks(win_sym_wave_bytes()), t));
-            return HCSP_OK;
-        }
         if (b == kSymGlobal) {
-            const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
-            HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, t));
-            HCSP_HIP(launch_sym_dense(v.cluster, false, a, waves / 4, t));
+            HCSP_HIP(launch_win_prep(true, v.cluster, a, t));
+            HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, t));
+            HCSP_HIP(launch_sym_win(v.cluster, a, win_blocks(win_sym_wave_bytes()), t));
             return HCSP_OK;
         }
         const int sc = (b - 1) / kSymT;
@@ -655,7 +649,7 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
     if (tu.G != info->lanes || tu.load_pct != info->load_pct || tu.win_log2 != info->win_chunk_log2)
         return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
     Workspace ws;
-    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, (char *)ws_d, &ws);
+    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, (char *)ws_d, &ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     hipStream_t s = (hipStream_t)stream;
     hcsp_opts z;
@@ -703,16 +697,10 @@ static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, cons
         const int64_t c = info->num_bin_count[b];
         a.bin_begin = begin[b];
         a.count = c;
-        if (b == kNumGlobal && !cluster) {
-            HCSP_HIP(launch_win_prep(false, a, st));
-            HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, st));
-            HCSP_HIP(launch_num_win(a, win_blocks(win_num_wave_bytes()), st));
-            return HCSP_OK;
-        }
         if (b == kNumGlobal) {
-            const int waves = (int)std::min<int64_t>(tu.dense_slots, (c + 3) / 4 * 4);
-            HCSP_HIP(launch_fill_u32(ws.dense_bits, (int64_t)waves * ws.dense_words, 0u, st));
-            HCSP_HIP(launch_num_dense(cluster, false, a, waves / 4, st));
+            HCSP_HIP(launch_win_prep(false, cluster, a, st));
+            HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, st));
+            HCSP_HIP(launch_num_win(cluster, a, win_blocks(win_num_wave_bytes()), st));
             return HCSP_OK;
         }
         const int sc = (b - 1) / kNumT;
@@ -744,7 +732,7 @@ static int numeric_setup(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     if (rc) return rc;
     if (tu->G != info->lanes || tu->load_pct != info->load_pct || tu->win_log2 != info->win_chunk_log2)
         return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
-    const size_t need = layout_workspace(v->nunits, v->nrows, B->ncols, tu->dense_slots, !v->cluster, (char *)ws_d, ws);
+    const size_t need = layout_workspace(v->nunits, v->nrows, B->ncols, tu->dense_slots, true, (char *)ws_d, ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     return HCSP_OK;
 }
@@ -903,7 +891,7 @@ int hcsp_predicted_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_op
     rc = make_tune(opts, B, false, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, nullptr, &ws);
+    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, nullptr, &ws);
     PredWs p;
     *bytes = layout_pred(base, v.nrows, pred_entries(ratio, products, v.nrows), nullptr, &p);
     return HCSP_OK;
@@ -928,7 +916,7 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, !v.cluster, (char *)ws_d, &ws);
+    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, (char *)ws_d, &ws);
     PredWs pw;
     const size_t need = layout_pred(base, v.nrows, pred_entries(ratio, products, v.nrows), (char *)ws_d, &pw);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "predicted-size workspace too small");

@@ -985,27 +985,35 @@ __device__ __forceinline__ uint32_t lower_bound_col(const int32_t *col, uint32_t
     return lo;
 }
 
-// Loads the next round of a CSR row's items for the window [w0, w1): lane i
-// takes column q0+i of the row and the part of row k of B inside the window.
-template <bool NUM>
-__device__ __forceinline__ int load_round_win(const SpArgs &a, int64_t it1, int64_t &q0, int &off0, ItemRec *items,
-                                              uint64_t *sbits, int w0, int w1)
+// A row of the window path: a CSR row (items: its columns), or member l of
+// a cluster of s rows (items: the cluster's union columns whose mask has
+// bit l; values at vbase + t*s + l for union column t).
+struct WinRow {
+    int64_t it0, it1, vbase;
+    int l, s;
+};
+
+// Loads the next round of a window row's items for the window [w0, w1):
+// lane i takes item q0+i and the part of row k of B inside the window.
+template <bool NUM, bool CL>
+__device__ __forceinline__ int load_round_win(const SpArgs &a, const WinRow &r, int64_t &q0, int &off0,
+                                              ItemRec *items, uint64_t *sbits, int w0, int w1)
 {
     const int lane = (int)__lane_id();
     sbits[lane] = 0ull;
     const int64_t q = q0 + lane;
     uint32_t lo = 0, hi = 0;
     double a1 = 0.0;
-    if (q < it1) {
-        const int k = a.a_col[q];
+    if (q < r.it1 && (!CL || ((a.cl_mask[q] >> r.l) & 1u))) {
+        const int k = CL ? a.cl_col[q] : a.a_col[q];
         lo = (uint32_t)a.b_rp[k];
         hi = (uint32_t)a.b_rp[k + 1];
         if (lo < hi && ld_col(a.b_col, lo) < w0) lo = lower_bound_col(a.b_col, lo + 1, hi, w0);
         if (lo < hi && ld_col(a.b_col, hi - 1) >= w1) hi = lower_bound_col(a.b_col, lo, hi - 1, w1);
-        if (NUM) a1 = a.a_val[q];
+        if (NUM) a1 = CL ? a.cl_val[r.vbase + (q - r.it0) * r.s + r.l] : a.a_val[q];
     }
     const uint64_t ab = (uint64_t)__double_as_longlong(a1);
-    return flatten_round(it1, q0, off0, items, sbits, lo, (int)(hi - lo), (uint32_t)ab, (uint32_t)(ab >> 32));
+    return flatten_round(r.it1, q0, off0, items, sbits, lo, (int)(hi - lo), (uint32_t)ab, (uint32_t)(ab >> 32));
 }
 
 // Window table sizes (slots, powers of two): keys only for the symbolic
@@ -1035,10 +1043,10 @@ struct WinNumLayout {
 int64_t win_sym_wave_bytes() { return SymLayout(0, 1 << kWinSymLog2T).bytes; }
 int64_t win_num_wave_bytes() { return WinNumLayout().bytes; }
 
-// Distinct output columns of CSR row [it0, it1) inside [w0, w1), or -1 when
-// the table got too full for another batch of passes (window too wide).
-__device__ __forceinline__ int sym_window(const SpArgs &a, int64_t it0, int64_t it1, int w0, int w1,
-                                          unsigned char *base)
+// Distinct output columns of window row r inside [w0, w1), or -1 when the
+// table got too full for another batch of passes (window too wide).
+template <bool CL>
+__device__ __forceinline__ int sym_window(const SpArgs &a, const WinRow &r, int w0, int w1, unsigned char *base)
 {
     constexpr int T = 1 << kWinSymLog2T, kR = 8;
     const int lane = (int)__lane_id();
@@ -1050,7 +1058,7 @@ __device__ __forceinline__ int sym_window(const SpArgs &a, int64_t it0, int64_t 
     if (lane == 0) keys[T] = kDummyKey;
     const uint64_t le = lanemask_le(lane);
     int total = 0;  // keys in the table (wave-uniform)
-    int64_t q0 = it0;
+    int64_t q0 = r.it0;
     int off0 = 0;
     // every probe finds a free slot while at most T - 1 keys are in
     auto probe = [&](int j) {
@@ -1062,8 +1070,8 @@ __device__ __forceinline__ int sym_window(const SpArgs &a, int64_t it0, int64_t 
         }
         total += __popcll(__ballot(old == kEmpty && h != (uint32_t)T));
     };
-    while (q0 < it1) {
-        const int E = load_round_win<false>(a, it1, q0, off0, items, sbits, w0, w1);
+    while (q0 < r.it1) {
+        const int E = load_round_win<false, CL>(a, r, q0, off0, items, sbits, w0, w1);
         const int npass = (E + 63) >> 6;
         int cum = 0;
         for (int p = 0; p < npass; p += kR) {
@@ -1087,15 +1095,16 @@ __device__ __forceinline__ int sym_window(const SpArgs &a, int64_t it0, int64_t 
     return total;
 }
 
-// Entries of CSR row [it0, it1) of C inside [w0, w1), written in column
-// order to ccol/cval; returns their number, -1 when the table got too full
+// Entries of window row r of C inside [w0, w1), written in column order to
+// ccol/cval; returns their number, -1 when the table got too full
 // for another batch of passes (window too wide, nothing written) or -2 when
 // there are more than room of them (nothing written).  Keys are placed by a
 // multiplicative hash; their ranks come from a counting sort over
 // kWinBuckets buckets of equal column range (a bucket's keys are compared
 // with each other only).
-__device__ __forceinline__ int num_window(const SpArgs &a, int64_t it0, int64_t it1, int w0, int w1,
-                                          unsigned char *base, int32_t *ccol, double *cval, int64_t room)
+template <bool CL>
+__device__ __forceinline__ int num_window(const SpArgs &a, const WinRow &r, int w0, int w1, unsigned char *base,
+                                          int32_t *ccol, double *cval, int64_t room)
 {
     constexpr int T = 1 << kWinNumLog2T, kR = 4, NB = kWinBuckets;
     const int lane = (int)__lane_id();
@@ -1133,10 +1142,10 @@ __device__ __forceinline__ int num_window(const SpArgs &a, int64_t it0, int64_t 
             vals[h] = __fma_rn(av, d.b, vals[h]);
         }
     };
-    int64_t q0 = it0;
+    int64_t q0 = r.it0;
     int off0 = 0;
-    while (q0 < it1) {
-        const int E = load_round_win<true>(a, it1, q0, off0, items, sbits, w0, w1);
+    while (q0 < r.it1) {
+        const int E = load_round_win<true, CL>(a, r, q0, off0, items, sbits, w0, w1);
         const int npass = (E + 63) >> 6;
         int cum = 0;
         for (int p = 0; p < npass; p += kR) {
@@ -1211,18 +1220,20 @@ __device__ __forceinline__ void win_chunk(int64_t ncols, int nch, int c, int *lo
 }
 
 // Next window width after a window of width w that held n keys, aiming at
-// tk keys (growing at most 8-fold), within [1, cap].
+// tk keys (growing at most 2-fold), within [1, cap].
 __device__ __forceinline__ int64_t win_next(int64_t w, int64_t n, int64_t tk, int64_t cap)
 {
-    const int64_t x = w * tk / max<int64_t>(n, tk / 8);
+    const int64_t x = w * tk / max<int64_t>(n, tk / 2);
     return max<int64_t>(1, min<int64_t>(x, cap));
 }
 
-// Chunks per row of a window launch: rows counted by chunks get
-// win_nchunks(products), rows the shared-memory symbolic phase counted whole
-// (numeric only) one.  base[i] = chunks of the bin's i-th row, base[count] =
-// 0; an exclusive scan then gives each row's first (row, chunk) pair.
-template <bool SYM>
+// (row, chunk) pairs of a window launch per unit of the bin: a CSR row, or
+// each member row of a cluster, gets win_nchunks(the unit's products)
+// chunks when the symbolic phase counted it by chunks, one chunk (numeric
+// only) when the shared-memory symbolic phase counted it whole.
+// base[i] = pairs of the bin's i-th unit, base[count] = 0; an exclusive scan
+// then gives each unit's first pair.
+template <bool SYM, bool CL>
 __global__ void __launch_bounds__(256) k_win_prep(SpArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1232,7 +1243,8 @@ __global__ void __launch_bounds__(256) k_win_prep(SpArgs a)
         return;
     }
     const int u = a.order[a.bin_begin + i];
-    a.win_base[i] = SYM || a.ucount[u] == INT32_MAX ? win_nchunks(a.probes[u], a.win_log2) : 1;
+    const int s = CL ? (int)(a.cl_row_ptr[u + 1] - a.cl_row_ptr[u]) : 1;
+    a.win_base[i] = (int64_t)s * (SYM || a.ucount[u] == INT32_MAX ? win_nchunks(a.probes[u], a.win_log2) : 1);
 }
 
 // The (row, chunk) pair i of a window launch: p = the largest position with
@@ -1255,8 +1267,39 @@ __device__ __forceinline__ int64_t win_find(const int64_t *base, int64_t count, 
     return lo + (63 - __clzll((long long)b));
 }
 
+// Pair i of a window launch resolved: its unit, window row, output row and
+// chunk c of nch (wave-uniform).
+struct WinPair {
+    int u, c, nch;
+    int64_t row;
+    WinRow r;
+};
+
+template <bool CL>
+__device__ __forceinline__ WinPair win_pair(const SpArgs &a, int64_t i)
+{
+    WinPair w;
+    const int64_t p = (int64_t)uniform64((uint64_t)win_find(a.win_base, a.count, i));
+    const int64_t b0 = (int64_t)uniform64((uint64_t)a.win_base[p]);
+    const int64_t np = (int64_t)uniform64((uint64_t)a.win_base[p + 1]) - b0;
+    w.u = uniform(a.order[a.bin_begin + p]);
+    const UnitView v = unit_view<CL>(a, w.u);
+    w.nch = (int)(np / v.s);
+    const int loc = (int)(i - b0);
+    const int l = loc / w.nch;
+    w.c = loc - l * w.nch;
+    w.r.it0 = v.it0;
+    w.r.it1 = v.it1;
+    w.r.vbase = v.vbase;
+    w.r.l = l;
+    w.r.s = v.s;
+    w.row = CL ? (int64_t)uniform(a.perm[v.pos0 + l]) : (int64_t)w.u;
+    return w;
+}
+
 // Symbolic: one wavefront per (row, chunk); the chunk's count goes to
 // chunk_cnt and is added to the row's count (zeroed by the binning kernel).
+template <bool CL>
 __global__ void __launch_bounds__(64) k_sym_win(SpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1264,22 +1307,17 @@ __global__ void __launch_bounds__(64) k_sym_win(SpArgs a)
     const int lane = (int)__lane_id();
     const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
     for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
-        const int64_t p = (int64_t)uniform64((uint64_t)win_find(a.win_base, a.count, i));
-        const int64_t b0 = (int64_t)uniform64((uint64_t)a.win_base[p]);
-        const int nch = (int)((int64_t)uniform64((uint64_t)a.win_base[p + 1]) - b0);
-        const int c = (int)(i - b0);
-        const int u = uniform(a.order[a.bin_begin + p]);
-        const int64_t it0 = (int64_t)uniform64((uint64_t)a.a_rp[u]);
-        const int64_t it1 = (int64_t)uniform64((uint64_t)a.a_rp[u + 1]);
+        const WinPair w = win_pair<CL>(a, i);
         int lo, hi;
-        win_chunk(a.ncols, nch, c, &lo, &hi);
+        win_chunk(a.ncols, w.nch, w.c, &lo, &hi);
         // first width: as if the chunk's share of the products were distinct
-        const int64_t ub = max<int64_t>(1, min<int64_t>((int64_t)uniform64((uint64_t)a.probes[u]) / nch, hi - lo));
+        const int64_t ub =
+            max<int64_t>(1, min<int64_t>((int64_t)uniform64((uint64_t)a.probes[w.u]) / w.nch, hi - lo));
         int64_t width = max<int64_t>(1, min<int64_t>(hi - lo, tk * (hi - lo) / ub));
         int64_t n = 0;
         for (int w0 = lo; w0 < hi;) {
             const int w1 = (int)min<int64_t>(hi, w0 + width);
-            const int k = sym_window(a, it0, it1, w0, w1, smem);
+            const int k = sym_window<CL>(a, w.r, w0, w1, smem);
             if (k < 0) {
                 width = max<int64_t>(1, (w1 - w0) / 2);
                 continue;
@@ -1289,16 +1327,17 @@ __global__ void __launch_bounds__(64) k_sym_win(SpArgs a)
             w0 = w1;
         }
         if (lane == 0) {
-            a.chunk_cnt[(int64_t)u * kWinChunksMax + c] = (int32_t)n;
-            if (n) atomicAdd((unsigned long long *)&a.c_rp[u], (unsigned long long)n);
-            if (c == 0) a.ucount[u] = INT32_MAX;
+            a.chunk_cnt[w.row * kWinChunksMax + w.c] = (int32_t)n;
+            if (n) atomicAdd((unsigned long long *)&a.c_rp[w.row], (unsigned long long)n);
+            if (w.c == 0 && w.r.l == 0) a.ucount[w.u] = INT32_MAX;
         }
     }
 }
 
-// Numeric: one wavefront per (row, chunk) for rows counted by chunks (count
-// INT32_MAX); a row counted whole by the shared-memory symbolic phase is one
-// chunk over its column range [keylo, keyhi].
+// Numeric: one wavefront per (row, chunk) for units counted by chunks (count
+// INT32_MAX); a row the shared-memory symbolic phase counted whole is one
+// chunk over its unit's column range [keylo, keyhi].
+template <bool CL>
 __global__ void __launch_bounds__(64) k_num_win(SpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1306,31 +1345,25 @@ __global__ void __launch_bounds__(64) k_num_win(SpArgs a)
     const int lane = (int)__lane_id();
     const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
     for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
-        const int64_t p = (int64_t)uniform64((uint64_t)win_find(a.win_base, a.count, i));
-        const int64_t b0 = (int64_t)uniform64((uint64_t)a.win_base[p]);
-        const int nch = (int)((int64_t)uniform64((uint64_t)a.win_base[p + 1]) - b0);
-        const int c = (int)(i - b0);
-        const int u = uniform(a.order[a.bin_begin + p]);
-        if (u < a.unit_lo || u >= a.unit_hi) continue;
-        const bool chunked = uniform(a.ucount[u]) == INT32_MAX;
-        const int64_t it0 = (int64_t)uniform64((uint64_t)a.a_rp[u]);
-        const int64_t it1 = (int64_t)uniform64((uint64_t)a.a_rp[u + 1]);
-        int64_t off = (int64_t)uniform64((uint64_t)a.c_rp[u]) - a.out_base;
+        const WinPair w = win_pair<CL>(a, i);
+        if (w.u < a.unit_lo || w.u >= a.unit_hi) continue;
+        const bool chunked = uniform(a.ucount[w.u]) == INT32_MAX;
+        int64_t off = (int64_t)uniform64((uint64_t)a.c_rp[w.row]) - a.out_base;
         int64_t kc;
         int lo, hi;
         if (chunked) {
-            win_chunk(a.ncols, nch, c, &lo, &hi);
+            win_chunk(a.ncols, w.nch, w.c, &lo, &hi);
             // this chunk's entries follow those of the chunks before it
-            const int32_t *cc = a.chunk_cnt + (int64_t)u * kWinChunksMax;
+            const int32_t *cc = a.chunk_cnt + w.row * kWinChunksMax;
             int64_t before = 0;
-            for (int x = lane; x < c; x += 64) before += cc[x];
+            for (int x = lane; x < w.c; x += 64) before += cc[x];
             for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o);
             off += (int64_t)uniform64((uint64_t)before);
-            kc = uniform(cc[c]);
+            kc = uniform(cc[w.c]);
         } else {
-            lo = uniform(a.keylo[u]);
-            hi = uniform(a.keyhi[u]) + 1;
-            kc = (int64_t)uniform64((uint64_t)(a.c_rp[u + 1] - a.c_rp[u]));
+            lo = uniform(a.keylo[w.u]);
+            hi = uniform(a.keyhi[w.u]) + 1;
+            kc = (int64_t)uniform64((uint64_t)(a.c_rp[w.row + 1] - a.c_rp[w.row]));
         }
         if (kc <= 0) continue;
         if (off < 0 || off + kc > a.cap || lo < 0 || hi > a.ncols || lo >= hi) {
@@ -1341,7 +1374,7 @@ __global__ void __launch_bounds__(64) k_num_win(SpArgs a)
         int64_t done = 0;
         for (int w0 = lo; w0 < hi;) {
             const int w1 = (int)min<int64_t>(hi, w0 + width);
-            const int k = num_window(a, it0, it1, w0, w1, smem, a.c_col + off + done, a.c_val + off + done, kc - done);
+            const int k = num_window<CL>(a, w.r, w0, w1, smem, a.c_col + off + done, a.c_val + off + done, kc - done);
             if (k == -1) {
                 width = max<int64_t>(1, (w1 - w0) / 2);
                 continue;
@@ -1355,23 +1388,27 @@ __global__ void __launch_bounds__(64) k_num_win(SpArgs a)
     }
 }
 
-hipError_t launch_win_prep(bool sym, const SpArgs &a, hipStream_t s)
+hipError_t launch_win_prep(bool sym, bool cluster, const SpArgs &a, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((a.count + 1 + 255) / 256);
-    if (sym) hipLaunchKernelGGL(k_win_prep<true>, dim3(blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_win_prep<false>, dim3(blocks), dim3(256), 0, s, a);
+    if (sym && cluster) hipLaunchKernelGGL((k_win_prep<true, true>), dim3(blocks), dim3(256), 0, s, a);
+    else if (sym) hipLaunchKernelGGL((k_win_prep<true, false>), dim3(blocks), dim3(256), 0, s, a);
+    else if (cluster) hipLaunchKernelGGL((k_win_prep<false, true>), dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_win_prep<false, false>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sym_win(const SpArgs &a, int blocks, hipStream_t s)
+hipError_t launch_sym_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sym_win, dim3(blocks), dim3(64), (size_t)win_sym_wave_bytes(), s, a);
+    if (cluster) hipLaunchKernelGGL(k_sym_win<true>, dim3(blocks), dim3(64), (size_t)win_sym_wave_bytes(), s, a);
+    else hipLaunchKernelGGL(k_sym_win<false>, dim3(blocks), dim3(64), (size_t)win_sym_wave_bytes(), s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_num_win(const SpArgs &a, int blocks, hipStream_t s)
+hipError_t launch_num_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_num_win, dim3(blocks), dim3(64), (size_t)win_num_wave_bytes(), s, a);
+    if (cluster) hipLaunchKernelGGL(k_num_win<true>, dim3(blocks), dim3(64), (size_t)win_num_wave_bytes(), s, a);
+    else hipLaunchKernelGGL(k_num_win<false>, dim3(blocks), dim3(64), (size_t)win_num_wave_bytes(), s, a);
     return hipGetLastError();
 }
 

@@ -95,16 +95,18 @@ struct Workspace {
     double *dense_vals;
     int64_t dense_words; // 32-bit words per bitmap
     int dense_slots;
-    // column-window path (CSR rows too long for shared memory): per unit and
-    // column chunk, the chunk's distinct output columns [nunits][kWinChunksMax];
-    // per row of a window launch its first (row, chunk) pair [nunits + 1]
+    // column-window path (rows of units too long for shared memory): per row
+    // of C and column chunk, the chunk's distinct output columns
+    // [rows][kWinChunksMax]; per unit of a window launch its first (row,
+    // chunk) pair [nunits + 1]
     int32_t *chunk_cnt;
     int64_t *win_base;
     size_t bytes;
 };
 
-// windows: CSR operands, whose long rows take the column-window path (chunk
-// counts, no dense accumulators); otherwise dense_slots dense accumulators
+// windows: single products, whose units too long for shared memory take the
+// column-window path (chunk counts, no dense accumulators); otherwise
+// (batches) dense_slots dense accumulators
 size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, bool windows, char *base,
                         Workspace *ws);
 
@@ -208,9 +210,10 @@ hipError_t launch_sym_dense(bool cluster, bool batch, const SpArgs &a, int block
 // numeric with predicted sizes (CSR rows): bounded probing, padded output
 hipError_t launch_num_pred(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s);
 hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s);
-// column-window path for CSR rows too long for shared memory: one wavefront
-// per (row, chunk) of the output columns, persistent over the bin's rows; a
-// row of ub products gets about ub / kWinChunkWork chunks
+// column-window path for units too long for shared memory: one wavefront per
+// (row, chunk) of the output columns (a cluster's member rows one by one),
+// persistent over the bin; a unit of ub products gets about ub / 2^win_log2
+// chunks per row
 constexpr int kWinChunksMax = 256;
 constexpr int kWinLog2Default = 16;
 __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
@@ -218,11 +221,11 @@ __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
     const int64_t n = (ub + ((int64_t)1 << log2) - 1) >> log2;
     return (int)(n < 1 ? 1 : (n > kWinChunksMax ? kWinChunksMax : n));
 }
-hipError_t launch_win_prep(bool sym, const SpArgs &a, hipStream_t s);
+hipError_t launch_win_prep(bool sym, bool cluster, const SpArgs &a, hipStream_t s);
 int64_t win_sym_wave_bytes();
 int64_t win_num_wave_bytes();
-hipError_t launch_sym_win(const SpArgs &a, int blocks, hipStream_t s);
-hipError_t launch_num_win(const SpArgs &a, int blocks, hipStream_t s);
+hipError_t launch_sym_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
+hipError_t launch_num_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
 
 // launchers (util.hip)
 struct BinArgs {

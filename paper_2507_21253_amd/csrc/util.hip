@@ -140,8 +140,9 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
                 a.ws.ucount[u] = 0;
                 if (a.c_rp && on)  // null: estimate only; inactive units keep their count
                     for (int l = 0; l < w.s; ++l) w.c_rp[CL ? (int64_t)w.perm[w.pos0 + l] : w.u] = 0;
-            } else if (!CL && !BATCH && bin == kSymGlobal && a.c_rp) {
-                w.c_rp[w.u] = 0;  // the column-window chunks add their counts to it
+            } else if (!BATCH && bin == kSymGlobal && a.c_rp) {
+                // the column-window chunks add their counts to the rows
+                for (int l = 0; l < w.s; ++l) w.c_rp[CL ? (int64_t)w.perm[w.pos0 + l] : w.u] = 0;
             }
         }
     }

@@ -1,6 +1,7 @@
-"""GPU parity of the column-window path: CSR rows whose output is too large
-for one shared-memory table are cut into column chunks (one wavefront each)
-and every chunk into windows that fit a table; C must still equal the
+"""GPU parity of the column-window path: rows whose output is too large for
+one shared-memory table (CSR rows, or the member rows of clusters) are cut
+into column chunks (one wavefront each) and every chunk into windows that fit
+a table; C must still equal the
 oracle bit for bit, since every output entry gets its products in ascending k.
 
 Cases: rows counted by chunks in the symbolic phase (products beyond the
@@ -8,8 +9,9 @@ largest symbolic table), with one chunk or up to 256 (win_chunk_log2 sets
 the products per chunk); rows counted whole in shared memory but too large
 for the numeric tables (one chunk over the row's column range); output
 columns packed densely into part of a chunk, so that first windows overflow
-and are redone narrower in both phases; row panels; R-MAT rows; a numeric
-call whose chunking differs from its symbolic call's is refused."""
+and are redone narrower in both phases; row panels; R-MAT rows; clustered
+operands (fixed and hierarchical plans); a numeric call whose chunking
+differs from its symbolic call's is refused."""
 import numpy as np
 import pytest
 
@@ -138,3 +140,33 @@ def test_numeric_with_other_chunking_is_refused():
     ref = oracle.spgemm(A, B)
     np.testing.assert_array_equal(col.cpu().numpy(), ref.col)
     np.testing.assert_array_equal(val.cpu().numpy(), ref.val)
+
+
+@pytest.mark.parametrize("plan_kind", ["fixed4", "hier8"])
+def test_clusters_on_window_path(plan_kind):
+    # a CSR_Cluster A whose clusters outgrow shared memory: each member row
+    # takes the window path on its own (union columns with its mask bit)
+    A, B = packed_case(11, 2_300, m=30, n=60)
+    Ad, Bd = hc.DeviceCSR.from_host(A), hc.DeviceCSR.from_host(B)
+    plan = hc.plan_fixed(A.nrows, 4) if plan_kind == "fixed4" else hc.plan_hierarchical(A, (1, 10), 8)
+    Dc = hc.cluster_build(Ad, plan)
+    ref = oracle.spgemm(A, B)
+    for o in (None, hc.opts(sym_tmax_log2=7, num_tmax=96), hc.opts(sym_tmax_log2=7, num_tmax=96, win_chunk_log2=8),
+              hc.opts(num_tmax=96)):
+        torch.cuda.synchronize()
+        C = hc.spgemm(Dc, Bd, o)
+        torch.cuda.synchronize()
+        assert_same(C.to_host(), ref, "%s %s" % (plan_kind, o))
+
+
+def test_rmat_clusters_on_window_path():
+    R = synth.rmat(12, 16, 0.57, 0.19, 0.19, 7)
+    Rd = hc.DeviceCSR.from_host(R)
+    plan = hc.plan_hierarchical(R, (3, 10), 4, perm_in=hc.order_rcm(R))
+    Dc = hc.cluster_build(Rd, plan)
+    ref = oracle.spgemm(R, R)
+    for o in (None, hc.opts(sym_tmax_log2=8, num_tmax=128, win_chunk_log2=6)):
+        torch.cuda.synchronize()
+        C = hc.spgemm(Dc, Rd, o)
+        torch.cuda.synchronize()
+        assert_same(C.to_host(), ref, str(o))
