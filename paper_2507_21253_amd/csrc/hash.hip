@@ -1017,8 +1017,8 @@ __device__ __forceinline__ int load_round_win(const SpArgs &a, const WinRow &r, 
 }
 
 // Window table sizes (slots, powers of two): keys only for the symbolic
-// phase, keys and values for the numeric one; a window aims at half a table
-// of keys.
+// phase, keys and values for the numeric one; a window aims at 5/8 of a
+// table of keys.
 constexpr int kWinSymLog2T = 11;
 constexpr int kWinNumLog2T = 10;
 constexpr int kWinBuckets = 1 << (kWinNumLog2T - 1);  // rank buckets of a numeric window
@@ -1303,7 +1303,7 @@ template <bool CL>
 __global__ void __launch_bounds__(64) k_sym_win(SpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int64_t tk = (1 << kWinSymLog2T) / 2;
+    constexpr int64_t tk = (1 << kWinSymLog2T) * 5 / 8;
     const int lane = (int)__lane_id();
     const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
     for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
@@ -1341,7 +1341,7 @@ template <bool CL>
 __global__ void __launch_bounds__(64) k_num_win(SpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int64_t tk = (1 << kWinNumLog2T) / 2;
+    constexpr int64_t tk = (1 << kWinNumLog2T) * 5 / 8;
     const int lane = (int)__lane_id();
     const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
     for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {

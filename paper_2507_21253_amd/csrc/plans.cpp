@@ -43,7 +43,23 @@ struct Pattern {
     const int32_t *cols(int64_t p) const { return col + rp[row[p]]; }
 };
 
-Sim jaccard(const Pattern &P, int64_t i, int64_t j)
+// A's rows copied in plan order (position p's columns contiguous), for the
+// merge loop, whose pairs are near each other in that order.
+struct PosPattern {
+    std::vector<int64_t> rp;
+    std::vector<int32_t> col;
+    explicit PosPattern(const Pattern &P) : rp((size_t)P.n + 1, 0)
+    {
+        for (int64_t p = 0; p < P.n; ++p) rp[(size_t)p + 1] = rp[(size_t)p] + P.len(p);
+        col.resize((size_t)rp[(size_t)P.n]);
+        for (int64_t p = 0; p < P.n; ++p) std::copy(P.cols(p), P.cols(p) + P.len(p), col.begin() + rp[(size_t)p]);
+    }
+    int64_t len(int64_t p) const { return rp[(size_t)p + 1] - rp[(size_t)p]; }
+    const int32_t *cols(int64_t p) const { return col.data() + rp[(size_t)p]; }
+};
+
+template <class Pat>
+Sim jaccard(const Pat &P, int64_t i, int64_t j)
 {
     const int32_t *a = P.cols(i), *b = P.cols(j);
     const int64_t na = P.len(i), nb = P.len(j);
@@ -410,14 +426,78 @@ int merge_phase(const Pattern &P, int64_t num, int64_t den, int32_t max_cluster,
     try {
         std::vector<int32_t> parent((size_t)n), size((size_t)n, 1), next((size_t)n, -1), tail((size_t)n);
         for (int64_t i = 0; i < n; ++i) parent[i] = tail[i] = (int32_t)i;
-        std::priority_queue<Cand, std::vector<Cand>, CandLess> heap;
-        PairSet cand((size_t)n * (size_t)std::max(topk, 1));
+        // The initial candidate pairs (each row's list, pairs listed from both
+        // ends once) are sorted best first and merged with a heap that only
+        // holds the pairs pushed during the loop: the same pop order as one
+        // heap over everything, without its cache misses.
+        const CandLess less;
+        std::vector<Cand> init;
+        size_t ninit = 0;
+        for (int64_t i = 0; i < n && topk > 0; ++i) ninit += (size_t)cnt[i];
+        init.reserve(ninit);
         for (int64_t i = 0; i < n && topk > 0; ++i)
             for (int x = 0; x < cnt[i]; ++x) {
                 int32_t a = (int32_t)i, b = nbr[(size_t)i * topk + x];
                 if (a > b) std::swap(a, b);
-                if (cand.insert(pair_key(a, b))) heap.push(Cand{nsim[(size_t)i * topk + x], a, b});
+                init.push_back(Cand{nsim[(size_t)i * topk + x], a, b});
             }
+        {
+            // order = similarity (exact ratio) descending, then i, then j: the
+            // distinct similarities are ranked once (equal ratios share a
+            // rank), then (rank, i, j) integer keys are sorted
+            std::vector<Sim> vals;
+            {
+                PairSet seen(1024);
+                for (const Cand &c : init)
+                    if (seen.insert(((uint64_t)c.s.ov << 32) | (uint64_t)c.s.un)) vals.push_back(c.s);
+            }
+            std::sort(vals.begin(), vals.end(), [](const Sim &x, const Sim &y) { return cmp_sim(x, y) > 0; });
+            std::vector<uint64_t> vkey(vals.size());
+            std::vector<uint32_t> vrank(vals.size());
+            for (size_t x = 0; x < vals.size(); ++x) {
+                vkey[x] = ((uint64_t)vals[x].ov << 32) | (uint64_t)vals[x].un;
+                vrank[x] = x > 0 && cmp_sim(vals[x], vals[x - 1]) == 0 ? vrank[x - 1] : (uint32_t)x;
+            }
+            // (ov, un) -> rank through a sorted key table
+            std::vector<size_t> vo(vals.size());
+            for (size_t x = 0; x < vo.size(); ++x) vo[x] = x;
+            std::sort(vo.begin(), vo.end(), [&](size_t x, size_t y) { return vkey[x] < vkey[y]; });
+            std::vector<uint64_t> skey(vals.size());
+            std::vector<uint32_t> srank(vals.size());
+            for (size_t x = 0; x < vo.size(); ++x) {
+                skey[x] = vkey[vo[x]];
+                srank[x] = vrank[vo[x]];
+            }
+            struct Key {
+                uint64_t hi;  // rank, i
+                uint32_t j;
+            };
+            std::vector<Key> keys(init.size());
+            for (size_t x = 0; x < init.size(); ++x) {
+                const uint64_t k = ((uint64_t)init[x].s.ov << 32) | (uint64_t)init[x].s.un;
+                const uint32_t r = srank[(size_t)(std::lower_bound(skey.begin(), skey.end(), k) - skey.begin())];
+                keys[x] = Key{((uint64_t)r << 32) | (uint32_t)init[x].i, (uint32_t)init[x].j};
+            }
+            std::sort(keys.begin(), keys.end(),
+                      [](const Key &x, const Key &y) { return x.hi != y.hi ? x.hi < y.hi : x.j < y.j; });
+            for (size_t x = 0; x < keys.size(); ++x)
+                init[x] = Cand{vals[keys[x].hi >> 32], (int32_t)(uint32_t)keys[x].hi, (int32_t)keys[x].j};
+        }
+        // a pair listed by both rows has the same similarity: the copies are adjacent
+        init.erase(std::unique(init.begin(), init.end(),
+                               [](const Cand &x, const Cand &y) { return x.i == y.i && x.j == y.j; }),
+                   init.end());
+        std::priority_queue<Cand, std::vector<Cand>, CandLess> heap;
+        PairSet pushed(1024);
+        // was (a, b) ever a candidate: in a's or b's initial list, or pushed
+        auto listed = [&](int32_t a, int32_t b) -> bool {
+            for (int x = 0; x < cnt[a]; ++x)
+                if (nbr[(size_t)a * topk + x] == b) return true;
+            for (int x = 0; x < cnt[b]; ++x)
+                if (nbr[(size_t)b * topk + x] == a) return true;
+            return pushed.contains(pair_key(a, b));
+        };
+        const PosPattern Q(P);
         std::vector<int64_t> mark;
         int64_t stamp = 0;
         if (sim_flags == HCSP_SIM_UNION) mark.assign((size_t)std::max<int64_t>(P.ncols, 1), -1);
@@ -425,8 +505,8 @@ int merge_phase(const Pattern &P, int64_t num, int64_t den, int32_t max_cluster,
             const int64_t sa = ++stamp;
             int64_t na = 0;
             for (int32_t m = a; m >= 0; m = next[m])
-                for (int64_t q = 0; q < P.len(m); ++q) {
-                    const int32_t c = P.cols(m)[q];
+                for (int64_t q = 0; q < Q.len(m); ++q) {
+                    const int32_t c = Q.cols(m)[q];
                     if (mark[c] != sa) {
                         mark[c] = sa;
                         ++na;
@@ -435,8 +515,8 @@ int merge_phase(const Pattern &P, int64_t num, int64_t den, int32_t max_cluster,
             const int64_t sb = ++stamp;
             int64_t nb = 0, ov = 0;
             for (int32_t m = b; m >= 0; m = next[m])
-                for (int64_t q = 0; q < P.len(m); ++q) {
-                    const int32_t c = P.cols(m)[q];
+                for (int64_t q = 0; q < Q.len(m); ++q) {
+                    const int32_t c = Q.cols(m)[q];
                     if (mark[c] == sb) continue;
                     if (mark[c] == sa) ++ov;
                     mark[c] = sb;
@@ -444,9 +524,15 @@ int merge_phase(const Pattern &P, int64_t num, int64_t den, int32_t max_cluster,
                 }
             return Sim{ov, na + nb - ov};
         };
-        while (!heap.empty()) {
-            const Cand top = heap.top();
-            heap.pop();
+        size_t ip = 0;
+        while (ip < init.size() || !heap.empty()) {
+            Cand top;
+            if (heap.empty() || (ip < init.size() && less(heap.top(), init[ip]))) {
+                top = init[ip++];
+            } else {
+                top = heap.top();
+                heap.pop();
+            }
             const int32_t i = top.i, j = top.j;
             if (parent[i] == i && parent[j] == j) {
                 if (size[i] + size[j] <= max_cluster) {
@@ -460,11 +546,11 @@ int merge_phase(const Pattern &P, int64_t num, int64_t den, int32_t max_cluster,
             const int32_t ri = uf_find(parent, i), rj = uf_find(parent, j);
             if (ri == rj) continue;
             const int32_t a = std::min(ri, rj), b = std::max(ri, rj);
-            if (cand.contains(pair_key(a, b))) continue;
-            const Sim s = sim_flags == HCSP_SIM_UNION ? union_sim(a, b) : jaccard(P, a, b);
+            if (topk > 0 && listed(a, b)) continue;
+            const Sim s = sim_flags == HCSP_SIM_UNION ? union_sim(a, b) : jaccard(Q, a, b);
             if (cmp_thr(s, num, den) > 0) {
                 heap.push(Cand{s, a, b});
-                cand.insert(pair_key(a, b));
+                pushed.insert(pair_key(a, b));
             }
         }
         return emit(P, parent, next, perm_out_h, cl_row_ptr_h, ncl);
