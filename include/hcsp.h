@@ -233,6 +233,10 @@ int hcsp_cluster_fill(const hcsp_csr *A, const hcsp_csr_cluster *out, void *stre
  * hcsp_spgemm_symbolic: the symbolic phase (paper, "SpGEMM Kernel").
  * Writes C_row_ptr_d[A.nrows+1] (offsets of C in A's original row order) and
  * fills *info (host).  Synchronizes twice (after binning and to read nnz).
+ * Rows of units too long for shared memory are counted in (row, column
+ * chunk) pairs whose counts the workspace keeps (room for 4 per row plus
+ * 2^22); HCSP_E_CAPACITY if a product needs more (a larger
+ * opts->win_chunk_log2 gives fewer chunks).
  *
  * hcsp_spgemm_numeric: the numeric phase.  C_col_d/C_val_d hold `capacity`
  * entries starting at global entry opts->out_base, so a caller can compute

@@ -51,7 +51,12 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->dense_slots = windows ? 0 : dense_slots;
     ws->dense_bits = (uint32_t *)take(4 * (size_t)ws->dense_words * ws->dense_slots);
     ws->dense_vals = (double *)take(8 * (size_t)std::max<int64_t>(ncols, 1) * ws->dense_slots);
-    ws->chunk_cnt = (int32_t *)take(windows ? 4 * (size_t)kWinChunksMax * (size_t)std::max<int64_t>(nrows, nunits) : 0);
+    // counts of the symbolic window launch's (row, chunk) pairs: room for 4
+    // per row plus 4M (chunks follow the products, about products / 2^16 per
+    // unit; a launch that needs more fails with HCSP_E_CAPACITY)
+    ws->win_cap = windows ? 4 * std::max<int64_t>(nrows, nunits) + (1 << 22) : 0;
+    ws->chunk_cnt = (int32_t *)take(4 * (size_t)ws->win_cap);
+    ws->sym_base = (int64_t *)take(windows ? 8 * nu : 0);
     ws->win_base = (int64_t *)take(windows ? 8 * (nu + 1) : 0);
     ws->bytes = align_up(off, 256);
     return ws->bytes;
@@ -290,7 +295,9 @@ static SpArgs base_args(const hcsp_operand *A, const hcsp_csr *B, const Workspac
     a.dense_words = ws.dense_words;
     a.probes = ws.probes;
     a.chunk_cnt = ws.chunk_cnt;
+    a.sym_base = ws.sym_base;
     a.win_base = ws.win_base;
+    a.win_cap = ws.win_cap;
     a.win_log2 = tu.win_log2;
     a.ncols = B->ncols;
     a.unit_lo = 0;
@@ -610,9 +617,14 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.bin_hist, kNumBins, ws.num_count, ws.order_num, s));
     int64_t ncnt[HCSP_MAX_BINS];
     int64_t nnz = 0;
+    uint32_t e = 0;
     HCSP_HIP(hipMemcpyAsync(ncnt, ws.num_count, 8 * kNumBins, hipMemcpyDeviceToHost, s));
     HCSP_HIP(hipMemcpyAsync(&nnz, C_row_ptr_d + v.nrows, 8, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipMemcpyAsync(&e, ws.err, 4, hipMemcpyDeviceToHost, s));
     HCSP_HIP(hipStreamSynchronize(s));
+    if (e & kErrWindows)
+        return fail(HCSP_E_CAPACITY, "more (row, chunk) pairs of long rows than the workspace holds (raise "
+                                     "opts.win_chunk_log2 for fewer chunks)");
     info->nnz = nnz;
     info->units = v.nunits;
     for (int b = 0; b < kNumBins; ++b) info->num_bin_count[b] = ncnt[b];
@@ -674,6 +686,7 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
         HCSP_HIP(hipStreamSynchronize(s));
         if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "output capacity too small for the requested units");
         if (e & kErrCount) return fail(HCSP_E_INVALID, "row counts differ from the symbolic phase (inputs changed?)");
+        if (e & kErrWindows) return fail(HCSP_E_INVALID, "chunk counts of long rows missing (no matching symbolic call)");
     }
     return HCSP_OK;
 }

@@ -1271,7 +1271,7 @@ __device__ __forceinline__ int64_t win_find(const int64_t *base, int64_t count, 
 // chunk c of nch (wave-uniform).
 struct WinPair {
     int u, c, nch;
-    int64_t row;
+    int64_t row, first;  // first: the unit's first pair in this launch
     WinRow r;
 };
 
@@ -1283,6 +1283,7 @@ __device__ __forceinline__ WinPair win_pair(const SpArgs &a, int64_t i)
     const int64_t b0 = (int64_t)uniform64((uint64_t)a.win_base[p]);
     const int64_t np = (int64_t)uniform64((uint64_t)a.win_base[p + 1]) - b0;
     w.u = uniform(a.order[a.bin_begin + p]);
+    w.first = b0;
     const UnitView v = unit_view<CL>(a, w.u);
     w.nch = (int)(np / v.s);
     const int loc = (int)(i - b0);
@@ -1298,7 +1299,8 @@ __device__ __forceinline__ WinPair win_pair(const SpArgs &a, int64_t i)
 }
 
 // Symbolic: one wavefront per (row, chunk); the chunk's count goes to
-// chunk_cnt and is added to the row's count (zeroed by the binning kernel).
+// chunk_cnt[pair] and is added to the row's count (zeroed by the binning
+// kernel); the unit's first pair goes to sym_base.
 template <bool CL>
 __global__ void __launch_bounds__(64) k_sym_win(SpArgs a)
 {
@@ -1327,9 +1329,13 @@ __global__ void __launch_bounds__(64) k_sym_win(SpArgs a)
             w0 = w1;
         }
         if (lane == 0) {
-            a.chunk_cnt[w.row * kWinChunksMax + w.c] = (int32_t)n;
+            if (i < a.win_cap) a.chunk_cnt[i] = (int32_t)n;
+            else atomicOr(a.err, kErrWindows);
             if (n) atomicAdd((unsigned long long *)&a.c_rp[w.row], (unsigned long long)n);
-            if (w.c == 0 && w.r.l == 0) a.ucount[w.u] = INT32_MAX;
+            if (w.c == 0 && w.r.l == 0) {
+                a.ucount[w.u] = INT32_MAX;
+                a.sym_base[w.u] = w.first;
+            }
         }
     }
 }
@@ -1353,8 +1359,15 @@ __global__ void __launch_bounds__(64) k_num_win(SpArgs a)
         int lo, hi;
         if (chunked) {
             win_chunk(a.ncols, w.nch, w.c, &lo, &hi);
-            // this chunk's entries follow those of the chunks before it
-            const int32_t *cc = a.chunk_cnt + w.row * kWinChunksMax;
+            // this chunk's entries follow those of the chunks before it; the
+            // symbolic launch numbered the same (member, chunk) pairs from
+            // the unit's first pair
+            const int64_t cb = (int64_t)uniform64((uint64_t)a.sym_base[w.u]) + (int64_t)w.r.l * w.nch;
+            if (cb < 0 || cb + w.nch > a.win_cap) {
+                if (lane == 0) atomicOr(a.err, kErrWindows);
+                continue;
+            }
+            const int32_t *cc = a.chunk_cnt + cb;
             int64_t before = 0;
             for (int x = lane; x < w.c; x += 64) before += cc[x];
             for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o);

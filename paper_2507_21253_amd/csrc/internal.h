@@ -95,12 +95,14 @@ struct Workspace {
     double *dense_vals;
     int64_t dense_words; // 32-bit words per bitmap
     int dense_slots;
-    // column-window path (rows of units too long for shared memory): per row
-    // of C and column chunk, the chunk's distinct output columns
-    // [rows][kWinChunksMax]; per unit of a window launch its first (row,
-    // chunk) pair [nunits + 1]
+    // column-window path (rows of units too long for shared memory): the
+    // distinct output columns of each (row, chunk) pair of the symbolic
+    // window launch [win_cap]; per unit its first pair there [nunits]; per
+    // unit of a window launch its first pair [nunits + 1]
     int32_t *chunk_cnt;
+    int64_t *sym_base;
     int64_t *win_base;
+    int64_t win_cap;
     size_t bytes;
 };
 
@@ -174,7 +176,9 @@ struct SpArgs {
     // per-row first (row, chunk) pair of the launch
     const int64_t *probes;
     int32_t *chunk_cnt;
+    int64_t *sym_base;
     int64_t *win_base;
+    int64_t win_cap;
     int win_log2;
     // batch launches: the products, their unit bases [nprob+1], the bin's
     // unit count and start in device memory, per-product error words
@@ -197,7 +201,14 @@ struct SpArgs {
 };
 
 // error flag bits
-enum : uint32_t { kErrCapacity = 1u, kErrCount = 2u, kErrPtr = 4u, kErrRange = 8u, kErrUnsorted = 16u };
+enum : uint32_t {
+    kErrCapacity = 1u,
+    kErrCount = 2u,
+    kErrPtr = 4u,
+    kErrRange = 8u,
+    kErrUnsorted = 16u,
+    kErrWindows = 32u,  // more (row, chunk) pairs than the workspace holds counts for
+};
 
 // launchers (kernels.hip)
 // batch = true: persistent launches over a batch (unit ids are batch-wide,

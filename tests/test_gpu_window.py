@@ -170,3 +170,19 @@ def test_rmat_clusters_on_window_path():
         C = hc.spgemm(Dc, Rd, o)
         torch.cuda.synchronize()
         assert_same(C.to_host(), ref, str(o))
+
+
+def test_too_many_window_pairs_is_reported():
+    # 20,000 rows of 4,096 products each, all on the window path and cut into
+    # 256 chunks each: 5.1M (row, chunk) pairs, more than the workspace holds
+    # counts for (4 per row + 4M); the call fails cleanly, and fewer chunks fit
+    A = synth.uniform(20_000, 2_000, 16, 41)
+    B = synth.uniform(2_000, 100_000, 256, 42)
+    Ad, Bd = hc.DeviceCSR.from_host(A), hc.DeviceCSR.from_host(B)
+    with pytest.raises(hc.HcspError) as e:
+        hc.spgemm(Ad, Bd, hc.opts(sym_tmax_log2=7, num_tmax=96, win_chunk_log2=4))
+    assert "win_chunk_log2" in str(e.value)
+    torch.cuda.synchronize()
+    C = hc.spgemm(Ad, Bd, hc.opts(sym_tmax_log2=7, num_tmax=96, win_chunk_log2=12))
+    torch.cuda.synchronize()
+    assert_same(C.to_host(), oracle.spgemm(A, B))
