@@ -864,13 +864,14 @@ static int64_t pred_entries(float ratio, int64_t products, int64_t nrows)
 
 struct PredWs {
     int64_t *pad_off, *novf;
+    int2 *span;  // first and last column of each row of B
     uint8_t *active;
     int32_t *scol;
     double *sval;
     int64_t entries;
 };
 
-static size_t layout_pred(size_t base_bytes, int64_t nrows, int64_t entries, char *base, PredWs *p)
+static size_t layout_pred(size_t base_bytes, int64_t nrows, int64_t brows, int64_t entries, char *base, PredWs *p)
 {
     size_t off = base_bytes;
     auto take = [&](size_t bytes) -> void * {
@@ -881,6 +882,7 @@ static size_t layout_pred(size_t base_bytes, int64_t nrows, int64_t entries, cha
     };
     p->pad_off = (int64_t *)take(8 * ((size_t)nrows + 1));
     p->novf = (int64_t *)take(8);
+    p->span = (int2 *)take(8 * (size_t)std::max<int64_t>(brows, 1));
     p->active = (uint8_t *)take((size_t)std::max<int64_t>(nrows, 1));
     p->scol = (int32_t *)take(4 * (size_t)entries);
     p->sval = (double *)take(8 * (size_t)entries);
@@ -906,7 +908,7 @@ int hcsp_predicted_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_op
     Workspace ws;
     const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, nullptr, &ws);
     PredWs p;
-    *bytes = layout_pred(base, v.nrows, pred_entries(ratio, products, v.nrows), nullptr, &p);
+    *bytes = layout_pred(base, v.nrows, B->nrows, pred_entries(ratio, products, v.nrows), nullptr, &p);
     return HCSP_OK;
 }
 
@@ -931,7 +933,7 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     Workspace ws;
     const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, (char *)ws_d, &ws);
     PredWs pw;
-    const size_t need = layout_pred(base, v.nrows, pred_entries(ratio, products, v.nrows), (char *)ws_d, &pw);
+    const size_t need = layout_pred(base, v.nrows, B->nrows, pred_entries(ratio, products, v.nrows), (char *)ws_d, &pw);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "predicted-size workspace too small");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = v.nrows;
@@ -945,6 +947,8 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     BinArgs ba = bin_args(&op, B, ws, tu, n, C_row_ptr_d);
     ba.ratio = ratio;
     ba.pad = pw.pad_off;
+    ba.b_span = pw.span;
+    HCSP_HIP(launch_row_span(B->row_ptr, B->col, B->nrows, pw.span, s));
     HCSP_HIP(launch_work_pred(ba, s));
     HCSP_HIP(launch_scatter(ws.bin, n, ws.bin_hist, kNumBins, ws.num_count, ws.order_num, s));
     HCSP_HIP(launch_scan_exclusive(pw.pad_off, n + 1, ws.scan_tmp, s));
@@ -959,25 +963,31 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     a.c_val = pw.sval;
     a.cap = pw.entries;
     a.pad_off = pw.pad_off;
+    // the bins' launches, the largest on s and the others on side streams
+    std::vector<int64_t> pbegin(kNumBins), pwork(kNumBins, 0);
     int64_t start = 0;
     for (int b = 0; b < kNumBins; ++b) {
-        const int64_t c = cnt[b];
-        if (c > 0 && b != kBinEmpty && b != kNumGlobal) {
-            a.bin_begin = start;
-            a.count = c;
-            a.T = num_table((b - 1) % kNumT);
-            a.vcap = num_vcap(a.T, tu.load_pct);
-            const int64_t gb = num_wave_bytes(false, 0, a.T, tu.load_pct);
-            a.group_bytes = (int)gb;
-            int blocks, threads;
-            size_t lds;
-            geometry(gb, c, &blocks, &threads, &lds, true);
-            rc = ensure_lds(lds, tu.lds_budget);
-            if (rc) return rc;
-            HCSP_HIP(launch_num_pred(a, blocks, threads, lds, s));
-        }
-        start += c;
+        pbegin[b] = start;
+        start += cnt[b];
+        if (cnt[b] > 0 && b != kBinEmpty && b != kNumGlobal) pwork[b] = cnt[b] * num_table((b - 1) % kNumT);
     }
+    rc = run_bins(s, pwork, [&](int b, hipStream_t st) -> int {
+        SpArgs ab = a;
+        ab.bin_begin = pbegin[b];
+        ab.count = cnt[b];
+        ab.T = num_table((b - 1) % kNumT);
+        ab.vcap = num_vcap(ab.T, tu.load_pct);
+        const int64_t gb = num_wave_bytes(false, 0, ab.T, tu.load_pct);
+        ab.group_bytes = (int)gb;
+        int blocks, threads;
+        size_t lds;
+        geometry(gb, cnt[b], &blocks, &threads, &lds, true);
+        const int e = ensure_lds(lds, tu.lds_budget);
+        if (e) return e;
+        HCSP_HIP(launch_num_pred(ab, blocks, threads, lds, st));
+        return HCSP_OK;
+    });
+    if (rc) return rc;
     // 3. rows the prediction did not hold: exact symbolic (it also scans every
     //    row's count into offsets), else just the scan
     int64_t novf = 0, nnz = 0;

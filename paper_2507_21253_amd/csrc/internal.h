@@ -264,6 +264,7 @@ struct BinArgs {
     // predicted sizes: row capacity min(products, ceil(products * ratio)) into pad[]
     float ratio;
     int64_t *pad;
+    const int2 *b_span;  // predicted sizes: first and last column of each row of B (nullable)
 };
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
@@ -285,6 +286,8 @@ hipError_t launch_max_i64(const int64_t *x, int64_t n, int64_t *out, hipStream_t
 // predicted sizes
 hipError_t launch_products(const hcsp_csr &A, const hcsp_csr &B, int64_t *out, hipStream_t s);
 hipError_t launch_work_pred(const BinArgs &a, hipStream_t s);
+// span[k] = (first, last) column of row k of B; (INT_MAX, -1) for an empty row
+hipError_t launch_row_span(const int64_t *rp, const int32_t *col, int64_t n, int2 *span, hipStream_t s);
 hipError_t launch_mark_overflow(const int64_t *c_rp, int64_t n, uint8_t *active, int64_t *count, hipStream_t s);
 hipError_t launch_copy_rows(const int64_t *pad_off, const int32_t *scol, const double *sval, const int64_t *c_rp,
                             const uint8_t *active, int64_t n, int32_t *C_col, double *C_val, int64_t cap,

@@ -263,8 +263,9 @@ __global__ void __launch_bounds__(256) k_work_pred(BinArgs a)
             const int64_t b0 = a.b_rp[k], b1 = a.b_rp[k + 1];
             if (b1 > b0) {
                 probes += b1 - b0;
-                lo = min(lo, a.b_col[b0]);
-                hi = max(hi, a.b_col[b1 - 1]);
+                const int2 sp = a.b_span ? a.b_span[k] : make_int2(a.b_col[b0], a.b_col[b1 - 1]);
+                lo = min(lo, sp.x);
+                hi = max(hi, sp.y);
             }
         }
         probes = gsum64(g, probes);
@@ -299,6 +300,22 @@ __global__ void __launch_bounds__(256) k_work_pred(BinArgs a)
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kNumBins; i += blockDim.x) a.ws.bin_hist[(int64_t)blockIdx.x * HCSP_MAX_BINS + i] = hist[i];
+}
+
+__global__ void __launch_bounds__(256) k_row_span(const int64_t *rp, const int32_t *col, int64_t n, int2 *span)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b0 = rp[k], b1 = rp[k + 1];
+        span[k] = b1 > b0 ? make_int2(col[b0], col[b1 - 1]) : make_int2(INT_MAX, -1);
+    }
+}
+
+hipError_t launch_row_span(const int64_t *rp, const int32_t *col, int64_t n, int2 *span, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_row_span, dim3((unsigned)blocks), dim3(256), 0, s, rp, col, n, span);
+    return hipGetLastError();
 }
 
 hipError_t launch_work_pred(const BinArgs &a, hipStream_t s)
