@@ -268,7 +268,8 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
  * cl_val_ptr_d[nclusters+1] (device) and returns ncc and nslots (host) so
  * the caller can allocate cl_col (int32 [ncc]), cl_mask (uint16 [ncc]) and
  * cl_val (double [nslots]).  Synchronizes.  HCSP_E_UNSUPPORTED when a
- * cluster's union did not fit a shared-memory table (global-memory path).
+ * cluster's union did not fit a shared-memory table (its rows take the
+ * column-window path, which writes CSR only).
  *
  * hcsp_spgemm_numeric_cluster: the numeric phase writing C as CSR_Cluster.
  * C: nrows, nclusters as A's, ncols = B.ncols, ncc and nslots from the

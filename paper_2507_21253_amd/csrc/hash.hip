@@ -772,7 +772,8 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
 }
 
 // ================================================================ global-memory path
-// Units whose tables do not fit in shared memory.  Each wavefront owns a
+// Units of a batch whose tables do not fit in shared memory (single products
+// take the column-window path below instead).  Each wavefront owns a
 // bitmap over all columns of B (and, numeric, a value array of the same
 // width) in the workspace and takes units one after another; the products
 // are walked in the same 64-wide passes as above.  Cluster members are done

@@ -27,7 +27,8 @@ int fail(int code, const std::string &msg);
 // before each phase.  A bin fixes the cluster-size class (S = 1, 2, 4, 8, 16)
 // and the shared-memory table size, so one launch handles units of one
 // shape.  Bin 0 holds units with no work; the last bin holds units too big
-// for shared memory (the dense global-memory path).
+// for shared memory (the column-window path in single products, the dense
+// global-memory path in batches).
 constexpr int kSClasses = 5;                 // S = 1 << sclass
 constexpr int kSymLog2Min = 6;               // symbolic tables: 64 .. 2^kSymLog2Max slots
 constexpr int kSymLog2Max = 14;
@@ -274,7 +275,7 @@ hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
 // batches
 // CSR_Cluster output layout: per cluster its union count and union count x
 // members, [nunits] = 0 (exclusive scans then give the offsets and totals);
-// a unit of the global-memory path (count INT32_MAX) sets *err.
+// a unit counted by column chunks (count INT32_MAX) sets *err.
 hipError_t launch_cl_out_counts(const int32_t *ucount, const int64_t *cl_row_ptr, int64_t nunits, int64_t *colp,
                                 int64_t *valp, uint32_t *err, hipStream_t s);
 // SpGEMM_TopK: per row of the overlap matrix O (rows: original ids) the

@@ -1,5 +1,5 @@
 // Views of a work unit (a CSR row, or a CSR_Cluster cluster) shared by the
-// shared-memory and the dense global-memory kernels.
+// shared-memory, column-window and dense global-memory kernels.
 #pragma once
 #include "device.h"
 #include "internal.h"
