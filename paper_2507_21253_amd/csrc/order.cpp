@@ -14,6 +14,7 @@
 // in the order of their lowest-(degree, id) vertex, and the whole sequence
 // is reversed at the end.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <new>
 #include <thread>
@@ -30,10 +31,71 @@ struct Graph {
     std::vector<int64_t> deg;
 };
 
+// f(lo, hi) over [0, n) split into contiguous ranges on the host's threads.
+template <class F>
+void parallel_ranges(int64_t n, F f)
+{
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 64,
+                                                               (n + 65535) / 65536}));
+    if (nt == 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t t = 0; t < nt; ++t) th.emplace_back(f, n * t / nt, n * (t + 1) / nt);
+    for (auto &x : th) x.join();
+}
+
+// Whether A's pattern is symmetric (j in row i iff i in row j; rows sorted):
+// each entry looks itself up in the other row, rows split over the threads.
+bool pattern_symmetric(const hcsp_csr &A)
+{
+    std::atomic<bool> ok(true);
+    parallel_ranges(A.nrows, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi && ok.load(std::memory_order_relaxed); ++i)
+            for (int64_t p = A.row_ptr[i]; p < A.row_ptr[i + 1]; ++p) {
+                const int64_t j = A.col[p];
+                const int32_t *b = A.col + A.row_ptr[j], *e = A.col + A.row_ptr[j + 1];
+                const int32_t *f = std::lower_bound(b, e, (int32_t)i);
+                if (f == e || *f != (int32_t)i) {
+                    ok.store(false, std::memory_order_relaxed);
+                    break;
+                }
+            }
+    });
+    return ok.load();
+}
+
 // Pattern of A + A^T without the diagonal, duplicate-free.
 void build_graph(const hcsp_csr &A, Graph &g)
 {
     const int64_t n = A.nrows;
+    if (pattern_symmetric(A)) {
+        // A + A^T has A's pattern: rows copied without the diagonal
+        g.ptr.assign((size_t)n + 1, 0);
+        g.deg.assign((size_t)n, 0);
+        parallel_ranges(n, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) {
+                int64_t d = A.row_ptr[i + 1] - A.row_ptr[i];
+                const int32_t *b = A.col + A.row_ptr[i], *e = A.col + A.row_ptr[i + 1];
+                if (std::binary_search(b, e, (int32_t)i)) --d;
+                g.deg[(size_t)i] = d;
+            }
+        });
+        for (int64_t i = 0; i < n; ++i) g.ptr[(size_t)i + 1] = g.ptr[(size_t)i] + g.deg[(size_t)i];
+        g.adj.resize((size_t)g.ptr[(size_t)n]);
+        parallel_ranges(n, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) {
+                auto o = g.adj.begin() + g.ptr[(size_t)i];
+                for (int64_t p = A.row_ptr[i]; p < A.row_ptr[i + 1]; ++p)
+                    if (A.col[p] != i) *o++ = A.col[p];
+                std::sort(g.adj.begin() + g.ptr[(size_t)i], o, [&](int32_t x, int32_t y) {
+                    return g.deg[(size_t)x] != g.deg[(size_t)y] ? g.deg[(size_t)x] < g.deg[(size_t)y] : x < y;
+                });
+            }
+        });
+        return;
+    }
     std::vector<int64_t> cnt((size_t)n + 1, 0);
     for (int64_t i = 0; i < n; ++i)
         for (int64_t p = A.row_ptr[i]; p < A.row_ptr[i + 1]; ++p) {
@@ -54,21 +116,26 @@ void build_graph(const hcsp_csr &A, Graph &g)
         }
     g.ptr.assign((size_t)n + 1, 0);
     g.deg.assign((size_t)n, 0);
-    for (int64_t i = 0; i < n; ++i) {
-        auto b = raw.begin() + cnt[(size_t)i], e = raw.begin() + cnt[(size_t)i + 1];
-        std::sort(b, e);
-        g.deg[(size_t)i] = std::unique(b, e) - b;
-        g.ptr[(size_t)i + 1] = g.ptr[(size_t)i] + g.deg[(size_t)i];
-    }
+    // rows are independent: sorted and de-duplicated on the host's threads
+    parallel_ranges(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            auto b = raw.begin() + cnt[(size_t)i], e = raw.begin() + cnt[(size_t)i + 1];
+            std::sort(b, e);
+            g.deg[(size_t)i] = std::unique(b, e) - b;
+        }
+    });
+    for (int64_t i = 0; i < n; ++i) g.ptr[(size_t)i + 1] = g.ptr[(size_t)i] + g.deg[(size_t)i];
     g.adj.resize((size_t)g.ptr[(size_t)n]);
-    for (int64_t i = 0; i < n; ++i) {
-        std::copy(raw.begin() + cnt[(size_t)i], raw.begin() + cnt[(size_t)i] + g.deg[(size_t)i],
-                  g.adj.begin() + g.ptr[(size_t)i]);
-        auto b = g.adj.begin() + g.ptr[(size_t)i], e = g.adj.begin() + g.ptr[(size_t)i + 1];
-        std::sort(b, e, [&](int32_t x, int32_t y) {
-            return g.deg[(size_t)x] != g.deg[(size_t)y] ? g.deg[(size_t)x] < g.deg[(size_t)y] : x < y;
-        });
-    }
+    parallel_ranges(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            std::copy(raw.begin() + cnt[(size_t)i], raw.begin() + cnt[(size_t)i] + g.deg[(size_t)i],
+                      g.adj.begin() + g.ptr[(size_t)i]);
+            auto b = g.adj.begin() + g.ptr[(size_t)i], e = g.adj.begin() + g.ptr[(size_t)i + 1];
+            std::sort(b, e, [&](int32_t x, int32_t y) {
+                return g.deg[(size_t)x] != g.deg[(size_t)y] ? g.deg[(size_t)x] < g.deg[(size_t)y] : x < y;
+            });
+        }
+    });
 }
 
 inline bool before(const Graph &g, int64_t x, int64_t y)

@@ -126,8 +126,8 @@ def test_workspace_query_is_host_only():
     n = ctypes.c_size_t()
     rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b), None, ctypes.byref(n))
     assert rc == 0 and n.value > 0
-    # CSR rows too long for shared memory take the column-window path: per-row
-    # chunk counts in the workspace instead of dense accumulators
+    # rows too long for shared memory take the column-window path, whose chunk
+    # size option is checked with the other options
     for bad in (3, 31, -1):
         rc = hc.lib().hcsp_spgemm_workspace(ctypes.byref(op), ctypes.byref(b),
                                             ctypes.byref(hc.opts(win_chunk_log2=bad)), ctypes.byref(n))
@@ -183,6 +183,19 @@ def test_orderings_match_oracle():
         if A.nrows == A.ncols:
             np.testing.assert_array_equal(hc.order_rcm(A), oracle.order_rcm(A), err_msg=name)
         np.testing.assert_array_equal(hc.order_degree(A), oracle.order_degree(A), err_msg=name)
+    # square patterns that are not symmetric (A + A^T is built explicitly), and one that is
+    # symmetric but for a single entry
+    for seed in (5, 6):
+        A = synth.uniform(400, 400, 5, seed)
+        np.testing.assert_array_equal(hc.order_rcm(A), oracle.order_rcm(A), err_msg="uniform %d" % seed)
+    S = synth.stencil(27, 5, 2)
+    rp, col = S.rp.copy(), S.col.copy()
+    keep = np.ones(len(col), bool)
+    keep[rp[3] + 1] = False  # drop one off-diagonal entry of row 3 only
+    lens = np.diff(rp) - np.add.reduceat(~keep, rp[:-1]).astype(np.int64)
+    A = synth.HostCSR(np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), col[keep], S.val[keep], S.nrows,
+                      S.ncols)
+    np.testing.assert_array_equal(hc.order_rcm(A), oracle.order_rcm(A), err_msg="stencil minus one entry")
 
 
 def test_permute_h_is_the_symmetric_permutation():
