@@ -41,6 +41,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def csr_bytes(nrows: int, nnz: int) -> int:
     return 8 * (nrows + 1) + 12 * nnz
 
@@ -586,10 +596,19 @@ def main():
             Cref = oracle.spgemm_mt(M, M, nth)
             runs.append(time.perf_counter() - t)
         assert Cref.nnz == nnzC
-        tcpu = float(np.mean(runs))
-        cpu = {"value": round(flop / tcpu / 1e9, 3), "unit": "GFLOP/s", "cores": nth, "kind": "oracle",
-               "sample": "full C = M*M (count pass + fill pass), mean of %d runs, %.2f s each" % (len(runs), tcpu)}
         del Cref
+        tcpu = float(np.mean(runs))
+        # one thread on a bounded slice of the rows (the first 1/16)
+        hi1 = M.nrows // 16
+        flop1 = 2 * int(rowlen[M.col[:M.rp[hi1]]].sum())
+        t = time.perf_counter()
+        oracle.spgemm(M, M, (0, hi1))
+        t1 = time.perf_counter() - t
+        cpu = {"value": round(flop / tcpu / 1e9, 3), "unit": "GFLOP/s", "cores": nth, "kind": "oracle",
+               "sample": "full C = M*M (count pass + fill pass), mean of %d runs, %.2f s each" % (len(runs), tcpu),
+               "cpu_model": cpu_model(),
+               "single_thread": {"value": round(flop1 / t1 / 1e9, 3), "unit": "GFLOP/s",
+                                 "sample": "rows [0, %d) of C = M*M on one thread, %.2f s" % (hi1, t1)}}
 
     out = {
         "metric": "SpGEMM GFLOP/s + achieved HBM GB/s, CSR_Cluster vs plain CSR on 1 MI355X",
