@@ -961,11 +961,12 @@ hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int block
 }
 
 // ================================================================ column windows
-// CSR rows whose tables do not fit in shared memory.  A row's output columns
-// are cut into chunks of equal column range (more for rows with more
-// products, win_nchunks), and each chunk into
-// windows [w0, w1) that one wavefront takes one after another with a
-// shared-memory table.  A window's products are the entries of the rows of
+// Units of a single product whose tables do not fit in shared memory: their
+// rows (a CSR row, or each member row of a cluster) are taken one by one.  A
+// row's output columns are cut into chunks of equal column range (more for
+// units with more products, win_nchunks), and each chunk into windows
+// [w0, w1) that one wavefront takes one after another with a shared-memory
+// table.  A window's products are the entries of the rows of
 // B that fall inside it (found by binary search, the rows of B being sorted),
 // walked in ascending k as everywhere else, so every output entry still
 // receives its products in ascending k, one fma each from +0.0.  Window widths
