@@ -15,7 +15,10 @@
 // ascending k, each by one fma starting from +0.0 — the same sequence the
 // row-by-row Gustavson reference performs.  Entries of one row of B have
 // distinct columns, so lanes of one sub-step never share a slot, and the
-// wavefront's LDS operations stay in program order across sub-steps.
+// wavefront's LDS operations stay in program order across sub-steps.  When
+// every item of a round has at most 32 products (stencil-like rows), the
+// numeric phase walks the round two items per pass instead, one per half of
+// the wavefront, and applies the two halves in two fixed sub-steps.
 //
 // The kernels are bound by instruction issue, so the pass loop is written
 // to keep the common path branch-free: a probe is one LDS compare-and-swap
@@ -206,7 +209,7 @@ int64_t num_wave_bytes(bool cl, int sclass, int T, int load_pct)
 // off0 products of the item at q0 were taken by earlier rounds).  Returns the
 // number of products in the round.
 __device__ __forceinline__ int flatten_round(int64_t it1, int64_t &q0, int &off0, ItemRec *items, uint64_t *sbits,
-                                             int64_t bs, int bl, uint32_t rx, uint32_t ry)
+                                             int64_t bs, int bl, uint32_t rx, uint32_t ry, int *nitems = nullptr)
 {
     const int lane = (int)__lane_id();
     if (lane == 0) {
@@ -219,6 +222,7 @@ __device__ __forceinline__ int flatten_round(int64_t it1, int64_t &q0, int &off0
     const int E = uniform(min(__shfl(incl, 63), kRoundW));
     const bool in = blc > 0 && P < kRoundW;
     const uint64_t inb = __ballot(in);
+    if (nitems) *nitems = __popcll(inb);
     if (in) {
         ItemRec r;
         r.bs = (uint32_t)bs;
@@ -251,7 +255,8 @@ __device__ __forceinline__ int flatten_round(int64_t it1, int64_t &q0, int &off0
 // lane i also keeps the column's member values (areg, or aval[i*S ..]).
 template <bool CL, int S, bool NUM>
 __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, int64_t &q0, int &off0,
-                                          ItemRec *items, uint64_t *sbits, double *aval, double *areg)
+                                          ItemRec *items, uint64_t *sbits, double *aval, double *areg,
+                                          int *nitems = nullptr)
 {
     const int lane = (int)__lane_id();
     sbits[lane] = 0ull;
@@ -286,7 +291,7 @@ __device__ __forceinline__ int load_round(const SpArgs &a, const UnitView &v, in
     const uint64_t ab = (uint64_t)__double_as_longlong(a1);
     const uint32_t rx = CL && S > 1 ? m : (uint32_t)ab;
     const uint32_t ry = CL && S > 1 ? (uint32_t)lane : (uint32_t)(ab >> 32);
-    return flatten_round(v.it1, q0, off0, items, sbits, bs, bl, rx, ry);
+    return flatten_round(v.it1, q0, off0, items, sbits, bs, bl, rx, ry, nitems);
 }
 
 // One lane's share of one pass: its entry of the flattened product list.
@@ -459,7 +464,9 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
 // fit or exceed the capacity records -1 as its count and writes nothing;
 // otherwise its entries go to its padded slot (pad_off) and its count to
 // c_rp[row].
-template <int S, bool CL, bool PRED = false>
+// PAIRS: rounds of short items may be walked two items per pass (off in the
+// batch kernels, whose register budget is tighter).
+template <int S, bool CL, bool PRED = false, bool PAIRS = true>
 __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned char *base)
 {
     static_assert(!PRED || (S == 1 && !CL), "predicted sizes are for CSR rows");
@@ -563,9 +570,79 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         }
     };
 
+    // a round whose items have at most 32 products each is walked two items
+    // per pass, one per half of the wavefront: the products of the first half
+    // are applied before those of the second, so each output entry still gets
+    // its products in ascending k, in two fixed sub-steps per pass
+    auto paired_round = [&](int nit, int E) {
+        // each item's product count replaces its position in the record
+        const int t = lane;
+        const int Pt = t < nit ? items[t].P : 0;
+        const int Pn = t + 1 < nit ? items[t + 1].P : E;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (t < nit) items[t].P = Pn - Pt;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int half = lane >> 5, e = lane & 31;
+        constexpr int kP = Depth<S>::R;
+        for (int t0 = 0; t0 < nit; t0 += 2 * kP) {
+            int j[kP];
+            double b[kP];
+            ItemRec it[kP];
+            bool ok[kP];
+#pragma unroll
+            for (int rr = 0; rr < kP; ++rr) {
+                const int ti = t0 + 2 * rr + half;
+                it[rr] = items[min(ti, nit - 1)];
+                ok[rr] = ti < nit && e < it[rr].P;
+                const uint32_t off = ok[rr] ? it[rr].bs + (uint32_t)e : 0u;
+                const int jj = ld_col(a.b_col, off);
+                const double bb = ld_val(a.b_val, off);
+                j[rr] = ok[rr] ? jj : kDummyKey;
+                b[rr] = ok[rr] ? bb : 0.0;
+            }
+#pragma unroll
+            for (int rr = 0; rr < kP; ++rr) {
+                if (t0 + 2 * rr >= nit) break;
+                const int h = entry(probe(j[rr], std::false_type{}));
+                for (int hf = 0; hf < 2; ++hf) {
+                    if (half == hf && ok[rr]) {
+                        if (MS) {
+                            // the active lanes all hold item t0 + 2 rr + hf: its mask and
+                            // the lane with its member values are uniform among them
+                            const uint32_t mt = (uint32_t)uniform((int)it[rr].x);
+                            const int src = uniform((int)it[rr].y);
+                            mask_set<S>(masks, (uint32_t)h, mt);
+#pragma unroll
+                            for (int l = 0; l < S; ++l) {
+                                if ((mt >> l) & 1u) {
+                                    const double av = a_in_regs(S) ? readlane_f64(areg[l], src) : aval[src * S + l];
+                                    double *pv = &vals[l * VS + h];
+                                    *pv = __fma_rn(av, b[rr], *pv);
+                                }
+                            }
+                        } else {
+                            const double av = __longlong_as_double(((long long)it[rr].y << 32) | it[rr].x);
+                            vals[h] = __fma_rn(av, b[rr], vals[h]);
+                        }
+                    }
+                }
+            }
+        }
+    };
+
     constexpr int kR = Depth<S>::R;
     while (q0 < v.it1) {
-        const int E = load_round<CL, S, true>(a, v, q0, off0, items, sbits, aval, areg);
+        int nit = 0;
+        const int E = load_round<CL, S, true>(a, v, q0, off0, items, sbits, aval, areg, &nit);
+        {
+            const int t = lane;
+            const int Pt = t < nit ? items[t].P : 0;
+            const int Pn = t + 1 < nit ? items[t + 1].P : E;
+            if (PAIRS && uniform(nit) > 0 && __ballot(t < nit && Pn - Pt > 32) == 0ull) {
+                paired_round(uniform(nit), E);
+                continue;
+            }
+        }
         const int npass = (E + 63) >> 6;
         int cum = 0, p = 0;
         auto batch = [&](auto full_t) {
@@ -1453,7 +1530,7 @@ __device__ __forceinline__ void run_bin(const SpArgs &a0)
     for (int64_t i = begin + lw * count / W; i < e; ++i) {
         SpArgs a = a0;
         const int u = batch_resolve(a, a0.order[i]);
-        if (NUM) num_unit<S, CL>(a, u, base);
+        if (NUM) num_unit<S, CL, false, false>(a, u, base);
         else sym_unit<S, CL>(a, u, base);
     }
 }
