@@ -16,9 +16,10 @@
 // row-by-row Gustavson reference performs.  Entries of one row of B have
 // distinct columns, so lanes of one sub-step never share a slot, and the
 // wavefront's LDS operations stay in program order across sub-steps.  When
-// every item of a round has at most 32 products (stencil-like rows), the
-// numeric phase walks the round two items per pass instead, one per half of
-// the wavefront, and applies the two halves in two fixed sub-steps.
+// every item of a round has at most 32 products and they average at least 24
+// (stencil-like rows), the numeric phase walks the round two items per pass
+// instead, one per half of the wavefront, and applies the two halves in two
+// fixed sub-steps.
 //
 // The kernels are bound by instruction issue, so the pass loop is written
 // to keep the common path branch-free: a probe is one LDS compare-and-swap
@@ -570,8 +571,8 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         }
     };
 
-    // a round whose items have at most 32 products each is walked two items
-    // per pass, one per half of the wavefront: the products of the first half
+    // a round whose items have at most 32 products each (24 on average) is
+    // walked two items per pass, one per half of the wavefront: the products of the first half
     // are applied before those of the second, so each output entry still gets
     // its products in ascending k, in two fixed sub-steps per pass
     auto paired_round = [&](int nit, int E) {
@@ -638,7 +639,9 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
             const int t = lane;
             const int Pt = t < nit ? items[t].P : 0;
             const int Pn = t + 1 < nit ? items[t + 1].P : E;
-            if (PAIRS && uniform(nit) > 0 && __ballot(t < nit && Pn - Pt > 32) == 0ull) {
+            // two items per pass pay when they fill most of the lanes: at most
+            // 32 products each, at least 24 on average
+            if (PAIRS && uniform(nit) > 0 && E >= 24 * uniform(nit) && __ballot(t < nit && Pn - Pt > 32) == 0ull) {
                 paired_round(uniform(nit), E);
                 continue;
             }
