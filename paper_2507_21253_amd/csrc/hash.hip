@@ -819,36 +819,48 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         return;
     }
 
-    // ---- each member row's entries, in column order
+    // ---- each member row's entries, in column order: one sweep over the
+    // keys writes every member's row (a key goes to the rows of its mask)
     int64_t my_off = 0, my_want = 0;
     if (lane < v.s) {
         const int64_t row = member_row<CL>(a, v, lane);
         my_off = a.c_rp[row] - a.out_base;
         my_want = a.c_rp[row + 1] - a.c_rp[row];
     }
-    for (int l = 0; l < v.s; ++l) {
-        const int64_t roff = readlane_i64(my_off, l), rwant = readlane_i64(my_want, l);
-        int64_t w = 0;
-        for (int c0 = 0; c0 < U; c0 += 64) {
-            const int i = c0 + lane;
-            const int sl = i < U ? (int)order[i] : TX;
-            const int id = vidx[sl];
-            const bool has = (masks[id] >> l) & 1u && i < U;
+    int64_t roff[S], rwant[S], w[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        roff[l] = l < v.s ? readlane_i64(my_off, l) : 0;
+        rwant[l] = l < v.s ? readlane_i64(my_want, l) : 0;
+        w[l] = 0;
+    }
+    for (int c0 = 0; c0 < U; c0 += 64) {
+        const int i = c0 + lane;
+        const int sl = i < U ? (int)order[i] : TX;
+        const int id = vidx[sl];
+        const uint32_t m = i < U ? (uint32_t)masks[id] : 0u;
+        const int key = keys[sl];
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+            if (l >= v.s) break;
+            const bool has = (m >> l) & 1u;
             const uint64_t bal = __ballot(has);
             if (has) {
-                const int64_t pos = w + __popcll(bal & lanemask_lt(lane));
-                const int64_t dst = roff + pos;
-                if (dst >= 0 && dst < a.cap && pos < rwant) {
-                    a.c_col[dst] = keys[sl];
+                const int64_t pos = w[l] + __popcll(bal & lanemask_lt(lane));
+                const int64_t dst = roff[l] + pos;
+                if (dst >= 0 && dst < a.cap && pos < rwant[l]) {
+                    a.c_col[dst] = key;
                     a.c_val[dst] = vals[l * VS + id];
                 } else {
                     atomicOr(a.err, kErrCapacity);
                 }
             }
-            w += __popcll(bal);
+            w[l] += __popcll(bal);
         }
-        if (lane == 0 && w != rwant) atomicOr(a.err, kErrCount);
     }
+#pragma unroll
+    for (int l = 0; l < S; ++l)
+        if (l < v.s && lane == 0 && w[l] != rwant[l]) atomicOr(a.err, kErrCount);
 }
 
 // ================================================================ global-memory path
