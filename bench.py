@@ -5,8 +5,8 @@ Workload (default): C = M*M for M the 27-point stencil on a 100^3 grid with
 values U(-1,1), symmetrically relabelled by a seeded random permutation so
 the natural locality is gone.  The method recovers it: A's rows are put in
 reverse Cuthill-McKee order, hierarchical clustering (Alg. 3, jacc_th 0.3,
-at most 2 rows per cluster by default -- the autotuner's choice; the paper
-uses 8) regroups similar rows into CSR_Cluster, and the product runs
+at most 4 rows per cluster by default -- the autotuner's choice for this
+matrix class; the paper uses 8) regroups similar rows into CSR_Cluster, and the product runs
 cluster-wise (Alg. 1) against B = M.  The baseline is the plain row-wise
 product of M in its given order.  One step = symbolic phase (binning, counts,
 scan), the nnz read-back, and the numeric phase of the clustered product;

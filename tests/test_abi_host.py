@@ -83,6 +83,20 @@ def test_plan_from_given_candidates_matches_oracle(sim, t, maxc):
                       oracle.plan_hierarchical(A, t, maxc, sim, pi))
 
 
+def test_plan_hierarchical_hand_examples_both_readings():
+    # the library's plans on the hand-worked examples, under both readings of the merged-cluster similarity
+    import json
+    from test_oracle import csr_from_rows
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hierarchical_hand_examples.json")))
+    for ex in g["examples"]:
+        A = csr_from_rows(ex["rows"], ex["ncols"])
+        for case in ex["cases"]:
+            for sim, key in ((hc.SIM_ROOT, "expected_clusters_root"), (hc.SIM_UNION, "expected_clusters_union")):
+                p = hc.plan_hierarchical(A, tuple(case["jacc_th"]), case["max_cluster"], sim, 1)
+                got = [p.perm[p.cl_row_ptr[c]:p.cl_row_ptr[c + 1]].tolist() for c in range(p.nclusters)]
+                assert got == case.get(key, case.get("expected_clusters")), case["trace"]
+
+
 def test_plan_from_candidates_rejects_bad_lists():
     A = synth.stencil(27, 4, 2)
     cnt, nbr, ov, _ = oracle.topk_candidates(A, (3, 10), 3)

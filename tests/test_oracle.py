@@ -303,9 +303,25 @@ def test_hierarchical_hand_examples():
     for ex in g["examples"]:
         A = csr_from_rows(ex["rows"], ex["ncols"])
         for case in ex["cases"]:
-            for flags in (oracle.SIM_ROOT, oracle.SIM_UNION):
+            for flags, key in ((oracle.SIM_ROOT, "expected_clusters_root"), (oracle.SIM_UNION, "expected_clusters_union")):
                 plan = oracle.plan_hierarchical(A, tuple(case["jacc_th"]), case["max_cluster"], flags)
-                assert plan.clusters() == case["expected_clusters"], case["trace"]
+                assert plan.clusters() == case.get(key, case.get("expected_clusters")), case["trace"]
+
+
+def test_hierarchical_similarity_readings_differ_on_hand_example():
+    # the hand-worked example whose lifted pair passes the threshold only when the members' unions are
+    # scored: the two readings of the merged-cluster similarity must give different plans
+    g = json.load(open(os.path.join(GOLDEN, "hierarchical_hand_examples.json")))
+    seen = 0
+    for ex in g["examples"]:
+        A = csr_from_rows(ex["rows"], ex["ncols"])
+        for case in ex["cases"]:
+            if "expected_clusters_union" in case and case["expected_clusters_union"] != case["expected_clusters_root"]:
+                r = oracle.plan_hierarchical(A, tuple(case["jacc_th"]), case["max_cluster"], oracle.SIM_ROOT)
+                u = oracle.plan_hierarchical(A, tuple(case["jacc_th"]), case["max_cluster"], oracle.SIM_UNION)
+                assert r.clusters() != u.clusters()
+                seen += 1
+    assert seen >= 1
 
 
 @pytest.mark.parametrize("seed", range(4))
