@@ -121,7 +121,9 @@ typedef struct hcsp_ratio {
 
 /* Product options.  Zero-initialised means: defaults, whole matrix. */
 enum {
-    HCSP_F_SYNC_CHECK = 1   /* numeric: synchronize and report out-of-range writes as HCSP_E_CAPACITY */
+    HCSP_F_SYNC_CHECK = 1,  /* numeric: synchronize and report out-of-range writes as HCSP_E_CAPACITY */
+    HCSP_F_ONE_STREAM = 2   /* every launch on the caller's stream (by default the bins of a phase are
+                               spread over side streams forked from it and joined back into it) */
 };
 typedef struct hcsp_opts {
     int32_t lanes;          /* lanes per row/cluster: 0 = automatic (one 64-lane wavefront) or 64 */
@@ -232,7 +234,11 @@ int hcsp_cluster_fill(const hcsp_csr *A, const hcsp_csr_cluster *out, void *stre
  *
  * hcsp_spgemm_symbolic: the symbolic phase (paper, "SpGEMM Kernel").
  * Writes C_row_ptr_d[A.nrows+1] (offsets of C in A's original row order) and
- * fills *info (host).  Synchronizes twice (after binning and to read nnz).
+ * fills *info (host).  Synchronizes twice: after binning, because the host
+ * sizes each bin's launch (table size and grid) from the bin counts, and to
+ * read nnz(C).  A product that must be captured into a graph runs through
+ * hcsp_spgemm_batched (a batch of one), whose launches read the bin counts
+ * from device memory.
  * Rows of units too long for shared memory are counted in (row, column
  * chunk) pairs whose counts the workspace keeps (room for 4 per row plus
  * 2^22); HCSP_E_CAPACITY if a product needs more (a larger
@@ -244,6 +250,14 @@ int hcsp_cluster_fill(const hcsp_csr *A, const hcsp_csr_cluster *out, void *stre
  * hcsp_spgemm_symbolic call on the same A, B, opts and workspace, and the
  * workspace must not have been touched since.  Asynchronous unless
  * HCSP_F_SYNC_CHECK is set.
+ *
+ * hcsp_spgemm_status: the errors the kernels of the last numeric call on
+ * this workspace recorded (hcsp_spgemm_numeric, _numeric_cluster,
+ * _predicted; the symbolic phase clears them): HCSP_E_CAPACITY when an
+ * output write fell outside the capacity given (the write was dropped),
+ * HCSP_E_INVALID when a row's count differs from the symbolic phase's (the
+ * inputs changed in between) or the long rows' chunk counts are missing.
+ * Reads 4 bytes at offset 0 of ws_d; synchronizes.
  */
 int hcsp_spgemm_workspace(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts,
                           size_t *bytes);
@@ -254,6 +268,7 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
                         const hcsp_sym_info *info, const int64_t *C_row_ptr_d, int32_t *C_col_d,
                         double *C_val_d, int64_t capacity, void *ws_d, size_t ws_bytes,
                         void *stream);
+int hcsp_spgemm_status(const void *ws_d, size_t ws_bytes, void *stream);
 
 /*
  * C in CSR_Cluster form (paper, Alg. 1, which writes C cluster by cluster):
@@ -339,11 +354,23 @@ int hcsp_permute_h(const hcsp_csr *A_h, const int32_t *rperm_h, const int32_t *c
                    int32_t nthreads);
 
 /*
+ * hcsp_csr_transpose: At = A^T on the device (paper, Alg. 3 forms the
+ * transpose of A for SpGEMM_TopK(A, A^T)).  At->nrows = A->ncols, At->ncols =
+ * A->nrows, At->nnz = A->nnz; At->row_ptr[A->ncols+1] and At->col[nnz] are
+ * caller-allocated and written with ascending columns per row; At->val is
+ * written too when it is not NULL (then A->val must be set), else only the
+ * pattern is formed.  ws_d: hcsp_csr_transpose_workspace(A->nrows, A->ncols)
+ * bytes.  Asynchronous.
+ */
+int hcsp_csr_transpose_workspace(int64_t nrows, int64_t ncols, size_t *bytes);
+int hcsp_csr_transpose(const hcsp_csr *A, hcsp_csr *At, void *ws_d, size_t ws_bytes, void *stream);
+
+/*
  * hcsp_topk_candidates: the candidate search of the hierarchical plan
  * (paper, Alg. 3, SpGEMM_TopK) on the GPU.  O (device CSR, n x n) is the
  * overlap matrix A A^T of A's pattern: O_ij = number of columns rows i and j
- * share, e.g. the library's own product of A with all values 1 and A^T (A
- * itself for a structurally symmetric A).  a_rp_d: A's row offsets (row
+ * share, e.g. the library's own product of A's pattern (all values 1) with
+ * its transpose from hcsp_csr_transpose.  a_rp_d: A's row offsets (row
  * lengths |S_i|).  pos_d[n]: position of each row in the plan order (the
  * inverse of perm_in; NULL = identity).  For every row i, the partners j != i
  * with J = O_ij / (|S_i| + |S_j| - O_ij) strictly above jacc_th, best first

@@ -31,6 +31,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_PTR", -3: "E_RANGE", -4: "E_UNSORTED"
 OP_CSR, OP_CLUSTER = 0, 1
 SIM_ROOT, SIM_UNION = 0, 1
 F_SYNC_CHECK = 1
+F_ONE_STREAM = 2
 MAX_BINS = 96
 
 i64, i32, u32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p
@@ -99,6 +100,9 @@ _SIGS = {
                               ctypes.POINTER(c_sym_info), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "hcsp_spgemm_numeric": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
                              ctypes.POINTER(c_sym_info), vp, vp, vp, i64, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_spgemm_status": ([vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_csr_transpose_workspace": ([i64, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hcsp_csr_transpose": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "hcsp_cluster_output_layout": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
                                     ctypes.POINTER(c_sym_info), vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
                                     ctypes.c_size_t, vp], ctypes.c_int),
@@ -335,14 +339,37 @@ def plan_hierarchical(A_host, jacc_th=(3, 10), max_cluster: int = 8, sim=SIM_ROO
     return Plan(perm[:A_host.nrows], crp[:ncl.value + 1].copy())
 
 
-def topk_candidates_gpu(A: "DeviceCSR", jacc_th=(3, 10), topk: int = 7, perm_in=None, stream=None):
-    """SpGEMM_TopK (Alg. 3) on the GPU for a structurally symmetric A: the overlap matrix A A^T is the
-    library's own product of A's pattern (all values 1) with itself, then one wavefront per row keeps its topk
-    best partners.  Returns host arrays in plan positions: (cnt[n], nbr[n, topk], ov[n, topk])."""
+def csr_transpose(A: "DeviceCSR", values: bool = True, stream=None) -> "DeviceCSR":
+    """A^T on the device (values gathered when ``values``; otherwise val is an empty tensor)."""
     import torch
     dev = A.row_ptr.device
-    ones = DeviceCSR(A.row_ptr, A.col, torch.ones(A.nnz, dtype=torch.float64, device=dev), A.nrows, A.ncols)
-    O = spgemm(ones, ones, stream=stream)
+    nb = ctypes.c_size_t()
+    _check(lib().hcsp_csr_transpose_workspace(A.nrows, A.ncols, ctypes.byref(nb)), "csr_transpose_workspace")
+    ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=dev)
+    T = DeviceCSR(torch.empty(A.ncols + 1, dtype=torch.int64, device=dev),
+                  torch.empty(A.nnz, dtype=torch.int32, device=dev),
+                  torch.empty(A.nnz if values else 0, dtype=torch.float64, device=dev), A.ncols, A.nrows)
+    a = A.c()
+    t = T.c()
+    if not values:
+        t.val = None
+    _check(lib().hcsp_csr_transpose(ctypes.byref(a), ctypes.byref(t), _tp(ws), ws.numel(), _stream(stream)),
+           "csr_transpose")
+    T._ws = ws  # kept alive until the asynchronous launches are done with it
+    return T
+
+
+def topk_candidates_gpu(A: "DeviceCSR", jacc_th=(3, 10), topk: int = 7, perm_in=None, stream=None):
+    """SpGEMM_TopK(A, A^T) (Alg. 3) on the GPU: the overlap matrix A A^T is the library's own product of A's
+    pattern (all values 1) with its transpose (formed on the device), then one wavefront per row keeps its
+    topk best partners.  Returns host arrays in plan positions: (cnt[n], nbr[n, topk], ov[n, topk])."""
+    import torch
+    dev = A.row_ptr.device
+    ones = torch.ones(A.nnz, dtype=torch.float64, device=dev)
+    P = DeviceCSR(A.row_ptr, A.col, ones, A.nrows, A.ncols)
+    Pt = csr_transpose(P, values=False, stream=stream)
+    Pt.val = ones                      # the pattern's values are all 1 on both sides
+    O = spgemm(P, Pt, stream=stream)
     n = A.nrows
     pos = None
     if perm_in is not None:
@@ -378,8 +405,8 @@ def plan_hierarchical_candidates(A_host, jacc_th, max_cluster: int, sim, cnt, nb
 
 def plan_hierarchical_gpu(A_host, A: "DeviceCSR", jacc_th=(3, 10), max_cluster: int = 8, sim=SIM_ROOT,
                           perm_in=None) -> Plan:
-    """hierarchical plan with the candidate search on the GPU (structurally symmetric A) and the merge loop
-    on the host; the same plan as plan_hierarchical."""
+    """hierarchical plan with the candidate search on the GPU and the merge loop on the host; the same plan
+    as plan_hierarchical."""
     if max_cluster <= 1:
         return plan_hierarchical(A_host, jacc_th, max_cluster, sim, perm_in=perm_in)
     cnt, nbr, ov = topk_candidates_gpu(A, jacc_th, max_cluster - 1, perm_in)
@@ -493,6 +520,11 @@ def spgemm_symbolic(A, B: DeviceCSR, C_row_ptr, ws, o: c_opts | None = None, str
     return info
 
 
+def spgemm_status(ws, stream=None):
+    """Raises HcspError if the kernels of the last numeric call on this workspace recorded an error."""
+    _check(lib().hcsp_spgemm_status(_tp(ws), ws.numel(), _stream(stream)), "spgemm_status")
+
+
 def spgemm_numeric(A, B: DeviceCSR, info: c_sym_info, C_row_ptr, C_col, C_val, ws, o: c_opts | None = None,
                    capacity: int | None = None, stream=None):
     op = operand(A)
@@ -532,9 +564,17 @@ class Product:
         spgemm_numeric(self.A, self.B, self.info, self.C_row_ptr, self.C_col, self.C_val, self.ws, self.o,
                        capacity=self.info.nnz, stream=stream)
 
-    def run(self, stream=None) -> DeviceCSR:
+    def check(self, stream=None):
+        """Raises if the last numeric phase recorded an error (synchronizes)."""
+        spgemm_status(self.ws, stream)
+
+    def run(self, stream=None, check: bool = True) -> DeviceCSR:
+        """Both phases; with ``check`` the numeric phase's error word is read back (one more
+        synchronization), else call ``check()`` after a series of runs."""
         nnz = self.symbolic(stream)
         self.numeric(stream)
+        if check:
+            self.check(stream)
         return DeviceCSR(self.C_row_ptr, self.C_col[:nnz], self.C_val[:nnz], self.A.nrows, self.B.ncols)
 
 

@@ -35,6 +35,7 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
         return p;
     };
     const size_t nu = (size_t)std::max<int64_t>(nunits, 1);
+    ws->err = (uint32_t *)take(256);  // first: hcsp_spgemm_status reads it at offset 0
     ws->probes = (int64_t *)take(8 * nu);
     ws->keylo = (int32_t *)take(4 * nu);
     ws->keyhi = (int32_t *)take(4 * nu);
@@ -45,7 +46,6 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->sym_count = (int64_t *)take(8 * HCSP_MAX_BINS);
     ws->num_count = (int64_t *)take(8 * HCSP_MAX_BINS);
     ws->bin_hist = (int32_t *)take(4 * (size_t)kBinBlocks * HCSP_MAX_BINS);
-    ws->err = (uint32_t *)take(256);
     ws->scan_tmp = (int64_t *)take(8 * scan_tmp_elems(std::max(nrows, nunits) + 1));
     ws->dense_words = (std::max<int64_t>(ncols, 1) + 31) / 32;
     ws->dense_slots = windows ? 0 : dense_slots;
@@ -132,7 +132,7 @@ static SideStreams *side_streams()
 // (last), the others on the side streams (first).  The side streams are
 // joined back into s also when a launch fails; returns the first error.
 template <class F>
-static int run_bins(hipStream_t s, const std::vector<int64_t> &work, F launch)
+static int run_bins(hipStream_t s, const std::vector<int64_t> &work, bool one_stream, F launch)
 {
     int big = -1, nb = 0;
     for (int b = 0; b < (int)work.size(); ++b) {
@@ -141,7 +141,7 @@ static int run_bins(hipStream_t s, const std::vector<int64_t> &work, F launch)
         if (big < 0 || work[b] > work[big]) big = b;
     }
     std::lock_guard<std::mutex> lk(g_side_mu);
-    SideStreams *x = nb > 1 ? side_streams() : nullptr;
+    SideStreams *x = nb > 1 && !one_stream ? side_streams() : nullptr;
     if (x && hipEventRecord(x->fork, s) != hipSuccess) x = nullptr;
     bool used[kSide] = {false, false, false};
     int k = 0, rc = HCSP_OK;
@@ -178,6 +178,7 @@ static int make_tune(const hcsp_opts *o, const hcsp_csr *B, bool need_device, Tu
     if (!o) o = &z;
     if (o->lanes != 0 && o->lanes != 64) return fail(HCSP_E_INVALID, "opts.lanes must be 0 or 64");
     t->G = 64;
+    t->one_stream = (o->flags & HCSP_F_ONE_STREAM) != 0;
     t->load_pct = o->load_pct ? o->load_pct : 60;
     if (t->load_pct < 10 || t->load_pct > 95) return fail(HCSP_E_INVALID, "opts.load_pct must be in 10..95");
     t->sym_load_pct = o->sym_load_pct ? o->sym_load_pct : 70;
@@ -587,7 +588,7 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
         if (cnt[b] > 0 && b != kBinEmpty)
             work[b] = b == kSymGlobal ? INT64_MAX / 2 : cnt[b] << ((b - 1) % kSymT + kSymLog2Min);
     }
-    rc = run_bins(s, work, [&](int b, hipStream_t t) -> int {
+    rc = run_bins(s, work, tu.one_stream, [&](int b, hipStream_t t) -> int {
         const int64_t c = cnt[b];
         a.bin_begin = begin[b];
         a.count = c;
@@ -706,7 +707,7 @@ static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, cons
         start += c;
         if (c > 0 && b != kBinEmpty) work[b] = b == kNumGlobal ? INT64_MAX / 2 : c * num_table((b - 1) % kNumT);
     }
-    return run_bins(s, work, [&](int b, hipStream_t st) -> int {
+    return run_bins(s, work, tu.one_stream, [&](int b, hipStream_t st) -> int {
         const int64_t c = info->num_bin_count[b];
         a.bin_begin = begin[b];
         a.count = c;
@@ -764,6 +765,45 @@ int hcsp_topk_candidates(const hcsp_csr *O, const int64_t *a_rp_d, const int32_t
     if (O->nrows > 0 && (!a_rp_d || !cnt_d || !nbr_d || !ov_d)) return fail(HCSP_E_INVALID, "topk: null array");
     HCSP_HIP(launch_topk(O->row_ptr, O->col, O->val, a_rp_d, pos_d, O->nrows, jacc_th.num, jacc_th.den, topk, cnt_d,
                          nbr_d, ov_d, (hipStream_t)stream));
+    return HCSP_OK;
+}
+
+int hcsp_spgemm_status(const void *ws_d, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (!ws_d || ws_bytes < 256) return fail(HCSP_E_INVALID, "status: not a SpGEMM workspace");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t e = 0;
+    HCSP_HIP(hipMemcpyAsync(&e, ws_d, 4, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipStreamSynchronize(s));
+    if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "output capacity too small for the requested units");
+    if (e & kErrCount) return fail(HCSP_E_INVALID, "row counts differ from the symbolic phase (inputs changed?)");
+    if (e & kErrWindows) return fail(HCSP_E_INVALID, "chunk counts of long rows missing (no matching symbolic call)");
+    return HCSP_OK;
+}
+
+int hcsp_csr_transpose_workspace(int64_t nrows, int64_t ncols, size_t *bytes)
+{
+    clear_error();
+    if (!bytes || nrows < 0 || ncols < 0) return fail(HCSP_E_INVALID, "transpose: bad arguments");
+    TrWs w;
+    *bytes = layout_transpose(nrows, ncols, nullptr, &w);
+    return HCSP_OK;
+}
+
+int hcsp_csr_transpose(const hcsp_csr *A, hcsp_csr *At, void *ws_d, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    const bool vals = At && At->val;
+    int rc = check_csr_shape(A, "A", vals);
+    if (rc) return rc;
+    if (!At || At->nrows != A->ncols || At->ncols != A->nrows || At->nnz != A->nnz || !At->row_ptr ||
+        (A->nnz > 0 && !At->col))
+        return fail(HCSP_E_INVALID, "transpose: At must be ncols x nrows with nnz entries and its arrays set");
+    TrWs w;
+    const size_t need = layout_transpose(A->nrows, A->ncols, (char *)ws_d, &w);
+    if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "transpose workspace too small");
+    HCSP_HIP(launch_transpose(*A, *At, w, (hipStream_t)stream));
     return HCSP_OK;
 }
 
@@ -971,7 +1011,7 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
         start += cnt[b];
         if (cnt[b] > 0 && b != kBinEmpty && b != kNumGlobal) pwork[b] = cnt[b] * num_table((b - 1) % kNumT);
     }
-    rc = run_bins(s, pwork, [&](int b, hipStream_t st) -> int {
+    rc = run_bins(s, pwork, tu.one_stream, [&](int b, hipStream_t st) -> int {
         SpArgs ab = a;
         ab.bin_begin = pbegin[b];
         ab.count = cnt[b];

@@ -75,6 +75,7 @@ struct Tune {
     int dense_slots;     // concurrent dense accumulators
     int win_log2;        // column-window path: products per column chunk, log2
     int64_t lds_budget;  // shared memory per workgroup we plan for
+    bool one_stream;     // every launch on the caller's stream (no side streams)
 };
 
 // ------------------------------------------------------------ workspace
@@ -304,6 +305,18 @@ int bin_blocks(int64_t nunits);
 hipError_t launch_scan_exclusive(int64_t *data, int64_t n, int64_t *tmp, hipStream_t s);
 size_t scan_tmp_elems(int64_t n);
 hipError_t launch_csr_check(const hcsp_csr &A, uint32_t *flags, hipStream_t s);
+
+// launchers (transpose.hip): A^T of a device CSR matrix (values when At.val is set)
+struct TrWs {
+    int64_t *cursor;    // [ncols] next free slot of each row of A^T
+    int32_t *mid, *lng; // [ncols] rows of A^T for the two larger sorts
+    uint32_t *counts;   // [0] mid rows, [1] long rows
+    uint32_t *bits;     // bitmaps over A's rows, one per long-row block
+    int64_t words;      // 32-bit words per bitmap
+    int64_t *scan_tmp;
+};
+size_t layout_transpose(int64_t nrows, int64_t ncols, char *base, TrWs *w);
+hipError_t launch_transpose(const hcsp_csr &A, const hcsp_csr &At, const TrWs &w, hipStream_t s);
 
 // launchers (cluster.hip)
 hipError_t launch_cluster_count(const hcsp_csr &A, const int32_t *perm, const int64_t *cl_row_ptr, int64_t ncl,
