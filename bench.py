@@ -91,6 +91,7 @@ def parse():
                    help="only the three timed products (no GPU-assisted plan, CSR_Cluster output or learned legs; "
                         "for counter runs that attribute launches by their order)")
     p.add_argument("--cpu-threads", type=int, default=0)
+    p.add_argument("--cpu-runs", type=int, default=10, help="timed runs of the CPU oracle (mean and median)")
     return p.parse_args()
 
 
@@ -113,6 +114,28 @@ def numeric_traffic(key: str, config: str):
     if not m or m.group(3) != h.hexdigest()[:16] or m.group(4) != config:
         return None
     return int(m.group(1) if key == "clustered" else m.group(2))
+
+
+def copy_bandwidth(torch, n=1 << 28, reps=5):
+    """GB/s (read + write) of a plain device copy of 2 GiB of float64 on the current stream."""
+    try:
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+    except RuntimeError:
+        return None
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 16 * n / ms / 1e6
 
 
 def copy_mode(args):
@@ -388,8 +411,9 @@ def batch_mode(args):
     print(json.dumps(out), flush=True)
 
 
-def time_product(P, steps, warmup, torch):
-    """Runs warmup + timed steps of symbolic+numeric; returns per-step wall ms and phase ms."""
+def time_product(P, steps, warmup, torch, detail=None):
+    """Runs warmup + timed steps of symbolic+numeric; returns per-step wall ms and phase ms (means over the
+    steps).  ``detail`` (a dict), when given, receives the per-step event times and their medians."""
     for _ in range(warmup):
         P.run()
     torch.cuda.synchronize()
@@ -407,9 +431,13 @@ def time_product(P, steps, warmup, torch):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
     P.check()                                  # errors the kernels recorded in the timed runs
-    sym = float(np.mean([a.elapsed_time(b) for a, b, c in ev]))
-    num = float(np.mean([b.elapsed_time(c) for a, b, c in ev]))
-    return wall, sym, num
+    syms = [a.elapsed_time(b) for a, b, c in ev]
+    nums = [b.elapsed_time(c) for a, b, c in ev]
+    if detail is not None:
+        detail.update({"step_ms_median": float(np.median([x + y for x, y in zip(syms, nums)])),
+                       "symbolic_ms_median": float(np.median(syms)), "numeric_ms_median": float(np.median(nums)),
+                       "numeric_ms": nums})
+    return wall, float(np.mean(syms)), float(np.mean(nums))
 
 
 def main():
@@ -508,7 +536,8 @@ def main():
                    sym_load_pct=args.sym_load_pct or tuned["sym_load_pct"])
     P_cl = hc.Product(Dc, Bd, o_cl)
     P_pl = hc.Product(Md, Md, o)
-    wall_cl, sym_cl, num_cl = time_product(P_cl, args.steps, args.warmup, torch)
+    det_cl = {}
+    wall_cl, sym_cl, num_cl = time_product(P_cl, args.steps, args.warmup, torch, det_cl)
     nnzC = P_cl.info.nnz
     wall_pl, sym_pl, num_pl = time_product(P_pl, args.steps, args.warmup, torch)
     assert P_pl.info.nnz == nnzC
@@ -544,11 +573,17 @@ def main():
         torch.cuda.synchronize()
         wall_pp = (time.perf_counter() - t) * 1e3 / args.steps
         assert PP.nnz == nnzC
+        # the predicted-size C equals the clustered product's C bit for bit (which the CPU leg below
+        # compares with the oracle's C)
+        pred_equal = bool(torch.equal(PP.C_row_ptr, P_cl.C_row_ptr) and torch.equal(PP.C_col[:nnzC], P_cl.C_col[:nnzC])
+                          and torch.equal(PP.C_val[:nnzC].view(torch.int64), P_cl.C_val[:nnzC].view(torch.int64)))
+        assert pred_equal, "predicted-size and clustered products differ"
         learned_out = {"selector_choice": learned.PATHS[int(np.argmax(z[:len(learned.PATHS)]))],
                        "ratio_predicted": round(ratio_pred, 4), "ratio_true": round(nnzC / products, 4),
                        "margin": args.margin, "predicted_size_product": {
                            "ms_per_step": round(wall_pp, 4), "gflops": round(flop / (wall_pp * 1e-3) / 1e9, 3),
-                           "rows_recomputed_exactly": int(PP.n_overflow)}}
+                           "rows_recomputed_exactly": int(PP.n_overflow),
+                           "equals_clustered_bitwise": pred_equal}}
         log("learned: %s" % learned_out)
         del PP
 
@@ -578,27 +613,35 @@ def main():
     bytes_A = csr_bytes(M.nrows, M.nnz)
     bytes_Acl = Dc.bytes()
     bytes_C = csr_bytes(M.nrows, nnzC)
-    comp_cl = bytes_Acl + bytes_A + bytes_C          # A in CSR_Cluster, B = M in CSR, C
-    comp_pl = 2 * bytes_A + bytes_C
+    comp = 2 * bytes_A + bytes_C                     # compulsory traffic |A| + |B| + |C| (CSR sizes)
+    comp_cl = bytes_Acl + bytes_A + bytes_C          # the same with A in its CSR_Cluster form
     gflops_cl = flop / (wall_cl * 1e-3) / 1e9
     gflops_pl = flop / (wall_pl * 1e-3) / 1e9
-    # dominant kernel family: the numeric launches; its algorithmic bytes are A (clustered), B and C
-    ach = comp_cl / (num_cl * 1e-3) / 1e9
+    # dominant kernel family: the numeric launches of one product; algorithmic bytes |A| + |B| + |C|
+    ach = comp / (num_cl * 1e-3) / 1e9
+    ach_step = comp / (wall_cl * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(torch)
     traffic = numeric_traffic("clustered", "m%d_%s%s_mc%d_%s_s%d_n%d" % (
         m, args.reorder, "sym" if args.symmetric else "", args.max_cluster, args.sim, o_cl.sym_load_pct,
         o_cl.load_pct))
 
     cpu = None
+    oracle_equal = None
     if not args.no_cpu:
         import oracle
         nth = args.cpu_threads or ncpu
         oracle.spgemm_mt(M, M, nth, structure_only=True)  # warm the pages
         runs = []
-        for _ in range(2):
+        for _ in range(args.cpu_runs):
             t = time.perf_counter()
             Cref = oracle.spgemm_mt(M, M, nth)
             runs.append(time.perf_counter() - t)
-        assert Cref.nnz == nnzC
+        # the timed clustered C against the oracle's C, entry by entry (row offsets, columns, value bits)
+        oracle_equal = bool(np.array_equal(P_cl.C_row_ptr.cpu().numpy(), Cref.rp)
+                            and np.array_equal(P_cl.C_col[:nnzC].cpu().numpy(), Cref.col)
+                            and np.array_equal(P_cl.C_val[:nnzC].cpu().numpy().view(np.int64),
+                                               Cref.val.view(np.int64)))
+        assert oracle_equal, "the clustered product differs from the oracle"
         del Cref
         tcpu = float(np.mean(runs))
         # one thread on a bounded slice of the rows (the first 1/16)
@@ -609,6 +652,7 @@ def main():
         t1 = time.perf_counter() - t
         cpu = {"value": round(flop / tcpu / 1e9, 3), "unit": "GFLOP/s", "cores": nth, "kind": "oracle",
                "sample": "full C = M*M (count pass + fill pass), mean of %d runs, %.2f s each" % (len(runs), tcpu),
+               "median_value": round(flop / float(np.median(runs)) / 1e9, 3),
                "cpu_model": cpu_model(),
                "single_thread": {"value": round(flop1 / t1 / 1e9, 3), "unit": "GFLOP/s",
                                  "sample": "rows [0, %d) of C = M*M on one thread, %.2f s" % (hi1, t1)}}
@@ -633,10 +677,15 @@ def main():
                    "jacc_th": "3/10", "max_cluster": args.max_cluster, "similarity": args.sim,
                    "sym_load_pct": o.sym_load_pct, "load_pct": o_cl.load_pct, "plain_load_pct": o.load_pct,
                    "autotuned": bool(tuned["tuned"])},
-        "gbs_compulsory": round(comp_cl / (wall_cl * 1e-3) / 1e9, 2),
+        "gbs_compulsory": round(comp / (wall_cl * 1e-3) / 1e9, 2),
+        "median": {"ms_per_step": round(det_cl["step_ms_median"], 4),
+                   "value": round(flop / (det_cl["step_ms_median"] * 1e-3) / 1e9, 3),
+                   "symbolic_ms": round(det_cl["symbolic_ms_median"], 4),
+                   "numeric_ms": round(det_cl["numeric_ms_median"], 4)},
+        "oracle_equal": oracle_equal,
         "phases_ms": {"symbolic_incl_readback": round(sym_cl, 4), "numeric": round(num_cl, 4)},
         "plain_csr": {"gflops": round(gflops_pl, 3), "ms_per_step": round(wall_pl, 4),
-                      "gbs_compulsory": round(comp_pl / (wall_pl * 1e-3) / 1e9, 2),
+                      "gbs_compulsory": round(comp / (wall_pl * 1e-3) / 1e9, 2),
                       "phases_ms": {"symbolic_incl_readback": round(sym_pl, 4), "numeric": round(num_pl, 4)}},
         "speedup_clustered_vs_plain": round(wall_pl / wall_cl, 3),
         "clustered_equals_plain_bitwise": None if args.symmetric else True,
@@ -651,9 +700,14 @@ def main():
                           "in_spgemms": round((t_reorder + t_plan + t_build) / (wall_cl * 1e-3), 1),
                           "nclusters": plan.nclusters, "ncc": Dc.ncc, "nslots": Dc.nslots,
                           "csr_cluster_over_csr_bytes": round(bytes_Acl / bytes_A, 3)},
-        "roofline": {"bound": "hbm", "kernel": "k_num (numeric phase launches)", "achieved": round(ach, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes": comp_cl},
+        "roofline": {"bound": "hbm", "kernel": "k_num (numeric phase launches of one product)",
+                     "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "algorithmic_bytes": comp,
+                     "algorithmic_bytes_csr_cluster_A": comp_cl,
+                     "frac_whole_step": round(ach_step / HBM_PEAK_GBS, 4),
+                     "achieved_whole_step": round(ach_step, 1),
+                     "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+                     "frac_of_copy": None if copy_gbs is None else round(ach / copy_gbs, 4)},
         "cpu_baseline": cpu,
         "learned": learned_out,
     }

@@ -63,6 +63,8 @@ def _load():
         lib.orc_spgemm_mt.restype = i64
         lib.orc_spgemm_rowstats.argtypes = [i64, vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, ctypes.c_int]
         lib.orc_spgemm_rowstats.restype = ctypes.c_int
+        lib.orc_spgemm_count.argtypes = [i64, vp, vp, vp, vp, i64, i64, vp, ctypes.c_int]
+        lib.orc_spgemm_count.restype = ctypes.c_int
         lib.orc_hash_cols.argtypes = [vp, i64]
         lib.orc_hash_cols.restype = ctypes.c_uint64
         lib.orc_dense_product.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp]
@@ -142,6 +144,16 @@ def spgemm_mt(A: HostCSR, B: HostCSR, nthreads: int, structure_only: bool = Fals
     if nnz2 != nnz:
         raise RuntimeError("orc_spgemm_mt fill failed")
     return HostCSR(rp, col, val, A.nrows, B.ncols)
+
+
+def spgemm_count(A: HostCSR, B: HostCSR, nthreads: int = 1, rows: tuple[int, int] | None = None) -> np.ndarray:
+    """Row counts of C = A*B (the structure: distinct columns per row) over rows ``rows`` of A (default all),
+    on ``nthreads`` host threads, without forming C."""
+    lo, hi = rows if rows else (0, A.nrows)
+    out = np.zeros(A.nrows, np.int64)
+    if _load().orc_spgemm_count(B.ncols, _p(A.rp), _p(A.col), _p(B.rp), _p(B.col), lo, hi, _p(out), nthreads):
+        raise RuntimeError("orc_spgemm_count failed")
+    return out[lo:hi]
 
 
 def rowstats(A: HostCSR, B: HostCSR, rows: np.ndarray | tuple[int, int], nthreads: int = 1):

@@ -10,6 +10,7 @@
  *   orc_spgemm*          Gustavson row-wise product C = A*B        [Background: SpGEMM Kernel, Fig. 1]
  *   orc_dense_product    brute-force dense triple loop (pin for the above)
  *   orc_jaccard          |Si n Sj| and |Si u Sj| of two rows        [Variable-length Clusters]
+ *   orc_spgemm_count     row counts of C only (structure)           [Background, SpGEMM Kernel]
  *   orc_plan_fixed       fixed-length clusters                      [Fixed-length Clusters]
  *   orc_plan_variable    variable-length clusters                   [Alg. 2]
  *   orc_topk_candidates  SpGEMM_TopK(A, A^T, topk, jacc_th)          [Alg. 3, Hierarchical Clusters]
@@ -145,6 +146,7 @@ int64_t orc_spgemm(int64_t p,
 
 typedef struct {
     int64_t p, lo, hi, phase;
+    int64_t *next;    /* shared cursor: the next unclaimed row */
     const int64_t *Arp; const int32_t *Acol; const double *Aval;
     const int64_t *Brp; const int32_t *Bcol; const double *Bval;
     int64_t *C_rp; int32_t *C_col; double *C_val;
@@ -164,27 +166,37 @@ static uint64_t hash_cols(const int32_t *c, int64_t n)
     return h;
 }
 
+/* Rows are handed out in chunks of MT_CHUNK from a shared cursor, so threads
+ * stay busy on inputs whose work is concentrated in a few rows; each row is
+ * computed exactly as by orc_spgemm. */
+#define MT_CHUNK 64
+
 static void *mt_worker(void *arg)
 {
     mtjob *j = (mtjob *)arg;
     rowws w;
     if (rowws_init(&w, j->p)) { rowws_free(&w); j->rc = -1; return NULL; }
-    for (int64_t i = j->lo; i < j->hi; ++i) {
-        int64_t cnt = gustavson_row(&w, i, j->Arp, j->Acol, j->Aval, j->Brp, j->Bcol, j->Bval);
-        if (j->phase == 0) {
-            j->row_nnz[i] = cnt;
-        } else if (j->phase == 1) {
-            int64_t o = j->C_rp[i];
-            for (int64_t t = 0; t < cnt; ++t) {
-                j->C_col[o + t] = w.list[t];
-                j->C_val[o + t] = w.acc[w.list[t]];
+    for (;;) {
+        int64_t c0 = __atomic_fetch_add(j->next, MT_CHUNK, __ATOMIC_RELAXED);
+        if (c0 >= j->hi) break;
+        int64_t c1 = c0 + MT_CHUNK < j->hi ? c0 + MT_CHUNK : j->hi;
+        for (int64_t i = c0; i < c1; ++i) {
+            int64_t cnt = gustavson_row(&w, i, j->Arp, j->Acol, j->Aval, j->Brp, j->Bcol, j->Bval);
+            if (j->phase == 0) {
+                j->row_nnz[i] = cnt;
+            } else if (j->phase == 1) {
+                int64_t o = j->C_rp[i];
+                for (int64_t t = 0; t < cnt; ++t) {
+                    j->C_col[o + t] = w.list[t];
+                    j->C_val[o + t] = w.acc[w.list[t]];
+                }
+            } else {
+                double s = 0.0;
+                for (int64_t t = 0; t < cnt; ++t) s += w.acc[w.list[t]];
+                j->row_nnz[i] = cnt;
+                j->row_hash[i] = hash_cols(w.list, cnt);
+                j->row_sum[i] = s;
             }
-        } else {
-            double s = 0.0;
-            for (int64_t t = 0; t < cnt; ++t) s += w.acc[w.list[t]];
-            j->row_nnz[i] = cnt;
-            j->row_hash[i] = hash_cols(w.list, cnt);
-            j->row_sum[i] = s;
         }
     }
     rowws_free(&w);
@@ -198,22 +210,23 @@ static int run_threads(int nthreads, int64_t lo, int64_t hi, mtjob proto)
     if (nthreads > 256) nthreads = 256;
     pthread_t th[256];
     mtjob jobs[256];
-    int64_t n = hi - lo;
+    int64_t next = lo;
     for (int t = 0; t < nthreads; ++t) {
         jobs[t] = proto;
-        jobs[t].lo = lo + (n * t) / nthreads;
-        jobs[t].hi = lo + (n * (t + 1)) / nthreads;
+        jobs[t].lo = lo;
+        jobs[t].hi = hi;
+        jobs[t].next = &next;
         jobs[t].rc = 0;
-        if (pthread_create(&th[t], NULL, mt_worker, &jobs[t])) return -1;
+        if (pthread_create(&th[t], NULL, mt_worker, &jobs[t])) { nthreads = t; break; }
     }
-    int rc = 0;
+    int rc = nthreads > 0 ? 0 : -1;
     for (int t = 0; t < nthreads; ++t) { pthread_join(th[t], NULL); if (jobs[t].rc) rc = jobs[t].rc; }
     return rc;
 }
 
 /*
- * Full product on `nthreads` host threads, rows split into equal contiguous
- * ranges; the same per-row Gustavson as orc_spgemm.  C_rp has nrows+1
+ * Full product on `nthreads` host threads (rows handed out in chunks); the
+ * same per-row Gustavson as orc_spgemm.  C_rp has nrows+1
  * entries.  Phase 0 counts, a host prefix sum sizes C, phase 1 fills.  If
  * C_col is NULL only C_rp is produced.  Returns nnz(C) or a negative code.
  */
@@ -257,6 +270,71 @@ int orc_spgemm_rowstats(int64_t p,
     proto.row_nnz = row_nnz; proto.row_hash = row_hash; proto.row_sum = row_sum;
     proto.phase = 2;
     return run_threads(nthreads, lo, hi, proto);
+}
+
+/*
+ * Structure of C = A*B only: row i's count is the number of distinct columns
+ * j in the rows of B that row i of A selects (the boolean product, the first
+ * phase of the two-phase product).  A bitmap over the columns of B marks the
+ * columns seen in the current row; it is cleared again by walking the same
+ * products.  Rows are handed out to `nthreads` threads in chunks.  Writes
+ * row_nnz[lo..hi) (absolute row index); returns 0, or -1 on allocation
+ * failure.
+ */
+typedef struct {
+    int64_t p, hi, *next, *row_nnz;
+    const int64_t *Arp, *Brp;
+    const int32_t *Acol, *Bcol;
+    int rc;
+} cntjob;
+
+static void *count_worker(void *arg)
+{
+    cntjob *j = (cntjob *)arg;
+    uint64_t *seen = (uint64_t *)calloc((size_t)(j->p / 64 + 1), sizeof(uint64_t));
+    if (!seen) { j->rc = -1; return NULL; }
+    for (;;) {
+        int64_t c0 = __atomic_fetch_add(j->next, MT_CHUNK, __ATOMIC_RELAXED);
+        if (c0 >= j->hi) break;
+        int64_t c1 = c0 + MT_CHUNK < j->hi ? c0 + MT_CHUNK : j->hi;
+        for (int64_t i = c0; i < c1; ++i) {
+            int64_t cnt = 0;
+            for (int64_t q = j->Arp[i]; q < j->Arp[i + 1]; ++q) {
+                int64_t k = j->Acol[q];
+                for (int64_t r = j->Brp[k]; r < j->Brp[k + 1]; ++r) {
+                    uint32_t c = (uint32_t)j->Bcol[r];
+                    uint64_t bit = 1ull << (c & 63);
+                    if (!(seen[c >> 6] & bit)) { seen[c >> 6] |= bit; ++cnt; }
+                }
+            }
+            for (int64_t q = j->Arp[i]; q < j->Arp[i + 1]; ++q) {
+                int64_t k = j->Acol[q];
+                for (int64_t r = j->Brp[k]; r < j->Brp[k + 1]; ++r) seen[(uint32_t)j->Bcol[r] >> 6] = 0;
+            }
+            j->row_nnz[i] = cnt;
+        }
+    }
+    free(seen);
+    j->rc = 0;
+    return NULL;
+}
+
+int orc_spgemm_count(int64_t p, const int64_t *Arp, const int32_t *Acol, const int64_t *Brp, const int32_t *Bcol,
+                     int64_t lo, int64_t hi, int64_t *row_nnz, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    cntjob jobs[256];
+    int64_t next = lo;
+    for (int t = 0; t < nthreads; ++t) {
+        cntjob z = {p, hi, &next, row_nnz, Arp, Brp, Acol, Bcol, 0};
+        jobs[t] = z;
+        if (pthread_create(&th[t], NULL, count_worker, &jobs[t])) { nthreads = t; break; }
+    }
+    int rc = nthreads > 0 ? 0 : -1;
+    for (int t = 0; t < nthreads; ++t) { pthread_join(th[t], NULL); if (jobs[t].rc) rc = jobs[t].rc; }
+    return rc;
 }
 
 /* Hash of a sorted column list, the same FNV-1a the row summary uses. */

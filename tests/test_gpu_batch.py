@@ -96,6 +96,28 @@ def test_batch_of_clustered_operands_bitwise():
     check_batch(bt, hosts)
 
 
+@pytest.mark.parametrize("sym,num", [(100, 70), (70, 50), (70, 70), (100, 50)])
+def test_batch_tuned_group_options_bitwise(sym, num):
+    # the table fills the autotuner picks for the benchmark's batch groups
+    hosts = problems(range(1500, 1512), 200, 6000)
+    bt = hc.Batch([(d, d) for d in map(dev, hosts)], hc.opts(sym_load_pct=sym, load_pct=num))
+    bt.run()
+    check_batch(bt, hosts)
+
+
+def test_batch_clustered_tuned_options_bitwise():
+    # clustered members as the tuner builds them: rows in RCM order, hierarchical clusters of at most 4
+    hosts = problems(range(1520, 1528), 500, 6000)
+    pairs = []
+    for H in hosts:
+        D = dev(H)
+        plan = hc.plan_hierarchical(H, (3, 10), 4, hc.SIM_ROOT, perm_in=oracle.order_rcm(H))
+        pairs.append((hc.cluster_build(D, plan), D))
+    bt = hc.Batch(pairs, hc.opts(sym_load_pct=100, load_pct=70))
+    bt.run()
+    check_batch(bt, hosts)
+
+
 def test_batch_graph_replays():
     # the whole launch sequence captured once; A's values change between
     # replays (same structure), eager work runs in between, every replay checked

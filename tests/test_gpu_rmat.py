@@ -2,9 +2,13 @@
 self-loops dropped, symmetrised, values 1.0) at full size: C = A*A has about
 2.4e10 entries (about 288 GB), more than one GPU holds beside its inputs, so
 the symbolic phase runs over all rows and the numeric phase in row panels.
-Checked: every row count against the oracle's count on sampled rows and
-against the product bound on all rows; sampled rows bit for bit, each
-computed as its own one-row panel; one large panel's sampled rows."""
+Checked: every row count against the oracle's structure count and the
+product bound; the 1,000 rows with the most products, and sampled rows, bit
+for bit, each computed as its own one-row panel; one large panel's sampled
+rows."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -40,10 +44,32 @@ def test_rmat20_symbolic_counts(rmat20):
     np.add.at(ub, np.repeat(np.arange(R.nrows), np.diff(R.rp)), np.diff(R.rp)[R.col])
     assert rp[0] == 0 and rp[-1] == nnz and np.all(cnt >= 0) and np.all(cnt <= ub)
     assert np.all((cnt == 0) == (ub == 0))
-    rng = np.random.default_rng(20)
-    rows = np.concatenate([rng.integers(0, R.nrows, 48), [int(np.argmax(ub)), int(np.argmax(cnt))]])
-    n_ref, _, _ = oracle.rowstats(R, R, rows)
-    np.testing.assert_array_equal(cnt[rows], n_ref)
+    # every row against the oracle's count of distinct columns (host threads, C never formed)
+    ref = oracle.spgemm_count(R, R, min(16, len(os.sched_getaffinity(0))))
+    bad = np.flatnonzero(cnt != ref)
+    assert bad.size == 0, "rows %s: gpu %s oracle %s" % (bad[:5], cnt[bad[:5]], ref[bad[:5]])
+    assert int(ref.sum()) == nnz
+
+
+def test_rmat20_heaviest_rows_bitwise(rmat20):
+    # the 1,000 rows with the most products (the column-window path's hub rows), each as a one-row panel
+    R, D, P, nnz = rmat20
+    rp = P.C_row_ptr.cpu().numpy()
+    ub = np.zeros(R.nrows, np.int64)
+    np.add.at(ub, np.repeat(np.arange(R.nrows), np.diff(R.rp)), np.diff(R.rp)[R.col])
+    rows = np.argsort(-ub, kind="stable")[:1000]
+    with ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)))) as ex:
+        refs = list(ex.map(lambda r: oracle.spgemm(R, R, (int(r), int(r) + 1)), rows))
+    width = int(max(rp[r + 1] - rp[r] for r in rows))
+    col = torch.empty(max(width, 1), dtype=torch.int32, device="cuda")
+    val = torch.empty(max(width, 1), dtype=torch.float64, device="cuda")
+    for r, ref in zip(rows, refs):
+        b, e = int(rp[r]), int(rp[r + 1])
+        assert e - b == ref.nnz, "row %d" % r
+        o = hc.opts(unit_lo=int(r), unit_hi=int(r) + 1, out_base=b, flags=hc.F_SYNC_CHECK)
+        hc.spgemm_numeric(D, D, P.info, P.C_row_ptr, col, val, P.ws, o, capacity=e - b)
+        np.testing.assert_array_equal(col[:e - b].cpu().numpy(), ref.col, err_msg="row %d" % r)
+        np.testing.assert_array_equal(val[:e - b].cpu().numpy(), ref.val, err_msg="row %d" % r)
 
 
 def test_rmat20_sampled_rows_bitwise(rmat20):

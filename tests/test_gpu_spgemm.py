@@ -335,3 +335,47 @@ def test_concurrent_host_threads_on_own_streams():
         t.join(timeout=120)
     assert not any(t.is_alive() for t in th), "a thread did not finish"
     assert not errors, errors
+
+
+@pytest.mark.parametrize("maxc,sim", [(4, hc.SIM_ROOT), (2, hc.SIM_ROOT), (8, hc.SIM_UNION)])
+def test_benchmark_configuration_bitwise(maxc, sim):
+    # the benchmark's configuration on a 32^3 relabelled 27-point stencil: rows of A in reverse
+    # Cuthill-McKee order, hierarchical clusters (the tuned size 4, and 2 / 8), symbolic tables filled up to
+    # 100 %, numeric tables 70 % (clustered) and 50 % (plain, given order and RCM rows)
+    M, _, _ = synth.workload_stencil27(32, 2, 3)
+    ref = oracle.spgemm(M, M)
+    Md = to_dev(M)
+    rcm = oracle.order_rcm(M)
+    plan = hc.plan_hierarchical(M, (3, 10), maxc, sim, perm_in=rcm)
+    Dc = hc.cluster_build(Md, plan)
+    for o in (hc.opts(sym_load_pct=100, load_pct=70), hc.opts(sym_load_pct=70, load_pct=70),
+              hc.opts(sym_load_pct=100, load_pct=85)):
+        assert_same(gpu_product(Dc, Md, o), ref, "clustered %d s%d n%d" % (maxc, o.sym_load_pct, o.load_pct))
+    o = hc.opts(sym_load_pct=100, load_pct=50)
+    assert_same(gpu_product(Md, Md, o), ref, "plain")
+    R = hc.permute_h(M, rcm)
+    C = gpu_product(to_dev(R), Md, o)
+    np.testing.assert_array_equal(np.diff(C.rp), np.diff(ref.rp)[rcm])    # rows of C in RCM order
+    inv = np.empty_like(rcm)
+    inv[rcm] = np.arange(len(rcm))
+    for r in (0, 1, M.nrows // 2, M.nrows - 1):
+        p = inv[r]
+        np.testing.assert_array_equal(C.col[C.rp[p]:C.rp[p + 1]], ref.col[ref.rp[r]:ref.rp[r + 1]])
+        np.testing.assert_array_equal(C.val[C.rp[p]:C.rp[p + 1]], ref.val[ref.rp[r]:ref.rp[r + 1]])
+
+
+def test_status_reports_dropped_writes_without_sync_flag():
+    # the numeric phase's error word, read back by hcsp_spgemm_status after an asynchronous call
+    A = synth.uniform(200, 200, 6, 31)
+    Ad = to_dev(A)
+    P = hc.Product(Ad, Ad)
+    nnz = P.symbolic()
+    cap = nnz // 3
+    bc = torch.empty(cap, dtype=torch.int32, device="cuda")
+    bv = torch.empty(cap, dtype=torch.float64, device="cuda")
+    hc.spgemm_numeric(Ad, Ad, P.info, P.C_row_ptr, bc, bv, P.ws, capacity=cap)
+    with pytest.raises(hc.HcspError) as e:
+        hc.spgemm_status(P.ws)
+    assert e.value.status == -5
+    P.run()                                     # a full run clears it
+    hc.spgemm_status(P.ws)

@@ -153,6 +153,37 @@ def test_multithreaded_equals_single():
     assert_csr_equal(C1, C2)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_structure_count_equals_boolean_product(seed):
+    # row counts of the boolean product, from an independent numpy boolean matmul; rectangular, empty rows
+    rng = np.random.default_rng(500 + seed)
+    n, m, p = (int(x) for x in rng.integers(1, 90, 3))
+    Ap = rng.random((n, m)) < rng.choice([0.0, 0.05, 0.3], size=n)[:, None]
+    Bp = rng.random((m, p)) < rng.choice([0.0, 0.1, 0.6], size=m)[:, None]
+    A = synth.from_dense(np.where(Ap, 1.0, 0.0), Ap)
+    B = synth.from_dense(np.where(Bp, 1.0, 0.0), Bp)
+    want = ((Ap.astype(np.int64) @ Bp.astype(np.int64)) > 0).sum(axis=1)
+    for nth in (1, 3):
+        np.testing.assert_array_equal(oracle.spgemm_count(A, B, nth), want)
+    if n > 2:
+        np.testing.assert_array_equal(oracle.spgemm_count(A, B, 2, (1, n - 1)), want[1:n - 1])
+
+
+@pytest.mark.parametrize("kind,m", [(27, 7), (7, 9), (5, 12)])
+def test_structure_count_stencil_closed_forms(kind, m):
+    S = synth.stencil(kind, m, 3)
+    total = int(oracle.spgemm_count(S, S, 4).sum())
+    closed = {27: (5 * m - 6) ** 3}
+    if kind in closed:
+        assert total == closed[kind]
+    np.testing.assert_array_equal(oracle.spgemm_count(S, S, 2), np.diff(oracle.spgemm(S, S).rp))
+
+
+def test_structure_count_power_law_equals_gustavson():
+    R = synth.rmat(11, 16, 0.57, 0.19, 0.19, 3)
+    np.testing.assert_array_equal(oracle.spgemm_count(R, R, 5), np.diff(oracle.spgemm(R, R).rp))
+
+
 def test_rowstats_matches_full():
     A = synth.uniform(200, 200, 8, 41)
     C = oracle.spgemm(A, A)
