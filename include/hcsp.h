@@ -271,6 +271,34 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
 int hcsp_spgemm_status(const void *ws_d, size_t ws_bytes, void *stream);
 
 /*
+ * hcsp_spgemm_noalloc: for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The whole product C = A x B -- hcsp_spgemm_symbolic, the
+ * nnz(C) read-back and hcsp_spgemm_numeric, with the same kernels and the
+ * same result bit for bit -- with its workspace in a static device array of
+ * HCSP_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends, instead of a caller-provided ws_d.  It calls no
+ * hipMalloc/hipFree and creates no streams: every launch runs on `stream`
+ * (HCSP_F_ONE_STREAM is implied; unit_lo/unit_hi/out_base are ignored, the
+ * whole matrix is computed).
+ *   C_row_ptr_d[A.nrows+1]    written (offsets of C in A's original row order)
+ *   C_col_d/C_val_d           caller-allocated, `capacity` entries
+ *   nnz_h                     (nullable) receives nnz(C), -1 if the symbolic
+ *                             phase did not run
+ * Errors: HCSP_E_CAPACITY when the product's workspace
+ * (hcsp_spgemm_workspace) exceeds the static array (nothing runs; about
+ * 7.5e5 rows for a square CSR A times a B of the same size) or when nnz(C) >
+ * capacity (then only C_row_ptr_d and *nnz_h are written); the numeric
+ * phase's own errors as hcsp_spgemm_status reports them.  Synchronizes.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (each call clears what must start at zero): calls that
+ * overlap on one device, from several host threads or streams, race.
+ */
+#define HCSP_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int hcsp_spgemm_noalloc(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opts *opts, int64_t *C_row_ptr_d,
+                        int32_t *C_col_d, double *C_val_d, int64_t capacity, int64_t *nnz_h, void *stream);
+
+/*
  * C in CSR_Cluster form (paper, Alg. 1, which writes C cluster by cluster):
  * for a CSR_Cluster A, C keeps A's clusters (cl_row_ptr and perm are A's),
  * and per cluster holds the sorted union of its member rows' output columns,

@@ -101,6 +101,8 @@ _SIGS = {
     "hcsp_spgemm_numeric": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
                              ctypes.POINTER(c_sym_info), vp, vp, vp, i64, vp, ctypes.c_size_t, vp], ctypes.c_int),
     "hcsp_spgemm_status": ([vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "hcsp_spgemm_noalloc": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts), vp, vp, vp,
+                             i64, ctypes.POINTER(i64), vp], ctypes.c_int),
     "hcsp_csr_transpose_workspace": ([i64, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hcsp_csr_transpose": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "hcsp_cluster_output_layout": ([ctypes.POINTER(c_operand), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts),
@@ -534,6 +536,22 @@ def spgemm_numeric(A, B: DeviceCSR, info: c_sym_info, C_row_ptr, C_col, C_val, w
     _check(lib().hcsp_spgemm_numeric(ctypes.byref(op), ctypes.byref(b), ctypes.byref(o), ctypes.byref(info),
                                      _tp(C_row_ptr), _tp(C_col), _tp(C_val), cap, _tp(ws), ws.numel(),
                                      _stream(stream)), "spgemm_numeric")
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def spgemm_noalloc(A, B: DeviceCSR, C_row_ptr, C_col, C_val, o: c_opts | None = None, stream=None) -> int:
+    """The whole product into caller buffers with the library's static workspace (no device allocation in
+    the library); returns nnz(C)."""
+    op = operand(A)
+    b = B.c()
+    o = o or c_opts()
+    nnz = i64()
+    rc = lib().hcsp_spgemm_noalloc(ctypes.byref(op), ctypes.byref(b), ctypes.byref(o), _tp(C_row_ptr), _tp(C_col),
+                                   _tp(C_val), C_col.numel(), ctypes.byref(nnz), _stream(stream))
+    _check(rc, "spgemm_noalloc")
+    return nnz.value
 
 
 class Product:
