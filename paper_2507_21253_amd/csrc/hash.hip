@@ -103,23 +103,10 @@ __device__ __forceinline__ double ld_val(const double *base, uint32_t off)
 template <int S>
 using MaskT = typename std::conditional<(S <= 8), uint8_t, uint16_t>::type;
 
-// Atomic OR of m into the mask of slot h (through the aligned 32-bit word
-// that holds it); returns the mask before.
-// The word is found by pointer arithmetic from the (4-byte aligned) mask
-// array, never through an integer, so the compiler keeps the access in shared
-// memory (a DS atomic rather than a generic one that also waits for every
-// outstanding global load).
-template <int S>
-__device__ __forceinline__ uint32_t mask_or(MaskT<S> *masks, uint32_t h, uint32_t m)
-{
-    const uint32_t byte = h * (uint32_t)sizeof(MaskT<S>);
-    const int sh = 8 * (int)(byte & 3u);
-    const uint32_t old = atomicOr(reinterpret_cast<uint32_t *>(masks) + (byte >> 2), m << sh);
-    return (old >> sh) & (S <= 8 ? 0xffu : 0xffffu);
-}
-
-// The same without reading the mask back: an atomic OR that returns nothing
-// (nothing to wait for).
+// Atomic OR of m into the mask of slot h, through the aligned 32-bit word
+// that holds it, returning nothing (nothing to wait for).  The word is found
+// by pointer arithmetic from the (4-byte aligned) mask array, never through
+// an integer, so the compiler keeps the access in shared memory.
 template <int S>
 __device__ __forceinline__ void mask_set(MaskT<S> *masks, uint32_t h, uint32_t m)
 {
@@ -336,9 +323,13 @@ __device__ __forceinline__ Pass<MS, NUM> fetch_pass(const SpArgs &a, const ItemR
 // into a power-of-two open-addressing table with a multiplicative hash; the
 // table has at least as many slots as the unit has products (by default
 // 100/70 times as many, so it stays at most 70% full even when nearly every
-// product hits a new column), so it never fills.  For clusters each key carries the OR of the masks of the columns k
-// that reached it: row l's count is the number of keys whose bit l got set,
-// counted (by ballot) when the bit first appears.
+// product hits a new column), so it never fills.  For clusters each key
+// carries the OR of the masks of the columns k that reached it (atomic ORs
+// that return nothing); once every product is in, one sweep over the table
+// counts the keys and, per member row l, the keys whose bit l is set.
+// Rounds of short items (at most 32 products each, 24 on average) are walked
+// two items per pass, one per half of the wavefront, which needs no per-lane
+// item search.
 template <int S, bool CL>
 __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned char *base)
 {
@@ -352,44 +343,80 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
     uint64_t *sbits = (uint64_t *)(base + L.sbits);
     lds_fill(keys, 4 * T, (uint32_t)kEmpty);
     if (MS) lds_fill(masks, (S <= 8 ? 1 : 2) * (T + 1), 0u);
-    if (lane == 0) keys[T] = kDummyKey;
-    int mcnt[S];  // wave-uniform per-member counts
-#pragma unroll
-    for (int l = 0; l < S; ++l) mcnt[l] = 0;
     const UnitView v = unit_view<CL>(a, u);
     const uint32_t hmask = (uint32_t)T - 1u;
     const int hshift = 32 - a.log2T;
     const uint64_t le = lanemask_le(lane);
-    int inserted = 0;
+    int inserted = 0;  // one-row units: keys this lane inserted
     int kmin = INT_MAX, kmax = -1;
     int64_t q0 = v.it0;
     int off0 = 0;
 
-    // one compare-and-swap takes an empty slot or confirms the key already
-    // there; only collisions walk on
-    auto probe = [&](const Pass<MS, false> &d, auto full_t) {
-        constexpr bool FULL = decltype(full_t)::value;
-        uint32_t h = !FULL && d.j == kDummyKey ? (uint32_t)T : ((uint32_t)d.j * 2654435761u) >> hshift;
-        int old = atomicCAS(&keys[h], kEmpty, d.j);
-        while (old != kEmpty && old != d.j) {
+    // key j into the table (one compare-and-swap takes an empty slot or
+    // confirms the key already there; only collisions walk on), its mask
+    // ORed into the slot's.  The table has more slots than the unit has
+    // products, so the walk always ends.
+    auto insert = [&](int j, uint32_t m) {
+        kmin = min(kmin, j);
+        kmax = max(kmax, j);
+        uint32_t h = ((uint32_t)j * 2654435761u) >> hshift;
+        int old = atomicCAS(&keys[h], kEmpty, j);
+        while (old != kEmpty && old != j) {
             h = (h + 1u) & hmask;
-            old = atomicCAS(&keys[h], kEmpty, d.j);
+            old = atomicCAS(&keys[h], kEmpty, j);
         }
-        inserted += old == kEmpty;
-        if (MS) {
-            // member rows that see this column for the first time
-            uint32_t fresh = d.m & ~mask_or<S>(masks, h, d.m);
-            if (h == (uint32_t)T) fresh = 0u;
-            if (__ballot(fresh != 0u)) {
+        if (MS) mask_set<S>(masks, h, m);
+        else inserted += old == kEmpty;
+    };
+
+    // two items per pass: half h of the wavefront takes item t0 + 2 rr + h
+    auto paired_round = [&](int nit, int E) {
+        {
+            // each item's product count replaces its position in the record
+            const int t = lane;
+            const int Pt = t < nit ? items[t].P : 0;
+            const int Pn = t + 1 < nit ? items[t + 1].P : E;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (t < nit) items[t].P = Pn - Pt;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+        const int half = lane >> 5, e = lane & 31;
+        constexpr int kP = 8;
+        for (int t0 = 0; t0 < nit; t0 += 2 * kP) {
+            int j[kP];
+            uint32_t m[kP];
+            bool ok[kP];
 #pragma unroll
-                for (int l = 0; l < S; ++l) mcnt[l] += __popcll(__ballot((fresh >> l) & 1u));
+            for (int rr = 0; rr < kP; ++rr) {
+                const int ti = t0 + 2 * rr + half;
+                const ItemRec it = items[min(ti, nit - 1)];
+                ok[rr] = ti < nit && e < it.P;
+                // (the select keeps the load ahead of its use rather than inside the branch)
+                const int jj = ld_col(a.b_col, ok[rr] ? it.bs + (uint32_t)e : 0u);
+                j[rr] = ok[rr] ? jj : kDummyKey;
+                m[rr] = it.x;
+            }
+#pragma unroll
+            for (int rr = 0; rr < kP; ++rr) {
+                if (t0 + 2 * rr >= nit) break;
+                if (j[rr] != kDummyKey) insert(j[rr], m[rr]);  // (tests the loaded key: idle lanes hold the dummy)
             }
         }
     };
 
     constexpr int kR = 8;
     while (q0 < v.it1) {
-        const int E = load_round<CL, S, false>(a, v, q0, off0, items, sbits, nullptr, nullptr);
+        int nit = 0;
+        const int E = load_round<CL, S, false>(a, v, q0, off0, items, sbits, nullptr, nullptr, &nit);
+        {
+            const int t = lane;
+            const int Pt = t < nit ? items[t].P : 0;
+            const int Pn = t + 1 < nit ? items[t + 1].P : E;
+            if (uniform(nit) > 0 && E >= 24 * uniform(nit) && __ballot(t < nit && Pn - Pt > 32) == 0ull) {
+                paired_round(uniform(nit), E);
+                continue;
+            }
+        }
         const int npass = (E + 63) >> 6;
         int cum = 0, p = 0;
         auto batch = [&](auto full_t) {
@@ -402,13 +429,8 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
                 cum += __popcll(w);
             }
 #pragma unroll
-            for (int rr = 0; rr < kR; ++rr) {
-                if (FULL || d[rr].j != kDummyKey) {
-                    kmin = min(kmin, d[rr].j);
-                    kmax = max(kmax, d[rr].j);
-                }
-                probe(d[rr], full_t);
-            }
+            for (int rr = 0; rr < kR; ++rr)
+                if (FULL || d[rr].j != kDummyKey) insert(d[rr].j, d[rr].m);
         };
         for (; p + kR <= npass; p += kR) {
             if (((p + kR) << 6) <= E) batch(std::true_type{});
@@ -418,16 +440,10 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
             const uint64_t w = uniform64(sbits[p]);
             const Pass<MS, false> d = fetch_pass<MS, false>(a, items, w, cum, (p << 6) + lane, E, le);
             cum += __popcll(w);
-            if (d.j != kDummyKey) {
-                kmin = min(kmin, d.j);
-                kmax = max(kmax, d.j);
-            }
-            probe(d, std::false_type{});
+            if (d.j != kDummyKey) insert(d.j, d.m);
         }
     }
-    int U = inserted;
     for (int o = 32; o > 0; o >>= 1) {
-        U += __shfl_xor(U, o);
         kmin = min(kmin, __shfl_xor(kmin, o));
         kmax = max(kmax, __shfl_xor(kmax, o));
     }
@@ -436,11 +452,26 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
         a.keyhi[u] = kmax;
     }
     if (!MS) {
+        int U = inserted;
+        for (int o = 32; o > 0; o >>= 1) U += __shfl_xor(U, o);
         if (lane == 0) {
             a.c_rp[member_row<CL>(a, v, 0)] = U;
             a.ucount[u] = U;
         }
         return;
+    }
+    // the keys, and per member the keys whose bit is set (T is a multiple of 64)
+    int U = 0;
+    int mcnt[S];  // wave-uniform per-member counts
+#pragma unroll
+    for (int l = 0; l < S; ++l) mcnt[l] = 0;
+    for (int c0 = 0; c0 < T; c0 += 64) {
+        const int sidx = c0 + lane;
+        U += __popcll(__ballot(keys[sidx] != kEmpty));
+        const uint32_t mk = (uint32_t)masks[sidx];
+#pragma unroll
+        for (int l = 0; l < S; ++l)
+            if (l < v.s) mcnt[l] += __popcll(__ballot((mk >> l) & 1u));
     }
     int mine = 0;
 #pragma unroll
