@@ -152,8 +152,19 @@ struct SymLayout {
 // one entry per distinct key, numbered in insertion order (at most vcap keys,
 // plus a dummy entry), found through a 16-bit index per slot.  A CSR row
 // keeps its value in the key's slot.
+// Large numeric tables (at least kHashedMinT slots) place keys by a
+// multiplicative hash instead of the order-preserving one: the output
+// columns of long rows can crowd into a small part of their range (rows of
+// power-law graphs meet the low-numbered hubs), which would make the
+// order-preserving placement's probe runs hundreds of slots long.  Their keys
+// are ranked by a counting sort over T/2 buckets of equal column range, then
+// by comparison within a bucket (a bucket never holds more keys than its
+// width in columns); the sort needs bucket ends and a key array.
+constexpr int kHashedMinT = 1024;
+__host__ __device__ constexpr bool hashed_table(int T) { return T >= kHashedMinT; }
+
 struct NumLayout {
-    int keys, vidx, masks, vals, aval, order, items, sbits, hcnt, obits, opre, bytes;
+    int keys, vidx, masks, vals, aval, order, items, sbits, hcnt, obits, opre, bend, arr, bytes;
     __host__ __device__ NumLayout(bool cl, int S, int T, int vcap)
     {
         const int TX = T + num_tail(T);
@@ -171,6 +182,16 @@ struct NumLayout {
         const int top = sbits + 8 * kRoundPasses;
         const int nw = (TX + 63) >> 6;
         const int ord_b = cl ? (2 * TX + 3) & ~3 : 0;
+        if (hashed_table(T)) {
+            const int need = 4 * (T / 2 + 1) + 4 * TX + ord_b;
+            const int at = need <= top - items ? items : top;
+            bend = at;
+            arr = bend + 4 * (T / 2 + 1);
+            order = arr + 4 * TX;
+            obits = opre = hcnt = at;  // unused
+            bytes = (at == items ? top : at + need + 15) & ~15;
+            return;
+        }
         const int hc_b = 2 * (T + 1);  // 16-bit counts, read through aligned 32-bit words
         const int need = 12 * nw + ord_b + hc_b;
         const int at = need <= top - items ? items : top;
@@ -178,6 +199,7 @@ struct NumLayout {
         opre = at + 8 * nw;
         order = opre + 4 * nw;
         hcnt = order + ord_b;
+        bend = arr = at;  // unused
         bytes = (at == items ? top : at + need + 15) & ~15;
     }
 };
@@ -498,7 +520,7 @@ __device__ __forceinline__ void sym_unit(const SpArgs &a, const int u, unsigned 
 // c_rp[row].
 // PAIRS: rounds of short items may be walked two items per pass (off in the
 // batch kernels, whose register budget is tighter).
-template <int S, bool CL, bool PRED = false, bool PAIRS = true>
+template <int S, bool CL, bool PRED = false, bool PAIRS = true, bool HASHED = false>
 __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned char *base)
 {
     static_assert(!PRED || (S == 1 && !CL), "predicted sizes are for CSR rows");
@@ -542,6 +564,7 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     for (int l = 0; l < S; ++l) areg[l] = 0.0;
 
     auto home = [&](int j) -> int {
+        if (HASHED) return (int)__umulhi((uint32_t)j * 2654435761u, (uint32_t)T);
         const int h = (int)((float)(uint32_t)(j - lo) * scale);
         return h < T ? h : T - 1;
     };
@@ -720,14 +743,17 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
     // keys homed below hx (a prefix sum of per-home counts) plus the smaller
     // keys sharing hx, which lie on the probe path from hx.  (A predicted
     // table that filled up, or holds more keys than the row's capacity, is
-    // given up before ranking.)
+    // given up before ranking.)  HASHED: the bucket sort described at
+    // kHashedMinT.
     uint64_t *obits = (uint64_t *)(base + L.obits);
     int *opre = (int *)(base + L.opre);
+    int *bend = (int *)(base + L.bend);
+    int *arr = (int *)(base + L.arr);
     int U = 0;
     for (int c0 = 0; c0 < TX; c0 += 64) {
         const int sidx = c0 + lane;
         const uint64_t occ = __ballot(sidx < TX && keys[sidx] != kEmpty);
-        if (lane == 0) {
+        if (!HASHED && lane == 0) {
             obits[c0 >> 6] = occ;
             opre[c0 >> 6] = U;
         }
@@ -738,7 +764,39 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         if (lane == 0) a.c_rp[row0] = -1;
         return;
     }
-    const bool runs_end = uniform(keys[TX - 1]) != kEmpty;
+    const int NB = T >> 1;
+    const float bscale = __fdividef((float)NB, (float)(uint32_t)(hi - lo + 1));
+    auto bucket = [&](int j) -> int {
+        const int b = (int)((float)(uint32_t)(j - lo) * bscale);
+        return b < NB ? b : NB - 1;
+    };
+    if (HASHED) {
+        // counts per bucket, their inclusive prefix (bucket ends), then the
+        // keys placed from each bucket's end down (the ends become starts)
+        lds_fill(bend, 4 * NB, 0u);  // NB is a multiple of 4
+        if (lane == 0) bend[NB] = U;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int c0 = 0; c0 < TX; c0 += 64) {
+            const int sidx = c0 + lane;
+            const int key = sidx < TX ? keys[sidx] : kEmpty;
+            if (key != kEmpty) atomicAdd(&bend[bucket(key)], 1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        int run = 0;
+        for (int c0 = 0; c0 < NB; c0 += 64) {
+            const int cnt = bend[c0 + lane];
+            const int incl = wave_incl_scan(cnt);
+            bend[c0 + lane] = run + incl;
+            run += __shfl(incl, 63);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int c0 = 0; c0 < TX; c0 += 64) {
+            const int sidx = c0 + lane;
+            const int key = sidx < TX ? keys[sidx] : kEmpty;
+            if (key != kEmpty) arr[atomicSub(&bend[bucket(key)], 1) - 1] = key;
+        }
+    }
+    const bool runs_end = !HASHED && uniform(keys[TX - 1]) != kEmpty;
     if (runs_end) {
         for (int i = lane; 2 * i < T; i += 64) ((uint32_t *)hcnt)[i] = 0u;  // T is even
         for (int c0 = 0; c0 < TX; c0 += 64) {
@@ -789,7 +847,12 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
         if (key == kEmpty) continue;
         const int hx = home(key);
         int rank;
-        if (!runs_end) {
+        if (HASHED) {
+            const int b = bucket(key);
+            const int s0 = bend[b], s1 = bend[b + 1];
+            rank = s0;
+            for (int t = s0; t < s1; ++t) rank += arr[t] < key;
+        } else if (!runs_end) {
             rank = opre[hx >> 6] + __popcll(obits[hx >> 6] & lanemask_lt(hx & 63));
             for (int x = hx;; ++x) {  // ends at an empty slot below TX - 1
                 const int kx = keys[x];
@@ -1555,7 +1618,7 @@ hipError_t launch_num_win(bool cluster, const SpArgs &a, int blocks, hipStream_t
 // batch (BATCH), a persistent grid whose wavefronts each take one contiguous
 // slice of the bin, whose size and start are read from device memory; each
 // unit is then resolved to its product first.
-template <int S, bool CL, bool BATCH, bool NUM, bool PRED = false>
+template <int S, bool CL, bool BATCH, bool NUM, bool PRED = false, bool HASHED = false>
 __device__ __forceinline__ void run_bin(const SpArgs &a0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1566,7 +1629,7 @@ __device__ __forceinline__ void run_bin(const SpArgs &a0)
     if (!BATCH) {
         if (lw >= a0.count) return;
         const int u = uniform(a0.order[a0.bin_begin + lw]);
-        if (NUM) num_unit<S, CL, PRED>(a0, u, base);
+        if (NUM) num_unit<S, CL, PRED, true, HASHED>(a0, u, base);
         else sym_unit<S, CL>(a0, u, base);
         return;
     }
@@ -1576,7 +1639,7 @@ __device__ __forceinline__ void run_bin(const SpArgs &a0)
     for (int64_t i = begin + lw * count / W; i < e; ++i) {
         SpArgs a = a0;
         const int u = batch_resolve(a, a0.order[i]);
-        if (NUM) num_unit<S, CL, false, false>(a, u, base);
+        if (NUM) num_unit<S, CL, false, false, HASHED>(a, u, base);
         else sym_unit<S, CL>(a, u, base);
     }
 }
@@ -1586,21 +1649,25 @@ __global__ void __launch_bounds__(256) k_sym(SpArgs a) { run_bin<S, CL, BATCH, f
 
 // Wavefronts per SIMD the numeric kernels must allow (their register budget):
 // CSR rows 8 (64 vector registers), two-row clusters 7 (72); in batches,
-// whose unit arguments are resolved per unit, 6 (80).
-template <int S, bool BATCH>
+// whose unit arguments are resolved per unit, 6 (80).  Large (hashed) tables
+// leave room for a few wavefronts per compute unit only, so their kernels
+// get 4 (128 registers).
+template <int S, bool BATCH, bool HASHED>
 struct NumOcc {
-    static constexpr int W = S == 1 && !BATCH ? 8 : S <= 2 ? (BATCH ? 6 : 7) : 1;
+    static constexpr int W = HASHED ? 4 : S == 1 && !BATCH ? 8 : S <= 2 ? (BATCH ? 6 : 7) : 1;
 };
 
-template <int S, bool CL, bool BATCH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NumOcc<S, BATCH>::W)))
-k_num(SpArgs a) { run_bin<S, CL, BATCH, true>(a); }
+template <int S, bool CL, bool BATCH, bool HASHED>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NumOcc<S, BATCH, HASHED>::W)))
+k_num(SpArgs a) { run_bin<S, CL, BATCH, true, false, HASHED>(a); }
 
-__global__ void __launch_bounds__(256) k_num_pred(SpArgs a) { run_bin<1, false, false, true, true>(a); }
+template <bool HASHED>
+__global__ void __launch_bounds__(256) k_num_pred(SpArgs a) { run_bin<1, false, false, true, true, HASHED>(a); }
 
 hipError_t launch_num_pred(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_num_pred, dim3(blocks), dim3(threads), lds, s, a);
+    if (hashed_table(a.T)) hipLaunchKernelGGL(k_num_pred<true>, dim3(blocks), dim3(threads), lds, s, a);
+    else hipLaunchKernelGGL(k_num_pred<false>, dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1616,8 +1683,11 @@ static hipError_t go_sym(bool batch, const SpArgs &a, int blocks, int threads, s
 template <int S, bool CL>
 static hipError_t go_num(bool batch, const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s)
 {
-    if (batch) hipLaunchKernelGGL((k_num<S, CL, true>), dim3(blocks), dim3(threads), lds, s, a);
-    else hipLaunchKernelGGL((k_num<S, CL, false>), dim3(blocks), dim3(threads), lds, s, a);
+    const bool h = hashed_table(a.T);
+    if (batch && h) hipLaunchKernelGGL((k_num<S, CL, true, true>), dim3(blocks), dim3(threads), lds, s, a);
+    else if (batch) hipLaunchKernelGGL((k_num<S, CL, true, false>), dim3(blocks), dim3(threads), lds, s, a);
+    else if (h) hipLaunchKernelGGL((k_num<S, CL, false, true>), dim3(blocks), dim3(threads), lds, s, a);
+    else hipLaunchKernelGGL((k_num<S, CL, false, false>), dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -379,3 +379,34 @@ def test_status_reports_dropped_writes_without_sync_flag():
     assert e.value.status == -5
     P.run()                                     # a full run clears it
     hc.spgemm_status(P.ws)
+
+
+def test_large_tables_bitwise():
+    # units whose numeric tables hold 1024 slots or more place keys by a multiplicative hash and rank them by
+    # a bucket sort: R-MAT rows (output columns crowded at the low-numbered hubs), uniform rows of ~830
+    # outputs, two-row clusters of those, C written as CSR_Cluster, and the predicted-size product
+    R = synth.rmat(13, 16, 0.57, 0.19, 0.19, 31)
+    Rd = to_dev(R)
+    ref = oracle.spgemm(R, R)
+    cnt = np.diff(ref.rp)
+    assert ((cnt >= 700) & (cnt <= 4300)).sum() > 4000  # rows in the hashed shared-memory bins
+    assert_same(gpu_product(Rd, Rd), ref, "rmat13")
+    plan = hc.plan_hierarchical(R, (3, 10), 2, hc.SIM_ROOT)
+    assert_same(gpu_product(hc.cluster_build(Rd, plan), Rd), ref, "rmat13 clusters")
+    U = synth.uniform(5000, 5000, 30, 32)
+    Ud = to_dev(U)
+    refu = oracle.spgemm(U, U)
+    assert_same(gpu_product(Ud, Ud), refu, "uniform")
+    plan2 = hc.plan_fixed(U.nrows, 2)
+    Uc = hc.cluster_build(Ud, plan2)
+    assert_same(gpu_product(Uc, Ud), refu, "uniform pairs")
+    C = hc.spgemm_cluster_out(Uc, Ud)
+    torch.cuda.synchronize()
+    got = host_cluster_of(C)
+    want = _ref_cluster_out(U, U, plan2)
+    for k in got:
+        np.testing.assert_array_equal(got[k], getattr(want, k), err_msg="uniform pairs CSR_Cluster %s" % k)
+    P = hc.PredictedProduct(Ud, Ud, 1.02 * refu.nnz / int(np.diff(U.rp)[U.col].sum()))
+    Cp = P.run()
+    torch.cuda.synchronize()
+    assert_same(Cp.to_host(), refu, "uniform predicted")
