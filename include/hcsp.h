@@ -334,7 +334,10 @@ int hcsp_spgemm_numeric_cluster(const hcsp_operand *A, const hcsp_csr *B, const 
  * product count (an upper bound on its count) and ratio a predicted
  * compression nnz(C)/products with margin (e.g. from the learned predictor);
  * the numeric phase runs with hash tables sized for capacity_i and writes
- * into a padded scratch.  Rows whose keys do not fit are recomputed exactly:
+ * into a padded scratch.  (One ratio per product rather than a capacity array
+ * per row: the learned predictor has one compression-ratio head per matrix,
+ * and the per-row capacities follow from it and the rows' product counts on
+ * the device.)  Rows whose keys do not fit are recomputed exactly:
  * the symbolic phase runs for those rows only (the exact fallback), then the
  * numeric phase.  Finally the predicted rows move to their exact places.  The
  * result is the same C as hcsp_spgemm_symbolic + hcsp_spgemm_numeric, bit
@@ -482,6 +485,116 @@ int hcsp_mlp_backward(const float *params_d, const float *act_d, const float *Z_
                       void *stream);
 int hcsp_mlp_adam(float *params_d, const float *grad_d, float *m_d, float *v_d, int32_t step, float lr, float beta1,
                   float beta2, float eps, void *stream);
+
+/*
+ * hcsp_mlp_train_step: one full-batch training step on the device -- forward
+ * (act_d required), back-propagation and one Adam step with the arrays and
+ * meanings above.  Never synchronizes.
+ *
+ * The model on the host (hcsp_mlp, opaque): the parameters, the feature
+ * normalization (mu then sd) and a one-line tag (e.g. the path names the
+ * selector head scores).  The library allocates host memory only.
+ *   hcsp_mlp_create   copies params_h[HCSP_MLP_NPARAMS] (NULL: zeros) and
+ *                     norm_h[2*HCSP_MLP_NIN] (NULL: mu 0, sd 1); tag NULL = ""
+ *   hcsp_mlp_get/set  copy out / in (NULL arguments are skipped); get's tag
+ *                     buffer needs the tag's length + 1 bytes
+ *   hcsp_mlp_save/load  a text file (layer sizes, tag, normalization and
+ *                     parameters to 9 significant digits: exact for float32);
+ *                     load refuses a file of another shape
+ *   hcsp_mlp_destroy  frees it (NULL is a no-op)
+ */
+typedef struct hcsp_mlp hcsp_mlp;
+int hcsp_mlp_train_step(float *params_d, const float *norm_d, const float *X_d, const int32_t *y_d, const float *t_d,
+                        int32_t B, float lam, float *act_d, float *Z_d, float *delta_d, float *loss_d, float *grad_d,
+                        float *m_d, float *v_d, int32_t step, float lr, float beta1, float beta2, float eps,
+                        void *stream);
+int hcsp_mlp_create(const float *params_h, const float *norm_h, const char *tag, hcsp_mlp **out);
+int hcsp_mlp_destroy(hcsp_mlp *m);
+int hcsp_mlp_get(const hcsp_mlp *m, float *params_h, float *norm_h, char *tag, size_t len);
+int hcsp_mlp_set(hcsp_mlp *m, const float *params_h, const float *norm_h);
+int hcsp_mlp_save(const hcsp_mlp *m, const char *path);
+int hcsp_mlp_load(const char *path, hcsp_mlp **out);
+
+/* ---------------------------------------------------------------- autotuner
+ * Tuned options per matrix class.  The paper fixes the clustering parameters
+ * (similarity threshold 0.3, at most 8 rows per cluster, Sec. "Hierarchical
+ * Clusters") and notes that the best cluster length depends on the matrix
+ * (Sec. "Clustering Without Changing Order"); here they are measured per
+ * class of matrices instead.  Host only; the library allocates host memory
+ * only.
+ *
+ * Class of a matrix: five of the structure features (hcsp_features) cut at
+ * fixed edges -- mean row length (feature 2; edges 6, 16, 40), coefficient of
+ * variation of the products per row (12; 0.5, 2), products per distinct output
+ * column of the sampled rows (22; 1.3, 3), the best similarity a row finds
+ * (21; 0.3, 0.6) and mean |col - row| / ncols (14; 0.05) -- as the key
+ * "rl<a>_cv<b>_cr<c>_sim<d>_loc<e>", each digit the number of edges at or
+ * below the feature's value (hcsp_tune_class; key buffer >= 32 bytes).
+ *
+ * A run is one matrix's measured product times (ms per product: symbolic
+ * phase, nnz read-back and numeric phase; NaN or <= 0 = not measured) on a
+ * fixed grid:
+ *   plain_ms[i][j]  plain CSR, symbolic fill {50,70,100}[i] (opts.sym_load_pct),
+ *                   numeric fill {50,60,70}[j] (opts.load_pct)
+ *   rcm_ms          plain CSR over reverse Cuthill-McKee rows (recorded, not
+ *                   used by the choice)
+ *   hc_ms[i][j]     CSR_Cluster of hierarchical clusters (Alg. 3, threshold
+ *                   3/10) of at most {2,4,8}[i] rows over RCM rows, numeric
+ *                   fill {50,60,70,75,80,85}[j]
+ * Choice of a class, over the candidates every one of its runs measured: a
+ * candidate's score is the sum over the runs of its time divided by the run's
+ * best time (over the plain grid and every cluster size at its best fill);
+ * sym_load_pct/load_pct are the best-scoring plain candidate's fills; each
+ * cluster size scores with its best fill per run, and the best-scoring size is
+ * best_cluster_size, its best-scoring fill cl_load_pct; the path is that
+ * cluster size (path 1, max_cluster) if it scores strictly lower than the
+ * plain candidate, else plain (path 0, max_cluster 0).  Ties go to the first
+ * candidate in grid order.  A class without runs gets the library defaults:
+ * tuned 0, plain, fills 70 and 60, best_cluster_size 2, cl_load_pct 60.
+ *
+ *   hcsp_tune_create/destroy  an empty table / free it (NULL is a no-op)
+ *   hcsp_tune_add      appends a run to a class (key from hcsp_tune_class)
+ *   hcsp_tune_get      the choice of the class with that key
+ *   hcsp_tune_lookup   the choice of the class of a matrix's features
+ *   hcsp_tune_classes  the class keys, one per line (keys may be NULL to get
+ *                      the count only)
+ *   hcsp_tune_runs     a class's runs (*count set; runs NULL: the count only;
+ *                      HCSP_E_CAPACITY if more than cap)
+ *   hcsp_tune_save/load  a text file: header with the grid shape, per class a
+ *                      line "class <key> <runs>" and one line per run (17
+ *                      significant digits, "nan" where not measured)
+ */
+#define HCSP_TUNE_NSYM 3
+#define HCSP_TUNE_NNUM 3
+#define HCSP_TUNE_NMC 3
+#define HCSP_TUNE_NCL 6
+typedef struct hcsp_tune_run {
+    int64_t nrows, nnz;
+    double plain_ms[HCSP_TUNE_NSYM][HCSP_TUNE_NNUM];
+    double rcm_ms;
+    double hc_ms[HCSP_TUNE_NMC][HCSP_TUNE_NCL];
+} hcsp_tune_run;
+typedef struct hcsp_tune_choice {
+    int32_t tuned;             /* 0: no runs for the class (defaults) */
+    int32_t path;              /* 0 plain CSR, 1 hierarchical clusters over RCM rows */
+    int32_t max_cluster;       /* rows per cluster of the chosen path (0 for plain) */
+    int32_t best_cluster_size; /* best-scoring cluster size */
+    int32_t sym_load_pct;      /* opts.sym_load_pct */
+    int32_t load_pct;          /* opts.load_pct, plain CSR */
+    int32_t cl_load_pct;       /* opts.load_pct, CSR_Cluster of best_cluster_size rows */
+    int32_t runs;              /* runs of the class */
+} hcsp_tune_choice;
+typedef struct hcsp_tune_table hcsp_tune_table;
+int hcsp_tune_create(hcsp_tune_table **out);
+int hcsp_tune_destroy(hcsp_tune_table *t);
+int hcsp_tune_class(const float *features, char *key, size_t len);
+int hcsp_tune_add(hcsp_tune_table *t, const char *key, const hcsp_tune_run *run);
+int hcsp_tune_get(const hcsp_tune_table *t, const char *key, hcsp_tune_choice *out);
+int hcsp_tune_lookup(const hcsp_tune_table *t, const float *features, hcsp_tune_choice *out);
+int hcsp_tune_classes(const hcsp_tune_table *t, char *keys, size_t len, int32_t *count);
+int hcsp_tune_runs(const hcsp_tune_table *t, const char *key, hcsp_tune_run *runs, int32_t cap, int32_t *count);
+int hcsp_tune_save(const hcsp_tune_table *t, const char *path);
+int hcsp_tune_load(const char *path, hcsp_tune_table **out);
 
 /* ---------------------------------------------------------------- batches
  * Many independent products C_p = A_p x B_p of uneven sizes in one fixed

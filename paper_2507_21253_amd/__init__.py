@@ -77,6 +77,23 @@ class c_batch_plan(ctypes.Structure):
                 ("out_capacity", i64), ("ws_bytes", ctypes.c_size_t), ("opts", c_opts)]
 
 
+TUNE_NSYM, TUNE_NNUM, TUNE_NMC, TUNE_NCL = 3, 3, 3, 6
+TUNE_SYM_FILLS = (50, 70, 100)
+TUNE_NUM_FILLS = (50, 60, 70)
+TUNE_CLUSTER_SIZES = (2, 4, 8)
+TUNE_CL_FILLS = (50, 60, 70, 75, 80, 85)
+
+
+class c_tune_run(ctypes.Structure):
+    _fields_ = [("nrows", i64), ("nnz", i64), ("plain_ms", (ctypes.c_double * TUNE_NNUM) * TUNE_NSYM),
+                ("rcm_ms", ctypes.c_double), ("hc_ms", (ctypes.c_double * TUNE_NCL) * TUNE_NMC)]
+
+
+class c_tune_choice(ctypes.Structure):
+    _fields_ = [("tuned", i32), ("path", i32), ("max_cluster", i32), ("best_cluster_size", i32),
+                ("sym_load_pct", i32), ("load_pct", i32), ("cl_load_pct", i32), ("runs", i32)]
+
+
 # every symbol include/hcsp.h declares, with its ctypes signature
 _SIGS = {
     "hcsp_version": ([], ctypes.c_char_p),
@@ -132,6 +149,24 @@ _SIGS = {
     "hcsp_mlp_backward": ([vp, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, vp], ctypes.c_int),
     "hcsp_mlp_adam": ([vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp],
                       ctypes.c_int),
+    "hcsp_mlp_train_step": ([vp, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, vp, vp, vp, vp, i32,
+                             ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp], ctypes.c_int),
+    "hcsp_mlp_create": ([vp, vp, ctypes.c_char_p, ctypes.POINTER(vp)], ctypes.c_int),
+    "hcsp_mlp_destroy": ([vp], ctypes.c_int),
+    "hcsp_mlp_get": ([vp, vp, vp, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+    "hcsp_mlp_set": ([vp, vp, vp], ctypes.c_int),
+    "hcsp_mlp_save": ([vp, ctypes.c_char_p], ctypes.c_int),
+    "hcsp_mlp_load": ([ctypes.c_char_p, ctypes.POINTER(vp)], ctypes.c_int),
+    "hcsp_tune_create": ([ctypes.POINTER(vp)], ctypes.c_int),
+    "hcsp_tune_destroy": ([vp], ctypes.c_int),
+    "hcsp_tune_class": ([vp, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+    "hcsp_tune_add": ([vp, ctypes.c_char_p, ctypes.POINTER(c_tune_run)], ctypes.c_int),
+    "hcsp_tune_get": ([vp, ctypes.c_char_p, ctypes.POINTER(c_tune_choice)], ctypes.c_int),
+    "hcsp_tune_lookup": ([vp, vp, ctypes.POINTER(c_tune_choice)], ctypes.c_int),
+    "hcsp_tune_classes": ([vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(i32)], ctypes.c_int),
+    "hcsp_tune_runs": ([vp, ctypes.c_char_p, ctypes.POINTER(c_tune_run), i32, ctypes.POINTER(i32)], ctypes.c_int),
+    "hcsp_tune_save": ([vp, ctypes.c_char_p], ctypes.c_int),
+    "hcsp_tune_load": ([ctypes.c_char_p, ctypes.POINTER(vp)], ctypes.c_int),
 }
 MLP_NPARAMS, MLP_NACT, MLP_NDELTA = 6597, 160, 133
 NFEATURES = 32
@@ -729,6 +764,127 @@ def mlp_backward(params, act, Z, y, t, lam, delta, loss, grad, stream=None):
 def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(lib().hcsp_mlp_adam(_tp(params), _tp(grad), _tp(m), _tp(v), int(step), float(lr), float(beta1),
                                float(beta2), float(eps), _stream(stream)), "mlp_adam")
+
+
+def mlp_train_step(params, norm, X, y, t, lam, act, Z, delta, loss, grad, m, v, step, lr=1e-3, beta1=0.9,
+                   beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().hcsp_mlp_train_step(_tp(params), _tp(norm), _tp(X), _tp(y), _tp(t), X.shape[0], float(lam), _tp(act),
+                                     _tp(Z), _tp(delta), _tp(loss), _tp(grad), _tp(m), _tp(v), int(step), float(lr),
+                                     float(beta1), float(beta2), float(eps), _stream(stream)), "mlp_train_step")
+
+
+class MlpModel:
+    """Host copy of the selector's model in the library (parameters, feature normalization, a one-line tag),
+    saved and loaded by the library's model file."""
+
+    def __init__(self, params=None, norm=None, tag: str = "", _handle=None):
+        if _handle is not None:
+            self._h = _handle
+            return
+        h = vp()
+        p = None if params is None else np.ascontiguousarray(params, np.float32)
+        nm = None if norm is None else np.ascontiguousarray(norm, np.float32)
+        if p is not None and p.size != MLP_NPARAMS or nm is not None and nm.size != 2 * NFEATURES:
+            raise ValueError("parameter or normalization size")
+        _check(lib().hcsp_mlp_create(_np(p), _np(nm), tag.encode(), ctypes.byref(h)), "mlp_create")
+        self._h = h
+
+    @staticmethod
+    def load(path: str) -> "MlpModel":
+        h = vp()
+        _check(lib().hcsp_mlp_load(path.encode(), ctypes.byref(h)), "mlp_load")
+        return MlpModel(_handle=h)
+
+    def save(self, path: str):
+        _check(lib().hcsp_mlp_save(self._h, path.encode()), "mlp_save")
+
+    def get(self):
+        """(params float32[MLP_NPARAMS], norm float32[64] (mu then sd), tag)"""
+        p = np.empty(MLP_NPARAMS, np.float32)
+        nm = np.empty(2 * NFEATURES, np.float32)
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().hcsp_mlp_get(self._h, _np(p), _np(nm), buf, len(buf)), "mlp_get")
+        return p, nm, buf.value.decode()
+
+    def set(self, params=None, norm=None):
+        p = None if params is None else np.ascontiguousarray(params, np.float32)
+        nm = None if norm is None else np.ascontiguousarray(norm, np.float32)
+        _check(lib().hcsp_mlp_set(self._h, _np(p), _np(nm)), "mlp_set")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.hcsp_mlp_destroy(h)
+            self._h = None
+
+
+# ------------------------------------------------------------------ autotuner table
+
+def tune_class(f) -> str:
+    """The autotuner's class key of a matrix from its structure features."""
+    f = np.ascontiguousarray(f, np.float32)
+    buf = ctypes.create_string_buffer(64)
+    _check(lib().hcsp_tune_class(_np(f), buf, len(buf)), "tune_class")
+    return buf.value.decode()
+
+
+def _choice_dict(c: c_tune_choice) -> dict:
+    return {"path": "hc" if c.path == 1 else "plain", "max_cluster": c.max_cluster,
+            "best_cluster_size": c.best_cluster_size, "sym_load_pct": c.sym_load_pct, "load_pct": c.load_pct,
+            "cl_load_pct": c.cl_load_pct, "tuned": bool(c.tuned), "runs": c.runs}
+
+
+class TuneTableNative:
+    """The library's autotuner table (per-class runs and the choice rule of include/hcsp.h)."""
+
+    def __init__(self, _handle=None):
+        if _handle is None:
+            _handle = vp()
+            _check(lib().hcsp_tune_create(ctypes.byref(_handle)), "tune_create")
+        self._h = _handle
+
+    @staticmethod
+    def load(path: str) -> "TuneTableNative":
+        h = vp()
+        _check(lib().hcsp_tune_load(path.encode(), ctypes.byref(h)), "tune_load")
+        return TuneTableNative(h)
+
+    def save(self, path: str):
+        _check(lib().hcsp_tune_save(self._h, path.encode()), "tune_save")
+
+    def add(self, key: str, run: c_tune_run):
+        _check(lib().hcsp_tune_add(self._h, key.encode(), ctypes.byref(run)), "tune_add")
+
+    def get(self, key: str) -> dict:
+        c = c_tune_choice()
+        _check(lib().hcsp_tune_get(self._h, key.encode(), ctypes.byref(c)), "tune_get")
+        return _choice_dict(c)
+
+    def lookup(self, f) -> dict:
+        f = np.ascontiguousarray(f, np.float32)
+        c = c_tune_choice()
+        _check(lib().hcsp_tune_lookup(self._h, _np(f), ctypes.byref(c)), "tune_lookup")
+        return _choice_dict(c)
+
+    def classes(self) -> list:
+        n = i32()
+        _check(lib().hcsp_tune_classes(self._h, None, 0, ctypes.byref(n)), "tune_classes")
+        buf = ctypes.create_string_buffer(64 * (n.value + 1))
+        _check(lib().hcsp_tune_classes(self._h, buf, len(buf), ctypes.byref(n)), "tune_classes")
+        return [k for k in buf.value.decode().split("\n") if k]
+
+    def runs(self, key: str) -> list:
+        n = i32()
+        _check(lib().hcsp_tune_runs(self._h, key.encode(), None, 0, ctypes.byref(n)), "tune_runs")
+        arr = (c_tune_run * max(n.value, 1))()
+        _check(lib().hcsp_tune_runs(self._h, key.encode(), arr, n.value, ctypes.byref(n)), "tune_runs")
+        return [arr[i] for i in range(n.value)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.hcsp_tune_destroy(h)
+            self._h = None
 
 
 # ------------------------------------------------------------------ predicted sizes

@@ -34,14 +34,14 @@ import time
 
 import numpy as np
 
-from . import (DeviceCSR, MLP_NACT, MLP_NDELTA, MLP_NPARAMS, Product, SIM_ROOT, cluster_build, features,
-               mlp_adam, mlp_backward, mlp_forward, order_rcm, permute_h, plan_hierarchical, plan_variable)
+from . import (DeviceCSR, MLP_NACT, MLP_NDELTA, MLP_NPARAMS, MlpModel, Product, SIM_ROOT, cluster_build,
+               features, mlp_forward, mlp_train_step, order_rcm, permute_h, plan_hierarchical, plan_variable)
 
 PATHS = ("plain", "rcm", "rcm_hc2", "variable")
 HORIZON = 1000
 NIN, NH, NOUT = 32, 64, 5
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "learned_set.npz")
-MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "selector.json")
+MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "selector.mlp")
 
 
 def _time_ms(P: Product, reps: int) -> float:
@@ -175,9 +175,7 @@ class Selector:
         v = torch.zeros(MLP_NPARAMS, dtype=torch.float32, device=dev)
         hist = []
         for step in range(1, epochs + 1):
-            mlp_forward(P, norm, X, Z, act)
-            mlp_backward(P, act, Z, Y, T, lam, delta, loss, g)
-            mlp_adam(P, g, m, v, step, lr)
+            mlp_train_step(P, norm, X, Y, T, lam, act, Z, delta, loss, g, m, v, step, lr)
             if step % 100 == 0 or step == 1:
                 hist.append(float(loss.mean().item()))
         self.params = P.cpu().numpy()
@@ -199,15 +197,17 @@ class Selector:
         return self.logits(F)[:, len(PATHS)]
 
     def save(self, path: str = MODEL):
-        with open(path, "w") as fh:
-            json.dump({"paths": PATHS, "horizon": HORIZON, "mu": self.mu.tolist(), "sd": self.sd.tolist(),
-                       "params": self.params.tolist()}, fh)
+        """The library's model file; the tag names the scored paths and the horizon of the labels."""
+        MlpModel(self.params, np.concatenate([self.mu, self.sd]),
+                 "paths %s horizon %d" % (",".join(PATHS), HORIZON)).save(path)
 
     @staticmethod
     def load(path: str = MODEL) -> "Selector":
-        with open(path) as fh:
-            d = json.load(fh)
-        return Selector(np.array(d["params"], np.float32), d["mu"], d["sd"])
+        params, norm, tag = MlpModel.load(path).get()
+        fields = tag.split()
+        if len(fields) < 2 or fields[0] != "paths" or fields[1] != ",".join(PATHS):
+            raise ValueError("%s scores paths %r, this module %r" % (path, tag, ",".join(PATHS)))
+        return Selector(params, norm[:NIN], norm[NIN:])
 
 
 def evaluate(sel: Selector, ds: dict) -> dict:

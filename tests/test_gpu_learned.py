@@ -114,3 +114,29 @@ def test_selector_gains_on_held_out_matrices():
     assert ev["selector_ms"] <= ev["always_variable_ms"]
     assert ev["selector_ms"] <= 1.05 * ev["best_ms"]
     assert ev["log_ratio_abs_err_median"] < 0.25
+
+
+def test_train_step_equals_its_three_kernels():
+    # hcsp_mlp_train_step = forward + back-propagation + one Adam step, bit for bit
+    X, y, t, mu, sd, theta = data(7, B=64)
+    norm = np.concatenate([mu, sd])
+    outs = []
+    for fused in (False, True):
+        P, M, V = dev(theta), torch.zeros(hc.MLP_NPARAMS, device="cuda"), torch.zeros(hc.MLP_NPARAMS, device="cuda")
+        Z = torch.empty(64, 5, dtype=torch.float32, device="cuda")
+        act = torch.empty(64, hc.MLP_NACT, dtype=torch.float32, device="cuda")
+        delta = torch.empty(64, hc.MLP_NDELTA, dtype=torch.float32, device="cuda")
+        loss = torch.empty(64, dtype=torch.float32, device="cuda")
+        g = torch.empty(hc.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+        Xd, yd, td, nd = dev(X), dev(y), dev(t), dev(norm)
+        for step in range(1, 4):
+            if fused:
+                hc.mlp_train_step(P, nd, Xd, yd, td, 0.5, act, Z, delta, loss, g, M, V, step, lr=1e-2)
+            else:
+                hc.mlp_forward(P, nd, Xd, Z, act)
+                hc.mlp_backward(P, act, Z, yd, td, 0.5, delta, loss, g)
+                hc.mlp_adam(P, g, M, V, step, lr=1e-2)
+        torch.cuda.synchronize()
+        outs.append((P.cpu().numpy(), loss.cpu().numpy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
