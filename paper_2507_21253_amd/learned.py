@@ -4,19 +4,22 @@ The paper leaves choosing the reordering and clustering for a matrix to
 machine learning as future work (Sec. "Conclusion and Future Work"); here a
 small network does it from the library's 32 structure features:
 
-  * selector: which of four paths to run for C = A*A --
+  * selector: which of four paths to run for C = A*A, the plain product and
+    the paper's three clusterings --
       ``plain``     row-wise product in the given order,
-      ``rcm``       rows of A reordered by reverse Cuthill-McKee first
-                    (Sec. "Matrix Reordering"), B unchanged,
-      ``rcm_hc2``   CSR_Cluster from hierarchical clustering (Alg. 3,
-                    threshold 3/10, at most 2 rows per cluster) of the rows
-                    taken in reverse Cuthill-McKee order (reorder, then
-                    cluster),
+      ``fixed8``    CSR_Cluster of fixed-length clusters of 8 consecutive
+                    rows in the given order (Sec. "Fixed-length Clusters"),
       ``variable``  CSR_Cluster from variable-length clustering (Alg. 2,
-                    threshold 3/10, at most 8 rows) in the given order;
+                    threshold 3/10, at most 8 rows) in the given order,
+      ``rcm_hc4``   CSR_Cluster from hierarchical clustering (Alg. 3,
+                    threshold 3/10, at most 4 rows per cluster) of the rows
+                    taken in reverse Cuthill-McKee order (reorder, then
+                    cluster: the benchmark's method path);
     the label is the path with the least time per product once its
-    preprocessing is spread over ``HORIZON`` products (repeated products over
-    one structure, the paper's use case for clustering);
+    preprocessing (host plan and orderings, device CSR_Cluster build) is
+    spread over ``HORIZON`` = 20 products, the horizon the paper measures
+    the amortization of its preprocessing against (Sec. "Evaluation",
+    preprocessing overhead);
   * predictor: log(nnz(C) / products), from which output and accumulator
     sizes can be estimated before the symbolic phase
     (``capacity = products * exp(prediction) * (1 + margin)``); the exact
@@ -35,11 +38,14 @@ import time
 import numpy as np
 
 from . import (DeviceCSR, MLP_NACT, MLP_NDELTA, MLP_NPARAMS, MlpModel, Product, SIM_ROOT, cluster_build,
-               features, mlp_forward, mlp_train_step, order_rcm, permute_h, plan_hierarchical, plan_variable)
+               features, mlp_forward, mlp_train_step, order_rcm, plan_fixed, plan_hierarchical, plan_variable)
 
-PATHS = ("plain", "rcm", "rcm_hc2", "variable")
-HORIZON = 1000
+PATHS = ("plain", "fixed8", "variable", "rcm_hc4")
+HORIZON = 20
 NIN, NH, NOUT = 32, 64, 5
+# seeds from LARGE_FROM draw matrices of LARGE rows (the benchmark's size class)
+LARGE_FROM = 20000
+LARGE = (5e5, 1.1e6)
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "learned_set.npz")
 MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "selector.mlp")
 
@@ -61,6 +67,7 @@ def _time_ms(P: Product, reps: int) -> float:
 
 def label(H, reps: int = 3, threads: int = 0) -> dict:
     """Features, per-path product time (ms) and preprocessing time (s), nnz(C) and the product count."""
+    import torch
     f = features(H)
     D = DeviceCSR.from_host(H)
     times, prep = {}, {}
@@ -69,22 +76,18 @@ def label(H, reps: int = 3, threads: int = 0) -> dict:
     prep["plain"] = 0.0
     nnz = int(P.info.nnz)
     del P
-    t = time.perf_counter()
-    rcm = order_rcm(H)
-    t_order = time.perf_counter() - t
-    R = permute_h(H, rcm, None, threads)
-    prep["rcm"] = time.perf_counter() - t
-    Rd = DeviceCSR.from_host(R)
-    times["rcm"] = _time_ms(Product(Rd, D), reps)
-    del Rd
-    for name, mk, base in (("rcm_hc2", lambda: plan_hierarchical(H, (3, 10), 2, SIM_ROOT, nthreads=threads,
-                                                                 perm_in=rcm), t_order),
-                           ("variable", lambda: plan_variable(H, (3, 10), 8), 0.0)):
+
+    def clustered(name, make_plan):
+        torch.cuda.synchronize()
         t = time.perf_counter()
-        Dc = cluster_build(D, mk())
-        prep[name] = base + time.perf_counter() - t
+        Dc = cluster_build(D, make_plan())
+        torch.cuda.synchronize()
+        prep[name] = time.perf_counter() - t
         times[name] = _time_ms(Product(Dc, D), reps)
-        del Dc
+
+    clustered("fixed8", lambda: plan_fixed(H.nrows, 8))
+    clustered("variable", lambda: plan_variable(H, (3, 10), 8))
+    clustered("rcm_hc4", lambda: plan_hierarchical(H, (3, 10), 4, SIM_ROOT, nthreads=threads, perm_in=order_rcm(H)))
     rl = np.diff(H.rp)
     return {"features": f, "times": np.array([times[p] for p in PATHS]), "prep": np.array([prep[p] for p in PATHS]),
             "nnz": nnz, "products": int(rl[H.col].sum())}
@@ -109,7 +112,7 @@ def gen(lo: int, hi: int, out: str, reps: int = 3):
     threads = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
     for s in range(lo, hi):
-        name, H = synth.learned_problem(s)
+        name, H = synth.learned_problem(s, *LARGE) if s >= LARGE_FROM else synth.learned_problem(s)
         r = label(H, reps, threads)
         for k in ("features", "times", "prep", "nnz", "products"):
             rows[k].append(r[k])
@@ -130,8 +133,10 @@ def load(path: str = DATA) -> dict:
         return {k: z[k] for k in z.files}
 
 
-def split(ds: dict, held_out_from: int = 12000) -> tuple[dict, dict]:
-    m = ds["seed"] >= held_out_from
+def split(ds: dict) -> tuple[dict, dict]:
+    """(training, held-out): seeds 12000..12199 of the main set and 20000..20029 of the large set are held out."""
+    s = ds["seed"]
+    m = ((s >= 12000) & (s < 12200)) | ((s >= LARGE_FROM) & (s < LARGE_FROM + 30))
     return {k: v[~m] for k, v in ds.items()}, {k: v[m] for k, v in ds.items()}
 
 
