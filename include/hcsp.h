@@ -334,10 +334,10 @@ int hcsp_spgemm_numeric_cluster(const hcsp_operand *A, const hcsp_csr *B, const 
  * product count (an upper bound on its count) and ratio a predicted
  * compression nnz(C)/products with margin (e.g. from the learned predictor);
  * the numeric phase runs with hash tables sized for capacity_i and writes
- * into a padded scratch.  (One ratio per product rather than a capacity array
- * per row: the learned predictor has one compression-ratio head per matrix,
- * and the per-row capacities follow from it and the rows' product counts on
- * the device.)  Rows whose keys do not fit are recomputed exactly:
+ * into a padded scratch.  (The learned predictor has one compression-ratio
+ * head per matrix, so this entry takes one ratio and derives the per-row
+ * capacities on the device; hcsp_spgemm_predicted_rows below takes them per
+ * row.)  Rows whose keys do not fit are recomputed exactly:
  * the symbolic phase runs for those rows only (the exact fallback), then the
  * numeric phase.  Finally the predicted rows move to their exact places.  The
  * result is the same C as hcsp_spgemm_symbolic + hcsp_spgemm_numeric, bit
@@ -359,6 +359,30 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
                           int64_t products, int64_t *C_row_ptr_d, int32_t *C_col_d, double *C_val_d,
                           int64_t capacity, int64_t *nnz_h, int64_t *n_overflow_h, void *ws_d, size_t ws_bytes,
                           void *stream);
+
+/*
+ * The same product with a capacity given per row instead of one ratio (a
+ * per-row size predictor; exact counts from an earlier product with the same
+ * pattern).  Row i's capacity is cap_row_d[i] clamped to [1, p_i]; the
+ * result is again the C of the two-phase product bit for bit, and the rows
+ * recomputed exactly are those whose count exceeds their capacity (or whose
+ * table would not fit in shared memory).
+ *   cap_row_d[A.nrows]             int32, device, read only
+ *   cap_sum                        >= the sum of the positive cap_row_d[i]
+ *                                  (sizes the padded scratch: cap_sum +
+ *                                  A.nrows entries)
+ *   hcsp_predicted_rows_workspace  workspace bytes for cap_sum; host only
+ * Other arguments and synchronization as hcsp_spgemm_predicted.  Errors:
+ * HCSP_E_INVALID when the clamped capacities need more scratch than cap_sum
+ * declares (detected before any numeric launch; nothing is written but
+ * C_row_ptr_d).
+ */
+int hcsp_predicted_rows_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, int64_t cap_sum,
+                                  size_t *bytes);
+int hcsp_spgemm_predicted_rows(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts,
+                               const int32_t *cap_row_d, int64_t cap_sum, int64_t *C_row_ptr_d, int32_t *C_col_d,
+                               double *C_val_d, int64_t capacity, int64_t *nnz_h, int64_t *n_overflow_h, void *ws_d,
+                               size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------- orderings
  * Row orderings applied before row-wise or cluster-wise SpGEMM (paper, Sec.

@@ -145,6 +145,11 @@ _SIGS = {
     "hcsp_spgemm_predicted": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts), ctypes.c_float,
                                i64, vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, ctypes.c_size_t,
                                vp], ctypes.c_int),
+    "hcsp_predicted_rows_workspace": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts), i64,
+                                       ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hcsp_spgemm_predicted_rows": ([ctypes.POINTER(c_csr), ctypes.POINTER(c_csr), ctypes.POINTER(c_opts), vp, i64,
+                                    vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, ctypes.c_size_t,
+                                    vp], ctypes.c_int),
     "hcsp_mlp_forward": ([vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
     "hcsp_mlp_backward": ([vp, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, vp], ctypes.c_int),
     "hcsp_mlp_adam": ([vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp],
@@ -900,20 +905,32 @@ def spgemm_products(A: DeviceCSR, B: DeviceCSR, stream=None) -> int:
 
 
 class PredictedProduct:
-    """C = A x B with row sizes predicted from a compression ratio (nnz(C)/products, margin included); rows
-    the prediction does not hold are recomputed through the exact symbolic phase.  ``run()`` returns C;
+    """C = A x B with row sizes predicted from a compression ratio (nnz(C)/products, margin included), or
+    given per row (``cap_row``: host integers, one per row of A, each clamped to [1, the row's products]);
+    rows the prediction does not hold are recomputed through the exact symbolic phase.  ``run()`` returns C;
     ``n_overflow`` is the number of rows recomputed."""
 
-    def __init__(self, A: DeviceCSR, B: DeviceCSR, ratio: float, o: c_opts | None = None, capacity=None):
+    def __init__(self, A: DeviceCSR, B: DeviceCSR, ratio: float | None, o: c_opts | None = None, capacity=None,
+                 cap_row=None):
         import torch
         self.A, self.B, self.o = A, B, o or c_opts()
-        self.ratio = float(min(1.0, max(ratio, 1e-6)))
+        self.ratio = float(min(1.0, max(ratio if ratio is not None else 1.0, 1e-6)))
         self.products = spgemm_products(A, B)
         a, b = A.c(), B.c()
         n = ctypes.c_size_t()
-        _check(lib().hcsp_predicted_workspace(ctypes.byref(a), ctypes.byref(b), ctypes.byref(self.o), self.ratio,
-                                              self.products, ctypes.byref(n)), "predicted_workspace")
         dev = B.row_ptr.device
+        self.cap_row = None
+        if cap_row is not None:
+            c = np.asarray(cap_row, dtype=np.int64)
+            if c.shape != (A.nrows,) or np.any(c > np.iinfo(np.int32).max):
+                raise ValueError("cap_row: one int32 capacity per row of A")
+            self.cap_sum = int(np.maximum(c, 0).sum())
+            self.cap_row = torch.from_numpy(c.astype(np.int32)).to(dev)
+            _check(lib().hcsp_predicted_rows_workspace(ctypes.byref(a), ctypes.byref(b), ctypes.byref(self.o),
+                                                       self.cap_sum, ctypes.byref(n)), "predicted_rows_workspace")
+        else:
+            _check(lib().hcsp_predicted_workspace(ctypes.byref(a), ctypes.byref(b), ctypes.byref(self.o),
+                                                  self.ratio, self.products, ctypes.byref(n)), "predicted_workspace")
         self.ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
         self.C_row_ptr = torch.empty(A.nrows + 1, dtype=torch.int64, device=dev)
         cap = self.products if capacity is None else capacity
@@ -924,9 +941,16 @@ class PredictedProduct:
     def run(self, stream=None) -> DeviceCSR:
         a, b = self.A.c(), self.B.c()
         nnz, novf = i64(), i64()
-        _check(lib().hcsp_spgemm_predicted(ctypes.byref(a), ctypes.byref(b), ctypes.byref(self.o), self.ratio,
-                                           self.products, _tp(self.C_row_ptr), _tp(self.C_col), _tp(self.C_val),
-                                           self.C_col.numel(), ctypes.byref(nnz), ctypes.byref(novf), _tp(self.ws),
-                                           self.ws.numel(), _stream(stream)), "spgemm_predicted")
+        if self.cap_row is not None:
+            _check(lib().hcsp_spgemm_predicted_rows(ctypes.byref(a), ctypes.byref(b), ctypes.byref(self.o),
+                                                    _tp(self.cap_row), self.cap_sum, _tp(self.C_row_ptr),
+                                                    _tp(self.C_col), _tp(self.C_val), self.C_col.numel(),
+                                                    ctypes.byref(nnz), ctypes.byref(novf), _tp(self.ws),
+                                                    self.ws.numel(), _stream(stream)), "spgemm_predicted_rows")
+        else:
+            _check(lib().hcsp_spgemm_predicted(ctypes.byref(a), ctypes.byref(b), ctypes.byref(self.o), self.ratio,
+                                               self.products, _tp(self.C_row_ptr), _tp(self.C_col), _tp(self.C_val),
+                                               self.C_col.numel(), ctypes.byref(nnz), ctypes.byref(novf),
+                                               _tp(self.ws), self.ws.numel(), _stream(stream)), "spgemm_predicted")
         self.nnz, self.n_overflow = nnz.value, novf.value
         return DeviceCSR(self.C_row_ptr, self.C_col[:self.nnz], self.C_val[:self.nnz], self.A.nrows, self.B.ncols)

@@ -930,50 +930,69 @@ static size_t layout_pred(size_t base_bytes, int64_t nrows, int64_t brows, int64
     return align_up(off, 256);
 }
 
-int hcsp_predicted_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
-                             int64_t products, size_t *bytes)
+// workspace bytes of a predicted product whose padded scratch holds `entries`
+static int pred_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, int64_t entries,
+                          size_t *bytes)
 {
-    clear_error();
     hcsp_operand op;
     std::memset(&op, 0, sizeof op);
     if (A) op.csr = *A;
     OpView v;
     int rc = check_operands(A ? &op : nullptr, B, &v);
     if (rc) return rc;
-    if (!bytes || !(ratio > 0.0f && ratio <= 1.0f) || products < 0)
-        return fail(HCSP_E_INVALID, "bad arguments (ratio must be in (0, 1])");
     Tune tu;
     rc = make_tune(opts, B, false, &tu);
     if (rc) return rc;
     Workspace ws;
     const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, nullptr, &ws);
     PredWs p;
-    *bytes = layout_pred(base, v.nrows, B->nrows, pred_entries(ratio, products, v.nrows), nullptr, &p);
+    *bytes = layout_pred(base, v.nrows, B->nrows, entries, nullptr, &p);
     return HCSP_OK;
 }
 
-int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
-                          int64_t products, int64_t *C_row_ptr_d, int32_t *C_col_d, double *C_val_d,
-                          int64_t capacity, int64_t *nnz_h, int64_t *n_overflow_h, void *ws_d, size_t ws_bytes,
-                          void *stream)
+int hcsp_predicted_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
+                             int64_t products, size_t *bytes)
 {
     clear_error();
+    if (!bytes || !(ratio > 0.0f && ratio <= 1.0f) || products < 0)
+        return fail(HCSP_E_INVALID, "bad arguments (ratio must be in (0, 1])");
+    return pred_workspace(A, B, opts, pred_entries(ratio, products, A ? A->nrows : 0), bytes);
+}
+
+// padded scratch entries for per-row capacities whose positive values sum to cap_sum (rows with a
+// capacity below 1 get 1)
+static int64_t pred_rows_entries(int64_t cap_sum, int64_t nrows) { return std::max<int64_t>(1, cap_sum + nrows); }
+
+int hcsp_predicted_rows_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, int64_t cap_sum,
+                                  size_t *bytes)
+{
+    clear_error();
+    if (!bytes || cap_sum < 0) return fail(HCSP_E_INVALID, "bad arguments");
+    return pred_workspace(A, B, opts, pred_rows_entries(cap_sum, A ? A->nrows : 0), bytes);
+}
+
+// The predicted-size product with row capacities from one ratio (cap_row_d null) or given per row; the
+// padded scratch holds `entries`.
+static int predicted_impl(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
+                          const int32_t *cap_row_d, int64_t entries, int64_t *C_row_ptr_d, int32_t *C_col_d,
+                          double *C_val_d, int64_t capacity, int64_t *nnz_h, int64_t *n_overflow_h, void *ws_d,
+                          size_t ws_bytes, void *stream)
+{
     hcsp_operand op;
     std::memset(&op, 0, sizeof op);
     if (A) op.csr = *A;
     OpView v;
     int rc = check_operands(A ? &op : nullptr, B, &v);
     if (rc) return rc;
-    if (!(ratio > 0.0f && ratio <= 1.0f) || products < 0 || !C_row_ptr_d || capacity < 0 ||
-        (capacity > 0 && (!C_col_d || !C_val_d)))
-        return fail(HCSP_E_INVALID, "bad arguments (ratio must be in (0, 1])");
+    if (!C_row_ptr_d || capacity < 0 || (capacity > 0 && (!C_col_d || !C_val_d)))
+        return fail(HCSP_E_INVALID, "bad arguments");
     Tune tu;
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
     Workspace ws;
     const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, (char *)ws_d, &ws);
     PredWs pw;
-    const size_t need = layout_pred(base, v.nrows, B->nrows, pred_entries(ratio, products, v.nrows), (char *)ws_d, &pw);
+    const size_t need = layout_pred(base, v.nrows, B->nrows, entries, (char *)ws_d, &pw);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "predicted-size workspace too small");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = v.nrows;
@@ -986,15 +1005,20 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     // 1. capacities and bins from the prediction, padded row starts
     BinArgs ba = bin_args(&op, B, ws, tu, n, C_row_ptr_d);
     ba.ratio = ratio;
+    ba.cap_row = cap_row_d;
     ba.pad = pw.pad_off;
     ba.b_span = pw.span;
     HCSP_HIP(launch_row_span(B->row_ptr, B->col, B->nrows, pw.span, s));
     HCSP_HIP(launch_work_pred(ba, s));
     HCSP_HIP(launch_scatter(ws.bin, n, ws.bin_hist, kNumBins, ws.num_count, ws.order_num, s));
     HCSP_HIP(launch_scan_exclusive(pw.pad_off, n + 1, ws.scan_tmp, s));
-    int64_t cnt[HCSP_MAX_BINS];
+    int64_t cnt[HCSP_MAX_BINS], padded = 0;
     HCSP_HIP(hipMemcpyAsync(cnt, ws.num_count, 8 * kNumBins, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(hipMemcpyAsync(&padded, pw.pad_off + n, 8, hipMemcpyDeviceToHost, s));
     HCSP_HIP(hipStreamSynchronize(s));
+    if (padded > pw.entries)  // per-row capacities summing past what the caller declared
+        return fail(HCSP_E_INVALID, "row capacities need " + std::to_string(padded) + " scratch entries, " +
+                                        std::to_string(pw.entries) + " declared");
     // 2. numeric with the predicted tables, into the padded scratch
     SpArgs a = base_args(&op, B, ws, tu);
     a.order = ws.order_num;
@@ -1069,6 +1093,29 @@ int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     if (e & kErrCapacity) return fail(HCSP_E_CAPACITY, "output capacity too small");
     if (e & kErrCount) return fail(HCSP_E_INVALID, "row counts differ between the phases (inputs changed?)");
     return HCSP_OK;
+}
+
+int hcsp_spgemm_predicted(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts, float ratio,
+                          int64_t products, int64_t *C_row_ptr_d, int32_t *C_col_d, double *C_val_d,
+                          int64_t capacity, int64_t *nnz_h, int64_t *n_overflow_h, void *ws_d, size_t ws_bytes,
+                          void *stream)
+{
+    clear_error();
+    if (!(ratio > 0.0f && ratio <= 1.0f) || products < 0)
+        return fail(HCSP_E_INVALID, "bad arguments (ratio must be in (0, 1])");
+    return predicted_impl(A, B, opts, ratio, nullptr, pred_entries(ratio, products, A ? A->nrows : 0), C_row_ptr_d,
+                          C_col_d, C_val_d, capacity, nnz_h, n_overflow_h, ws_d, ws_bytes, stream);
+}
+
+int hcsp_spgemm_predicted_rows(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts *opts,
+                               const int32_t *cap_row_d, int64_t cap_sum, int64_t *C_row_ptr_d, int32_t *C_col_d,
+                               double *C_val_d, int64_t capacity, int64_t *nnz_h, int64_t *n_overflow_h, void *ws_d,
+                               size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (!cap_row_d || cap_sum < 0) return fail(HCSP_E_INVALID, "bad arguments");
+    return predicted_impl(A, B, opts, 1.0f, cap_row_d, pred_rows_entries(cap_sum, A ? A->nrows : 0), C_row_ptr_d,
+                          C_col_d, C_val_d, capacity, nnz_h, n_overflow_h, ws_d, ws_bytes, stream);
 }
 
 // ================================================================ batches

@@ -263,8 +263,10 @@ struct BinArgs {
     int nprob;
     // restriction to the units with active[u] != 0 (nullable: all units)
     const uint8_t *active;
-    // predicted sizes: row capacity min(products, ceil(products * ratio)) into pad[]
+    // predicted sizes: row capacity min(products, ceil(products * ratio)), or the
+    // given one clamped to [1, products], into pad[]
     float ratio;
+    const int32_t *cap_row;  // per-row capacities instead of the ratio (nullable)
     int64_t *pad;
     const int2 *b_span;  // predicted sizes: first and last column of each row of B (nullable)
 };

@@ -245,8 +245,9 @@ hipError_t launch_products(const hcsp_csr &A, const hcsp_csr &B, int64_t *out, h
 
 // Per CSR row: products, a column range that holds every output column (the
 // smallest first and largest last column over the rows of B it reaches), and
-// the predicted capacity min(products, ceil(products * ratio)), which picks
-// the numeric bin directly (no symbolic phase).  Empty rows get count 0.
+// the predicted capacity min(products, ceil(products * ratio)) -- or the
+// caller's per-row capacity clamped to [1, products] -- which picks the
+// numeric bin directly (no symbolic phase).  Empty rows get count 0.
 __global__ void __launch_bounds__(256) k_work_pred(BinArgs a)
 {
     __shared__ int hist[kNumBins];
@@ -274,8 +275,8 @@ __global__ void __launch_bounds__(256) k_work_pred(BinArgs a)
         int bin = kBinEmpty;
         int64_t cap = 0;
         if (probes > 0) {
-            cap = min(probes, (int64_t)ceilf((float)probes * a.ratio));
-            cap = max(cap, (int64_t)1);
+            cap = a.cap_row ? (int64_t)a.cap_row[u] : (int64_t)ceilf((float)probes * a.ratio);
+            cap = max(min(cap, probes), (int64_t)1);
             const int64_t need = (cap * 100 + a.load_pct - 1) / a.load_pct;
             bin = kNumGlobal;
             for (int t = 0; t < kNumT; ++t) {

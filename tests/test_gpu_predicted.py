@@ -74,3 +74,40 @@ def test_predicted_capacity_error_is_reported():
     with pytest.raises(hc.HcspError) as e:
         P.run()
     assert e.value.status == -5
+
+
+def test_per_row_capacities_bitwise_and_overflow_rows():
+    rng = np.random.default_rng(11)
+    for name, A, B in inputs():
+        B = A if B is None else B
+        ref = oracle.spgemm(A, B)
+        counts = np.diff(ref.rp)
+        ub = np.zeros(A.nrows, np.int64)
+        np.add.at(ub, np.repeat(np.arange(A.nrows), np.diff(A.rp)), np.diff(B.rp)[A.col])
+        Ad, Bd = hc.DeviceCSR.from_host(A), hc.DeviceCSR.from_host(B)
+        # exact counts: nothing overflows; a seeded third of the rows one short: exactly those overflow
+        short = (rng.random(A.nrows) < 1 / 3) & (counts >= 2)
+        for caps, expect in ((counts.copy(), np.zeros(A.nrows, bool)),
+                             (np.where(short, counts - 1, counts + 3), short),
+                             (np.where(short, -5, ub), short & (counts > 1))):
+            cap_eff = np.where(ub > 0, np.clip(caps, 1, np.maximum(ub, 1)), 0)
+            need = (cap_eff * 100 + 59) // 60
+            P = hc.PredictedProduct(Ad, Bd, None, cap_row=caps)
+            C = P.run().to_host()
+            np.testing.assert_array_equal(C.rp, ref.rp, err_msg=name)
+            np.testing.assert_array_equal(C.col, ref.col, err_msg=name)
+            np.testing.assert_array_equal(C.val, ref.val, err_msg=name)
+            over = counts > cap_eff
+            assert np.array_equal(over, expect), name
+            if not np.any(need > 6144):
+                assert P.n_overflow == int(np.sum(over)), (name, P.n_overflow, int(np.sum(over)))
+
+
+def test_per_row_capacities_declared_sum_too_small():
+    A = synth.uniform(300, 300, 6, 2)
+    Ad = hc.DeviceCSR.from_host(A)
+    P = hc.PredictedProduct(Ad, Ad, None, cap_row=np.full(A.nrows, 20))
+    P.cap_sum = 100          # declares less than the rows ask for (the workspace is larger, so it stays in bounds)
+    with pytest.raises(hc.HcspError) as e:
+        P.run()
+    assert e.value.status == -1
