@@ -595,7 +595,10 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
         if (b == kSymGlobal) {
             HCSP_HIP(launch_win_prep(true, v.cluster, a, t));
             HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, t));
-            HCSP_HIP(launch_sym_win(v.cluster, a, win_blocks(win_sym_wave_bytes()), t));
+            const int e = ensure_lds((size_t)sym_bm_bytes(), tu.lds_budget);
+            if (e) return e;
+            const int64_t per_cu = std::max<int64_t>(1, (160 * 1024) / sym_bm_bytes());
+            HCSP_HIP(launch_sym_bm(v.cluster, a, (int)(per_cu * cu_count()), t));
             return HCSP_OK;
         }
         const int sc = (b - 1) / kSymT;

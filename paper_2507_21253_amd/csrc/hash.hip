@@ -1182,10 +1182,11 @@ struct WinRow {
 };
 
 // Loads the next round of a window row's items for the window [w0, w1):
-// lane i takes item q0+i and the part of row k of B inside the window.
+// lane i takes item q0+i and the part of row k of B inside the window
+// (clip false: the caller knows every row of B reached lies inside).
 template <bool NUM, bool CL>
 __device__ __forceinline__ int load_round_win(const SpArgs &a, const WinRow &r, int64_t &q0, int &off0,
-                                              ItemRec *items, uint64_t *sbits, int w0, int w1)
+                                              ItemRec *items, uint64_t *sbits, int w0, int w1, bool clip = true)
 {
     const int lane = (int)__lane_id();
     sbits[lane] = 0ull;
@@ -1196,18 +1197,16 @@ __device__ __forceinline__ int load_round_win(const SpArgs &a, const WinRow &r, 
         const int k = CL ? a.cl_col[q] : a.a_col[q];
         lo = (uint32_t)a.b_rp[k];
         hi = (uint32_t)a.b_rp[k + 1];
-        if (lo < hi && ld_col(a.b_col, lo) < w0) lo = lower_bound_col(a.b_col, lo + 1, hi, w0);
-        if (lo < hi && ld_col(a.b_col, hi - 1) >= w1) hi = lower_bound_col(a.b_col, lo, hi - 1, w1);
+        if (clip && lo < hi && ld_col(a.b_col, lo) < w0) lo = lower_bound_col(a.b_col, lo + 1, hi, w0);
+        if (clip && lo < hi && ld_col(a.b_col, hi - 1) >= w1) hi = lower_bound_col(a.b_col, lo, hi - 1, w1);
         if (NUM) a1 = CL ? a.cl_val[r.vbase + (q - r.it0) * r.s + r.l] : a.a_val[q];
     }
     const uint64_t ab = (uint64_t)__double_as_longlong(a1);
     return flatten_round(r.it1, q0, off0, items, sbits, lo, (int)(hi - lo), (uint32_t)ab, (uint32_t)(ab >> 32));
 }
 
-// Window table sizes (slots, powers of two): keys only for the symbolic
-// phase, keys and values for the numeric one; a window aims at 5/8 of a
-// table of keys.
-constexpr int kWinSymLog2T = 11;
+// Numeric window table size (slots, a power of two, keys and values); a
+// window aims at 5/8 of a table of keys.
 constexpr int kWinNumLog2T = 10;
 constexpr int kWinBuckets = 1 << (kWinNumLog2T - 1);  // rank buckets of a numeric window
 
@@ -1228,60 +1227,7 @@ struct WinNumLayout {
     }
 };
 
-int64_t win_sym_wave_bytes() { return SymLayout(0, 1 << kWinSymLog2T).bytes; }
 int64_t win_num_wave_bytes() { return WinNumLayout().bytes; }
-
-// Distinct output columns of window row r inside [w0, w1), or -1 when the
-// table got too full for another batch of passes (window too wide).
-template <bool CL>
-__device__ __forceinline__ int sym_window(const SpArgs &a, const WinRow &r, int w0, int w1, unsigned char *base)
-{
-    constexpr int T = 1 << kWinSymLog2T, kR = 8;
-    const int lane = (int)__lane_id();
-    const SymLayout L(0, T);
-    int *keys = (int *)(base + L.keys);
-    ItemRec *items = (ItemRec *)(base + L.items);
-    uint64_t *sbits = (uint64_t *)(base + L.sbits);
-    lds_fill(keys, 4 * T, (uint32_t)kEmpty);
-    if (lane == 0) keys[T] = kDummyKey;
-    const uint64_t le = lanemask_le(lane);
-    int total = 0;  // keys in the table (wave-uniform)
-    int64_t q0 = r.it0;
-    int off0 = 0;
-    // every probe finds a free slot while at most T - 1 keys are in
-    auto probe = [&](int j) {
-        uint32_t h = j == kDummyKey ? (uint32_t)T : ((uint32_t)j * 2654435761u) >> (32 - kWinSymLog2T);
-        int old = atomicCAS(&keys[h], kEmpty, j);
-        while (old != kEmpty && old != j) {
-            h = (h + 1u) & (uint32_t)(T - 1);
-            old = atomicCAS(&keys[h], kEmpty, j);
-        }
-        total += __popcll(__ballot(old == kEmpty && h != (uint32_t)T));
-    };
-    while (q0 < r.it1) {
-        const int E = load_round_win<false, CL>(a, r, q0, off0, items, sbits, w0, w1);
-        const int npass = (E + 63) >> 6;
-        int cum = 0;
-        for (int p = 0; p < npass; p += kR) {
-            if (total > T - 1 - 64 * kR) return -1;
-            Pass<false, false> d[kR];
-#pragma unroll
-            for (int rr = 0; rr < kR; ++rr) {
-                if (p + rr < npass) {
-                    const uint64_t w = uniform64(sbits[p + rr]);
-                    d[rr] = fetch_pass<false, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
-                    cum += __popcll(w);
-                } else {
-                    d[rr].j = kDummyKey;
-                }
-            }
-#pragma unroll
-            for (int rr = 0; rr < kR; ++rr)
-                if (p + rr < npass) probe(d[rr].j);
-        }
-    }
-    return total;
-}
 
 // Entries of window row r of C inside [w0, w1), written in column order to
 // ccol/cval; returns their number, -1 when the table got too full
@@ -1486,44 +1432,174 @@ __device__ __forceinline__ WinPair win_pair(const SpArgs &a, int64_t i)
     return w;
 }
 
-// Symbolic: one wavefront per (row, chunk); the chunk's count goes to
-// chunk_cnt[pair] and is added to the row's count (zeroed by the binning
-// kernel); the unit's first pair goes to sym_base.
+// Symbolic phase of the units too long for shared-memory tables: their member
+// rows' output columns are counted in a bitmap instead of a table, one
+// workgroup of kBmWaves wavefronts per unit (persistent over the bin), member
+// rows one after another.  A row's column range [lo, hi] (the first and last
+// columns of the rows of B its items reach) is taken in segments of
+// 2^kBmLog2Bits columns (one segment when the range fits, and then no row of B
+// needs clipping); the wavefronts take the row's items 64 at a time from a
+// shared counter and set one bit per product by an atomic OR that returns
+// nothing (ORs commute, so how the items are shared out does not change the
+// bitmap).  The bits are then counted per column chunk of the numeric phase
+// -- chunk_cnt[first + l*nch + c] for member l, chunk c, first the unit's
+// first pair -- and the row's total is added to its count (zeroed by the
+// binning kernel).
+constexpr int kBmLog2Bits = 20;  // columns per segment: a 128 KiB bitmap
+constexpr int kBmWaves = 8;
+constexpr int kBmWords = 1 << (kBmLog2Bits - 5);
+constexpr int kBmWaveBytes = 16 * 64 + 8 * kRoundPasses;  // a wavefront's item records and start bits
+
+struct BmLayout {
+    int bm, ccnt, red, next, waves, bytes;
+    __host__ __device__ BmLayout()
+    {
+        bm = 0;
+        ccnt = 4 * kBmWords;             // kWinChunksMax chunk counters
+        red = ccnt + 4 * kWinChunksMax;  // per-wavefront partial lo/hi
+        next = red + 8 * kBmWaves;       // the next item group to take
+        waves = align16(next + 4);
+        bytes = waves + kBmWaves * kBmWaveBytes;
+    }
+};
+
+int64_t sym_bm_bytes() { return BmLayout().bytes; }
+
 template <bool CL>
-__global__ void __launch_bounds__(64) k_sym_win(SpArgs a)
+__global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int64_t tk = (1 << kWinSymLog2T) * 5 / 8;
-    const int lane = (int)__lane_id();
-    const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
-    for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
-        const WinPair w = win_pair<CL>(a, i);
-        int lo, hi;
-        win_chunk(a.ncols, w.nch, w.c, &lo, &hi);
-        // first width: as if the chunk's share of the products were distinct
-        const int64_t ub =
-            max<int64_t>(1, min<int64_t>((int64_t)uniform64((uint64_t)a.probes[w.u]) / w.nch, hi - lo));
-        int64_t width = max<int64_t>(1, min<int64_t>(hi - lo, tk * (hi - lo) / ub));
-        int64_t n = 0;
-        for (int w0 = lo; w0 < hi;) {
-            const int w1 = (int)min<int64_t>(hi, w0 + width);
-            const int k = sym_window<CL>(a, w.r, w0, w1, smem);
-            if (k < 0) {
-                width = max<int64_t>(1, (w1 - w0) / 2);
-                continue;
+    constexpr int kR = 8, NT = 64 * kBmWaves;
+    const BmLayout L;
+    uint32_t *bm = (uint32_t *)(smem + L.bm);
+    int *ccnt = (int *)(smem + L.ccnt);
+    int *red = (int *)(smem + L.red);
+    int *next = (int *)(smem + L.next);
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)__lane_id();
+    ItemRec *items = (ItemRec *)(smem + L.waves + wave * kBmWaveBytes);
+    uint64_t *sbits = (uint64_t *)(smem + L.waves + wave * kBmWaveBytes + 16 * 64);
+    const uint64_t le = lanemask_le(lane);
+    for (int64_t i = xcd_block(); i < a.count; i += gridDim.x) {
+        const int u = uniform(a.order[a.bin_begin + i]);
+        const UnitView v = unit_view<CL>(a, u);
+        const int64_t first = (int64_t)uniform64((uint64_t)a.win_base[i]);
+        const int nch = (int)(((int64_t)uniform64((uint64_t)a.win_base[i + 1]) - first) / v.s);
+        const bool room = first + (int64_t)v.s * nch <= a.win_cap;
+        const int64_t cw = (a.ncols + nch - 1) / nch;  // chunk width (win_chunk)
+        const int m = (int)(v.it1 - v.it0);
+        for (int l = 0; l < v.s; ++l) {
+            int lo = INT_MAX, hi = -1;
+            for (int64_t q = v.it0 + threadIdx.x; q < v.it1; q += NT) {
+                if (CL && !((a.cl_mask[q] >> l) & 1u)) continue;
+                const int k = CL ? a.cl_col[q] : a.a_col[q];
+                const int64_t b0 = a.b_rp[k], b1 = a.b_rp[k + 1];
+                if (b1 > b0) {
+                    lo = min(lo, ld_col(a.b_col, (uint32_t)b0));
+                    hi = max(hi, ld_col(a.b_col, (uint32_t)(b1 - 1)));
+                }
             }
-            n += k;
-            width = win_next(w1 - w0, k, tk, hi - lo);
-            w0 = w1;
+            for (int o = 32; o > 0; o >>= 1) {
+                lo = min(lo, __shfl_xor(lo, o));
+                hi = max(hi, __shfl_xor(hi, o));
+            }
+            if (lane == 0) {
+                red[wave] = lo;
+                red[kBmWaves + wave] = hi;
+            }
+            for (int c = (int)threadIdx.x; c < nch; c += NT) ccnt[c] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < kBmWaves; ++w) {
+                lo = min(lo, red[w]);
+                hi = max(hi, red[kBmWaves + w]);
+            }
+            lo = uniform(lo);
+            hi = uniform(hi);
+            for (int64_t g0 = lo; g0 <= (int64_t)hi; g0 += (int64_t)1 << kBmLog2Bits) {
+                const int w0 = (int)g0;
+                const int w1 = (int)min<int64_t>((int64_t)hi + 1, g0 + ((int64_t)1 << kBmLog2Bits));
+                const int nw = (w1 - w0 + 31) >> 5;
+                const bool clip = g0 > lo || w1 <= hi;  // not the whole range in one segment
+                for (int x = (int)threadIdx.x; x < ((nw + 3) >> 2); x += NT) ((uint4 *)bm)[x] = make_uint4(0u, 0u, 0u, 0u);
+                if (threadIdx.x == 0) *next = 0;
+                __syncthreads();
+                for (;;) {
+                    int g = 0;
+                    if (lane == 0) g = atomicAdd(next, 64);
+                    g = uniform(__shfl(g, 0));
+                    if (g >= m) break;
+                    const WinRow r{v.it0 + g, min(v.it1, v.it0 + g + 64), v.vbase, l, v.s};
+                    int64_t q0 = r.it0;
+                    int off0 = 0;
+                    while (q0 < r.it1) {
+                        const int E = load_round_win<false, CL>(a, r, q0, off0, items, sbits, w0, w1, clip);
+                        const int npass = (E + 63) >> 6;
+                        int cum = 0;
+                        for (int p = 0; p < npass; p += kR) {
+                            Pass<false, false> d[kR];
+#pragma unroll
+                            for (int rr = 0; rr < kR; ++rr) {
+                                if (p + rr < npass) {
+                                    const uint64_t w = uniform64(sbits[p + rr]);
+                                    d[rr] = fetch_pass<false, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                                    cum += __popcll(w);
+                                } else {
+                                    d[rr].j = kDummyKey;
+                                }
+                            }
+#pragma unroll
+                            for (int rr = 0; rr < kR; ++rr) {
+                                if (d[rr].j != kDummyKey) {
+                                    const uint32_t x = (uint32_t)(d[rr].j - w0);
+                                    atomicOr(&bm[x >> 5], 1u << (x & 31u));
+                                }
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                // count the bits per chunk: a wavefront's 64 words usually lie in one chunk
+                for (int x0 = wave * 64; x0 < nw; x0 += NT) {
+                    const int wd = x0 + lane;
+                    const uint32_t bits = wd < nw ? bm[wd] : 0u;
+                    const int64_t col0 = g0 + 32 * (int64_t)wd;
+                    const int c0 = (int)(col0 / cw);
+                    const int c1 = (int)(min<int64_t>(col0 + 31, a.ncols - 1) / cw);
+                    const int cf = uniform(__shfl(c0, 0));
+                    if (__ballot(wd < nw && (c0 != cf || c1 != cf)) == 0ull) {
+                        int n = __popc(bits);
+                        for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+                        if (lane == 0 && n) atomicAdd(&ccnt[cf], n);
+                    } else {
+                        uint32_t y = bits;
+                        while (y) {
+                            const int c = (int)((col0 + (__ffs((int)y) - 1)) / cw);
+                            const int64_t nb = (int64_t)(c + 1) * cw - col0;  // this word's bits before chunk c+1
+                            const uint32_t mk = nb >= 32 ? 0xffffffffu : ((1u << nb) - 1u);
+                            atomicAdd(&ccnt[c], __popc(y & mk));
+                            y &= ~mk;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            int64_t tot = 0;
+            for (int c = (int)threadIdx.x; c < nch; c += NT) {
+                const int n = ccnt[c];
+                tot += n;
+                if (room) a.chunk_cnt[first + (int64_t)l * nch + c] = n;
+            }
+            for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+            if (lane == 0 && tot) {
+                const int64_t row = CL ? (int64_t)a.perm[v.pos0 + l] : (int64_t)u;
+                atomicAdd((unsigned long long *)&a.c_rp[row], (unsigned long long)tot);
+            }
+            __syncthreads();
         }
-        if (lane == 0) {
-            if (i < a.win_cap) a.chunk_cnt[i] = (int32_t)n;
-            else atomicOr(a.err, kErrWindows);
-            if (n) atomicAdd((unsigned long long *)&a.c_rp[w.row], (unsigned long long)n);
-            if (w.c == 0 && w.r.l == 0) {
-                a.ucount[w.u] = INT32_MAX;
-                a.sym_base[w.u] = w.first;
-            }
+        if (threadIdx.x == 0) {
+            if (!room) atomicOr(a.err, kErrWindows);
+            a.ucount[u] = INT32_MAX;
+            a.sym_base[u] = first;
         }
     }
 }
@@ -1599,10 +1675,11 @@ hipError_t launch_win_prep(bool sym, bool cluster, const SpArgs &a, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_sym_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
+hipError_t launch_sym_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
 {
-    if (cluster) hipLaunchKernelGGL(k_sym_win<true>, dim3(blocks), dim3(64), (size_t)win_sym_wave_bytes(), s, a);
-    else hipLaunchKernelGGL(k_sym_win<false>, dim3(blocks), dim3(64), (size_t)win_sym_wave_bytes(), s, a);
+    const dim3 g(blocks), t(64 * kBmWaves);
+    if (cluster) hipLaunchKernelGGL(k_sym_bm<true>, g, t, (size_t)sym_bm_bytes(), s, a);
+    else hipLaunchKernelGGL(k_sym_bm<false>, g, t, (size_t)sym_bm_bytes(), s, a);
     return hipGetLastError();
 }
 

@@ -235,9 +235,9 @@ __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
     return (int)(n < 1 ? 1 : (n > kWinChunksMax ? kWinChunksMax : n));
 }
 hipError_t launch_win_prep(bool sym, bool cluster, const SpArgs &a, hipStream_t s);
-int64_t win_sym_wave_bytes();
+int64_t sym_bm_bytes();
 int64_t win_num_wave_bytes();
-hipError_t launch_sym_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
+hipError_t launch_sym_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
 hipError_t launch_num_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
 
 // launchers (util.hip)

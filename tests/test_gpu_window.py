@@ -5,8 +5,9 @@ a table; C must still equal the
 oracle bit for bit, since every output entry gets its products in ascending k.
 
 Cases: rows counted by chunks in the symbolic phase (products beyond the
-largest symbolic table), with one chunk or up to 256 (win_chunk_log2 sets
-the products per chunk); rows counted whole in shared memory but too large
+largest symbolic table; a bitmap per row, the counts split at the numeric
+chunks), with one chunk or up to 256 (win_chunk_log2 sets the products per
+chunk); rows whose column range is wider than one bitmap segment; rows counted whole in shared memory but too large
 for the numeric tables (one chunk over the row's column range); output
 columns packed densely into part of a chunk, so that first windows overflow
 and are redone narrower in both phases; row panels; R-MAT rows; clustered
@@ -67,6 +68,19 @@ def test_packed_columns_force_narrower_windows(dense_cols):
     for log2 in (30, 8):
         o = hc.opts(sym_tmax_log2=7, num_tmax=96, win_chunk_log2=log2)
         assert_same(product(A, B, o), oracle.spgemm(A, B), "forced, chunks of 2^%d products" % log2)
+
+
+def test_rows_wider_than_one_bitmap_segment():
+    # output columns spread over 1.3M columns: the symbolic bitmap takes each
+    # row in three segments of 2^19 columns; chunk edges fall inside words
+    rng = np.random.default_rng(21)
+    ncols = 1_300_000
+    brows = [rng.choice(ncols, int(rng.integers(1_000, 4_000)), replace=False) for _ in range(40)]
+    arows = [rng.choice(40, int(rng.integers(0, 24)), replace=False) for _ in range(30)]
+    A, B = csr_from_rows(arows, 40, rng), csr_from_rows(brows, ncols, rng)
+    ref = oracle.spgemm(A, B)
+    for o in (None, hc.opts(sym_tmax_log2=8, num_tmax=128), hc.opts(sym_tmax_log2=8, num_tmax=128, win_chunk_log2=9)):
+        assert_same(product(A, B, o), ref, str(o))
 
 
 def test_rows_counted_whole_then_windowed():
