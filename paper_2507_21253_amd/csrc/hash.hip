@@ -1437,11 +1437,13 @@ __device__ __forceinline__ WinPair win_pair(const SpArgs &a, int64_t i)
 // workgroup of kBmWaves wavefronts per unit (persistent over the bin), member
 // rows one after another.  A row's column range [lo, hi] (the first and last
 // columns of the rows of B its items reach) is taken in segments of
-// 2^kBmLog2Bits columns (one segment when the range fits, and then no row of B
-// needs clipping); the wavefronts take the row's items 64 at a time from a
-// shared counter and set one bit per product by an atomic OR that returns
-// nothing (ORs commute, so how the items are shared out does not change the
-// bitmap).  The bits are then counted per column chunk of the numeric phase
+// 2^kBmLog2Bits columns.  When the range fits one segment (no row of B needs
+// clipping) the row's flattened product list is cut into kBmWaves equal
+// parts, one per wavefront (a few items carry most of the products of a
+// power-law row, so items alone would share the work out badly); otherwise
+// the wavefronts take the items 64 at a time from a shared counter.  Each
+// product sets one bit by an atomic OR that returns nothing (ORs commute, so
+// how the work is shared out does not change the bitmap).  The bits are then counted per column chunk of the numeric phase
 // -- chunk_cnt[first + l*nch + c] for member l, chunk c, first the unit's
 // first pair -- and the row's total is added to its count (zeroed by the
 // binning kernel).
@@ -1451,19 +1453,50 @@ constexpr int kBmWords = 1 << (kBmLog2Bits - 5);
 constexpr int kBmWaveBytes = 16 * 64 + 8 * kRoundPasses;  // a wavefront's item records and start bits
 
 struct BmLayout {
-    int bm, ccnt, red, next, waves, bytes;
+    int bm, ccnt, red, psum, next, waves, bytes;
     __host__ __device__ BmLayout()
     {
         bm = 0;
         ccnt = 4 * kBmWords;             // kWinChunksMax chunk counters
         red = ccnt + 4 * kWinChunksMax;  // per-wavefront partial lo/hi
-        next = red + 8 * kBmWaves;       // the next item group to take
+        psum = red + 8 * kBmWaves;       // per-wavefront partial product counts
+        next = psum + 8 * kBmWaves;      // the next item group to take
         waves = align16(next + 4);
         bytes = waves + kBmWaves * kBmWaveBytes;
     }
 };
 
 int64_t sym_bm_bytes() { return BmLayout().bytes; }
+
+// Item and offset holding product X of member row l's flattened product
+// list (items without bit l count no products); (it1, 0) if X is past the end.
+// Called by a whole wavefront.
+template <bool CL>
+__device__ __forceinline__ void bm_locate(const SpArgs &a, const UnitView &v, int l, int64_t X, int64_t &q0,
+                                          int &off0)
+{
+    const int lane = (int)__lane_id();
+    int64_t before = 0;  // products of the items before this group
+    for (int64_t g = v.it0; g < v.it1; g += 64) {
+        const int64_t q = g + lane;
+        int len = 0;
+        if (q < v.it1 && (!CL || ((a.cl_mask[q] >> l) & 1u))) {
+            const int k = CL ? a.cl_col[q] : a.a_col[q];
+            len = (int)(a.b_rp[k + 1] - a.b_rp[k]);
+        }
+        const int incl = wave_incl_scan(len);
+        const uint64_t past = __ballot(before + incl > X);
+        if (past) {
+            const int L = __ffsll((unsigned long long)past) - 1;
+            q0 = g + L;
+            off0 = (int)(X - before - (__shfl(incl, L) - __shfl(len, L)));
+            return;
+        }
+        before += __shfl(incl, 63);
+    }
+    q0 = v.it1;
+    off0 = 0;
+}
 
 template <bool CL>
 __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
@@ -1474,6 +1507,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
     uint32_t *bm = (uint32_t *)(smem + L.bm);
     int *ccnt = (int *)(smem + L.ccnt);
     int *red = (int *)(smem + L.red);
+    int64_t *psum = (int64_t *)(smem + L.psum);
     int *next = (int *)(smem + L.next);
     const int wave = (int)(threadIdx.x >> 6), lane = (int)__lane_id();
     ItemRec *items = (ItemRec *)(smem + L.waves + wave * kBmWaveBytes);
@@ -1489,6 +1523,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
         const int m = (int)(v.it1 - v.it0);
         for (int l = 0; l < v.s; ++l) {
             int lo = INT_MAX, hi = -1;
+            int64_t np = 0;  // the row's products
             for (int64_t q = v.it0 + threadIdx.x; q < v.it1; q += NT) {
                 if (CL && !((a.cl_mask[q] >> l) & 1u)) continue;
                 const int k = CL ? a.cl_col[q] : a.a_col[q];
@@ -1496,25 +1531,31 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
                 if (b1 > b0) {
                     lo = min(lo, ld_col(a.b_col, (uint32_t)b0));
                     hi = max(hi, ld_col(a.b_col, (uint32_t)(b1 - 1)));
+                    np += b1 - b0;
                 }
             }
             for (int o = 32; o > 0; o >>= 1) {
                 lo = min(lo, __shfl_xor(lo, o));
                 hi = max(hi, __shfl_xor(hi, o));
+                np += __shfl_xor(np, o);
             }
             if (lane == 0) {
                 red[wave] = lo;
                 red[kBmWaves + wave] = hi;
+                psum[wave] = np;
             }
             for (int c = (int)threadIdx.x; c < nch; c += NT) ccnt[c] = 0;
             __syncthreads();
+            np = 0;
 #pragma unroll
             for (int w = 0; w < kBmWaves; ++w) {
                 lo = min(lo, red[w]);
                 hi = max(hi, red[kBmWaves + w]);
+                np += psum[w];
             }
             lo = uniform(lo);
             hi = uniform(hi);
+            np = (int64_t)uniform64((uint64_t)np);
             for (int64_t g0 = lo; g0 <= (int64_t)hi; g0 += (int64_t)1 << kBmLog2Bits) {
                 const int w0 = (int)g0;
                 const int w1 = (int)min<int64_t>((int64_t)hi + 1, g0 + ((int64_t)1 << kBmLog2Bits));
@@ -1523,16 +1564,35 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
                 for (int x = (int)threadIdx.x; x < ((nw + 3) >> 2); x += NT) ((uint4 *)bm)[x] = make_uint4(0u, 0u, 0u, 0u);
                 if (threadIdx.x == 0) *next = 0;
                 __syncthreads();
+                // whole range: products [x0, x1) of the flattened list; else item groups
+                int64_t x0 = 0, x1 = INT64_MAX;
+                if (!clip) {
+                    x0 = np * wave / kBmWaves;
+                    x1 = np * (wave + 1) / kBmWaves;
+                }
                 for (;;) {
-                    int g = 0;
-                    if (lane == 0) g = atomicAdd(next, 64);
-                    g = uniform(__shfl(g, 0));
-                    if (g >= m) break;
-                    const WinRow r{v.it0 + g, min(v.it1, v.it0 + g + 64), v.vbase, l, v.s};
-                    int64_t q0 = r.it0;
+                    int64_t q0;
                     int off0 = 0;
-                    while (q0 < r.it1) {
-                        const int E = load_round_win<false, CL>(a, r, q0, off0, items, sbits, w0, w1, clip);
+                    WinRow r{v.it0, v.it1, v.vbase, l, v.s};
+                    if (clip) {
+                        int g = 0;
+                        if (lane == 0) g = atomicAdd(next, 64);
+                        g = uniform(__shfl(g, 0));
+                        if (g >= m) break;
+                        r.it0 = v.it0 + g;
+                        r.it1 = min(v.it1, v.it0 + g + 64);
+                        q0 = r.it0;
+                    } else {
+                        if (x0 >= x1) break;
+                        bm_locate<CL>(a, v, l, x0, q0, off0);
+                        q0 = (int64_t)uniform64((uint64_t)q0);
+                        off0 = uniform(off0);
+                    }
+                    int64_t rem = x1 - x0;
+                    while (q0 < r.it1 && rem > 0) {
+                        const int E = (int)min<int64_t>(
+                            load_round_win<false, CL>(a, r, q0, off0, items, sbits, w0, w1, clip), rem);
+                        rem -= E;
                         const int npass = (E + 63) >> 6;
                         int cum = 0;
                         for (int p = 0; p < npass; p += kR) {
@@ -1556,6 +1616,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
                             }
                         }
                     }
+                    if (!clip) break;
                 }
                 __syncthreads();
                 // count the bits per chunk: a wavefront's 64 words usually lie in one chunk
