@@ -24,6 +24,8 @@ int fail(int code, const std::string &msg)
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+static int64_t win_num_blocks();
+
 size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, bool windows, char *base,
                         Workspace *ws)
 {
@@ -58,6 +60,8 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->chunk_cnt = (int32_t *)take(4 * (size_t)ws->win_cap);
     ws->sym_base = (int64_t *)take(windows ? 8 * nu : 0);
     ws->win_base = (int64_t *)take(windows ? 8 * (nu + 1) : 0);
+    ws->win_cur_slots = windows ? win_num_blocks() : 0;
+    ws->win_cur = (int32_t *)take(4 * 2 * (size_t)kWinCurMax * (size_t)ws->win_cur_slots);
     ws->bytes = align_up(off, 256);
     return ws->bytes;
 }
@@ -299,6 +303,7 @@ static SpArgs base_args(const hcsp_operand *A, const hcsp_csr *B, const Workspac
     a.sym_base = ws.sym_base;
     a.win_base = ws.win_base;
     a.win_cap = ws.win_cap;
+    a.win_cur = ws.win_cur;
     a.win_log2 = tu.win_log2;
     a.ncols = B->ncols;
     a.unit_lo = 0;
@@ -363,6 +368,9 @@ static int win_blocks(int64_t wave_bytes)
     const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(32, (160 * 1024) / std::max<int64_t>(wave_bytes, 1)));
     return (int)(per_cu * cu_count());
 }
+
+// Wavefronts (one-wavefront blocks) of a numeric window launch.
+static int64_t win_num_blocks() { return win_blocks(win_num_wave_bytes()); }
 
 static int ensure_lds(size_t lds, int64_t budget)
 {
@@ -717,7 +725,8 @@ static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, cons
         if (b == kNumGlobal) {
             HCSP_HIP(launch_win_prep(false, cluster, a, st));
             HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, st));
-            HCSP_HIP(launch_num_win(cluster, a, win_blocks(win_num_wave_bytes()), st));
+            // one wavefront per cursor slot of the workspace at most
+            HCSP_HIP(launch_num_win(cluster, a, (int)std::max<int64_t>(1, std::min(win_num_blocks(), ws.win_cur_slots)), st));
             return HCSP_OK;
         }
         const int sc = (b - 1) / kNumT;

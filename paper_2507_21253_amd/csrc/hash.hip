@@ -1173,6 +1173,19 @@ __device__ __forceinline__ uint32_t lower_bound_col(const int32_t *col, uint32_t
     return lo;
 }
 
+// First position in [lo, hi) of B's columns whose column is >= x (hi if none),
+// by doubling steps from lo and then a binary search: a few loads when the
+// answer lies near lo, one when lo itself qualifies.
+__device__ __forceinline__ uint32_t gallop_col(const int32_t *col, uint32_t lo, uint32_t hi, int x)
+{
+    uint32_t b = lo, s = 1;
+    while (b + s - 1 < hi && ld_col(col, b + s - 1) < x) {
+        b += s;
+        s <<= 1;
+    }
+    return lower_bound_col(col, b, min(b + s - 1, hi), x);
+}
+
 // A row of the window path: a CSR row (items: its columns), or member l of
 // a cluster of s rows (items: the cluster's union columns whose mask has
 // bit l; values at vbase + t*s + l for union column t).
@@ -1183,10 +1196,14 @@ struct WinRow {
 
 // Loads the next round of a window row's items for the window [w0, w1):
 // lane i takes item q0+i and the part of row k of B inside the window
-// (clip false: the caller knows every row of B reached lies inside).
+// (clip false: the caller knows every row of B reached lies inside).  With
+// cursors, item t < kWinCurMax of the row starts at cin[t] (where its row of
+// B reached w0, left there by the window before) and its end goes to
+// cout[t] for the window after; without, both ends are searched.
 template <bool NUM, bool CL>
 __device__ __forceinline__ int load_round_win(const SpArgs &a, const WinRow &r, int64_t &q0, int &off0,
-                                              ItemRec *items, uint64_t *sbits, int w0, int w1, bool clip = true)
+                                              ItemRec *items, uint64_t *sbits, int w0, int w1, bool clip = true,
+                                              const int32_t *cin = nullptr, int32_t *cout = nullptr)
 {
     const int lane = (int)__lane_id();
     sbits[lane] = 0ull;
@@ -1194,11 +1211,19 @@ __device__ __forceinline__ int load_round_win(const SpArgs &a, const WinRow &r, 
     uint32_t lo = 0, hi = 0;
     double a1 = 0.0;
     if (q < r.it1 && (!CL || ((a.cl_mask[q] >> r.l) & 1u))) {
+        const int64_t t = q - r.it0;
+        const bool cur = cout && t < kWinCurMax;
         const int k = CL ? a.cl_col[q] : a.a_col[q];
         lo = (uint32_t)a.b_rp[k];
         hi = (uint32_t)a.b_rp[k + 1];
-        if (clip && lo < hi && ld_col(a.b_col, lo) < w0) lo = lower_bound_col(a.b_col, lo + 1, hi, w0);
-        if (clip && lo < hi && ld_col(a.b_col, hi - 1) >= w1) hi = lower_bound_col(a.b_col, lo, hi - 1, w1);
+        if (cur && cin) {
+            lo = (uint32_t)cin[t];
+            hi = gallop_col(a.b_col, lo, hi, w1);
+        } else {
+            if (clip && lo < hi && ld_col(a.b_col, lo) < w0) lo = lower_bound_col(a.b_col, lo + 1, hi, w0);
+            if (clip && lo < hi && ld_col(a.b_col, hi - 1) >= w1) hi = lower_bound_col(a.b_col, lo, hi - 1, w1);
+        }
+        if (cur) cout[t] = (int32_t)hi;
         if (NUM) a1 = CL ? a.cl_val[r.vbase + (q - r.it0) * r.s + r.l] : a.a_val[q];
     }
     const uint64_t ab = (uint64_t)__double_as_longlong(a1);
@@ -1238,7 +1263,8 @@ int64_t win_num_wave_bytes() { return WinNumLayout().bytes; }
 // with each other only).
 template <bool CL>
 __device__ __forceinline__ int num_window(const SpArgs &a, const WinRow &r, int w0, int w1, unsigned char *base,
-                                          int32_t *ccol, double *cval, int64_t room)
+                                          int32_t *ccol, double *cval, int64_t room, const int32_t *cin,
+                                          int32_t *cout)
 {
     constexpr int T = 1 << kWinNumLog2T, kR = 4, NB = kWinBuckets;
     const int lane = (int)__lane_id();
@@ -1279,7 +1305,7 @@ __device__ __forceinline__ int num_window(const SpArgs &a, const WinRow &r, int 
     int64_t q0 = r.it0;
     int off0 = 0;
     while (q0 < r.it1) {
-        const int E = load_round_win<true, CL>(a, r, q0, off0, items, sbits, w0, w1);
+        const int E = load_round_win<true, CL>(a, r, q0, off0, items, sbits, w0, w1, true, cin, cout);
         const int npass = (E + 63) >> 6;
         int cum = 0;
         for (int p = 0; p < npass; p += kR) {
@@ -1675,6 +1701,8 @@ __global__ void __launch_bounds__(64) k_num_win(SpArgs a)
     constexpr int64_t tk = (1 << kWinNumLog2T) * 5 / 8;
     const int lane = (int)__lane_id();
     const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
+    int32_t *const cur0 = a.win_cur ? a.win_cur + (size_t)blockIdx.x * (2 * kWinCurMax) : nullptr;
+    int32_t *const cur1 = cur0 ? cur0 + kWinCurMax : nullptr;
     for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
         const WinPair w = win_pair<CL>(a, i);
         if (w.u < a.unit_lo || w.u >= a.unit_hi) continue;
@@ -1710,14 +1738,21 @@ __global__ void __launch_bounds__(64) k_num_win(SpArgs a)
         }
         int64_t width = max<int64_t>(1, min<int64_t>(hi - lo, (hi - lo) * tk / kc));
         int64_t done = 0;
+        // the items' positions in B at the window start (none before the first
+        // window), and where they reach the window's end; swapped after each
+        // window that completes (a window redone narrower starts from the same)
+        int32_t *cin = nullptr, *cout = cur0;
         for (int w0 = lo; w0 < hi;) {
             const int w1 = (int)min<int64_t>(hi, w0 + width);
-            const int k = num_window<CL>(a, w.r, w0, w1, smem, a.c_col + off + done, a.c_val + off + done, kc - done);
+            const int k = num_window<CL>(a, w.r, w0, w1, smem, a.c_col + off + done, a.c_val + off + done, kc - done,
+                                         cin, cout);
             if (k == -1) {
                 width = max<int64_t>(1, (w1 - w0) / 2);
                 continue;
             }
             if (k < 0) break;
+            cin = cout;
+            cout = cout == cur0 ? cur1 : cur0;
             done += k;
             width = win_next(w1 - w0, k, tk, hi - lo);
             w0 = w1;

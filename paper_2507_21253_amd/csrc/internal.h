@@ -105,6 +105,11 @@ struct Workspace {
     int64_t *sym_base;
     int64_t *win_base;
     int64_t win_cap;
+    // per wavefront of the numeric window launch (win_cur_slots of them), two
+    // arrays of kWinCurMax positions in B (where each item's row of B reaches
+    // the next window)
+    int32_t *win_cur;
+    int64_t win_cur_slots;
     size_t bytes;
 };
 
@@ -181,6 +186,7 @@ struct SpArgs {
     int64_t *sym_base;
     int64_t *win_base;
     int64_t win_cap;
+    int32_t *win_cur;
     int win_log2;
     // batch launches: the products, their unit bases [nprob+1], the bin's
     // unit count and start in device memory, per-product error words
@@ -228,6 +234,9 @@ hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int block
 // persistent over the bin; a unit of ub products gets about ub / 2^win_log2
 // chunks per row
 constexpr int kWinChunksMax = 256;
+// items of a window row whose positions in B are carried from one window to
+// the next (later items are found by binary search in every window)
+constexpr int kWinCurMax = 1024;
 constexpr int kWinLog2Default = 16;
 __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
 {
