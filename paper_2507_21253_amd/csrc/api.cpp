@@ -725,8 +725,14 @@ static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, cons
         if (b == kNumGlobal) {
             HCSP_HIP(launch_win_prep(false, cluster, a, st));
             HCSP_HIP(launch_scan_exclusive(ws.win_base, c + 1, ws.scan_tmp, st));
-            // one wavefront per cursor slot of the workspace at most
-            HCSP_HIP(launch_num_win(cluster, a, (int)std::max<int64_t>(1, std::min(win_num_blocks(), ws.win_cur_slots)), st));
+            const int e = ensure_lds((size_t)num_bm_bytes(), tu.lds_budget);
+            if (e) return e;
+            // workgroups: as many as fit on the device, each wavefront with a
+            // slot of carried positions in the workspace
+            const int64_t per_cu = std::max<int64_t>(1, (160 * 1024) / num_bm_bytes());
+            const int64_t blocks = std::min<int64_t>(per_cu * cu_count(), ws.win_cur_slots / kBmWaves);
+            if (blocks < 1) return fail(HCSP_E_CAPACITY, "workspace has no room for the long rows' positions");
+            HCSP_HIP(launch_num_bm(cluster, a, (int)blocks, st));
             return HCSP_OK;
         }
         const int sc = (b - 1) / kNumT;

@@ -1474,7 +1474,6 @@ __device__ __forceinline__ WinPair win_pair(const SpArgs &a, int64_t i)
 // first pair -- and the row's total is added to its count (zeroed by the
 // binning kernel).
 constexpr int kBmLog2Bits = 20;  // columns per segment: a 128 KiB bitmap
-constexpr int kBmWaves = 8;
 constexpr int kBmWords = 1 << (kBmLog2Bits - 5);
 constexpr int kBmWaveBytes = 16 * 64 + 8 * kRoundPasses;  // a wavefront's item records and start bits
 
@@ -1524,11 +1523,129 @@ __device__ __forceinline__ void bm_locate(const SpArgs &a, const UnitView &v, in
     off0 = 0;
 }
 
+// A member row's column range [lo, hi] (the first and last columns of the
+// rows of B its items reach) and product count, reduced over the workgroup
+// (lo > hi for a row without products).  Contains a barrier.
+template <bool CL>
+__device__ __forceinline__ void bm_range(const SpArgs &a, const UnitView &v, int l, int *red, int64_t *psum, int &lo,
+                                         int &hi, int64_t &np)
+{
+    constexpr int NT = 64 * kBmWaves;
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)__lane_id();
+    lo = INT_MAX;
+    hi = -1;
+    np = 0;
+    for (int64_t q = v.it0 + threadIdx.x; q < v.it1; q += NT) {
+        if (CL && !((a.cl_mask[q] >> l) & 1u)) continue;
+        const int k = CL ? a.cl_col[q] : a.a_col[q];
+        const int64_t b0 = a.b_rp[k], b1 = a.b_rp[k + 1];
+        if (b1 > b0) {
+            lo = min(lo, ld_col(a.b_col, (uint32_t)b0));
+            hi = max(hi, ld_col(a.b_col, (uint32_t)(b1 - 1)));
+            np += b1 - b0;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+        np += __shfl_xor(np, o);
+    }
+    if (lane == 0) {
+        red[wave] = lo;
+        red[kBmWaves + wave] = hi;
+        psum[wave] = np;
+    }
+    __syncthreads();
+    np = 0;
+#pragma unroll
+    for (int w = 0; w < kBmWaves; ++w) {
+        lo = min(lo, red[w]);
+        hi = max(hi, red[kBmWaves + w]);
+        np += psum[w];
+    }
+    lo = uniform(lo);
+    hi = uniform(hi);
+    np = (int64_t)uniform64((uint64_t)np);
+}
+
+// Sets the bits of member row l's output columns inside the segment [w0, w1)
+// (bit x of bm: column w0 + x), clearing the segment's words first.  clip
+// false: the segment holds the row's whole range, and the row's np products
+// are cut into kBmWaves equal parts, one per wavefront; else the wavefronts
+// take the items 64 at a time from *next.  Starts and ends with a barrier.
+template <bool CL>
+__device__ __forceinline__ void bm_fill(const SpArgs &a, const UnitView &v, int l, int64_t np, int w0, int w1,
+                                        bool clip, uint32_t *bm, int *next, ItemRec *items, uint64_t *sbits)
+{
+    constexpr int kR = 8, NT = 64 * kBmWaves;
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)__lane_id();
+    const uint64_t le = lanemask_le(lane);
+    const int nw = (w1 - w0 + 31) >> 5;
+    const int m = (int)(v.it1 - v.it0);
+    for (int x = (int)threadIdx.x; x < ((nw + 3) >> 2); x += NT) ((uint4 *)bm)[x] = make_uint4(0u, 0u, 0u, 0u);
+    if (threadIdx.x == 0) *next = 0;
+    __syncthreads();
+    int64_t x0 = 0, x1 = INT64_MAX;
+    if (!clip) {
+        x0 = np * wave / kBmWaves;
+        x1 = np * (wave + 1) / kBmWaves;
+    }
+    for (;;) {
+        int64_t q0;
+        int off0 = 0;
+        WinRow r{v.it0, v.it1, v.vbase, l, v.s};
+        if (clip) {
+            int g = 0;
+            if (lane == 0) g = atomicAdd(next, 64);
+            g = uniform(__shfl(g, 0));
+            if (g >= m) break;
+            r.it0 = v.it0 + g;
+            r.it1 = min(v.it1, v.it0 + g + 64);
+            q0 = r.it0;
+        } else {
+            if (x0 >= x1) break;
+            bm_locate<CL>(a, v, l, x0, q0, off0);
+            q0 = (int64_t)uniform64((uint64_t)q0);
+            off0 = uniform(off0);
+        }
+        int64_t rem = x1 - x0;
+        while (q0 < r.it1 && rem > 0) {
+            const int E =
+                (int)min<int64_t>(load_round_win<false, CL>(a, r, q0, off0, items, sbits, w0, w1, clip), rem);
+            rem -= E;
+            const int npass = (E + 63) >> 6;
+            int cum = 0;
+            for (int p = 0; p < npass; p += kR) {
+                Pass<false, false> d[kR];
+#pragma unroll
+                for (int rr = 0; rr < kR; ++rr) {
+                    if (p + rr < npass) {
+                        const uint64_t w = uniform64(sbits[p + rr]);
+                        d[rr] = fetch_pass<false, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                        cum += __popcll(w);
+                    } else {
+                        d[rr].j = kDummyKey;
+                    }
+                }
+#pragma unroll
+                for (int rr = 0; rr < kR; ++rr) {
+                    if (d[rr].j != kDummyKey) {
+                        const uint32_t x = (uint32_t)(d[rr].j - w0);
+                        atomicOr(&bm[x >> 5], 1u << (x & 31u));
+                    }
+                }
+            }
+        }
+        if (!clip) break;
+    }
+    __syncthreads();
+}
+
 template <bool CL>
 __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int kR = 8, NT = 64 * kBmWaves;
+    constexpr int NT = 64 * kBmWaves;
     const BmLayout L;
     uint32_t *bm = (uint32_t *)(smem + L.bm);
     int *ccnt = (int *)(smem + L.ccnt);
@@ -1538,7 +1655,6 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
     const int wave = (int)(threadIdx.x >> 6), lane = (int)__lane_id();
     ItemRec *items = (ItemRec *)(smem + L.waves + wave * kBmWaveBytes);
     uint64_t *sbits = (uint64_t *)(smem + L.waves + wave * kBmWaveBytes + 16 * 64);
-    const uint64_t le = lanemask_le(lane);
     for (int64_t i = xcd_block(); i < a.count; i += gridDim.x) {
         const int u = uniform(a.order[a.bin_begin + i]);
         const UnitView v = unit_view<CL>(a, u);
@@ -1546,105 +1662,16 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
         const int nch = (int)(((int64_t)uniform64((uint64_t)a.win_base[i + 1]) - first) / v.s);
         const bool room = first + (int64_t)v.s * nch <= a.win_cap;
         const int64_t cw = (a.ncols + nch - 1) / nch;  // chunk width (win_chunk)
-        const int m = (int)(v.it1 - v.it0);
         for (int l = 0; l < v.s; ++l) {
-            int lo = INT_MAX, hi = -1;
-            int64_t np = 0;  // the row's products
-            for (int64_t q = v.it0 + threadIdx.x; q < v.it1; q += NT) {
-                if (CL && !((a.cl_mask[q] >> l) & 1u)) continue;
-                const int k = CL ? a.cl_col[q] : a.a_col[q];
-                const int64_t b0 = a.b_rp[k], b1 = a.b_rp[k + 1];
-                if (b1 > b0) {
-                    lo = min(lo, ld_col(a.b_col, (uint32_t)b0));
-                    hi = max(hi, ld_col(a.b_col, (uint32_t)(b1 - 1)));
-                    np += b1 - b0;
-                }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                lo = min(lo, __shfl_xor(lo, o));
-                hi = max(hi, __shfl_xor(hi, o));
-                np += __shfl_xor(np, o);
-            }
-            if (lane == 0) {
-                red[wave] = lo;
-                red[kBmWaves + wave] = hi;
-                psum[wave] = np;
-            }
             for (int c = (int)threadIdx.x; c < nch; c += NT) ccnt[c] = 0;
-            __syncthreads();
-            np = 0;
-#pragma unroll
-            for (int w = 0; w < kBmWaves; ++w) {
-                lo = min(lo, red[w]);
-                hi = max(hi, red[kBmWaves + w]);
-                np += psum[w];
-            }
-            lo = uniform(lo);
-            hi = uniform(hi);
-            np = (int64_t)uniform64((uint64_t)np);
+            int lo, hi;
+            int64_t np;
+            bm_range<CL>(a, v, l, red, psum, lo, hi, np);
             for (int64_t g0 = lo; g0 <= (int64_t)hi; g0 += (int64_t)1 << kBmLog2Bits) {
                 const int w0 = (int)g0;
                 const int w1 = (int)min<int64_t>((int64_t)hi + 1, g0 + ((int64_t)1 << kBmLog2Bits));
                 const int nw = (w1 - w0 + 31) >> 5;
-                const bool clip = g0 > lo || w1 <= hi;  // not the whole range in one segment
-                for (int x = (int)threadIdx.x; x < ((nw + 3) >> 2); x += NT) ((uint4 *)bm)[x] = make_uint4(0u, 0u, 0u, 0u);
-                if (threadIdx.x == 0) *next = 0;
-                __syncthreads();
-                // whole range: products [x0, x1) of the flattened list; else item groups
-                int64_t x0 = 0, x1 = INT64_MAX;
-                if (!clip) {
-                    x0 = np * wave / kBmWaves;
-                    x1 = np * (wave + 1) / kBmWaves;
-                }
-                for (;;) {
-                    int64_t q0;
-                    int off0 = 0;
-                    WinRow r{v.it0, v.it1, v.vbase, l, v.s};
-                    if (clip) {
-                        int g = 0;
-                        if (lane == 0) g = atomicAdd(next, 64);
-                        g = uniform(__shfl(g, 0));
-                        if (g >= m) break;
-                        r.it0 = v.it0 + g;
-                        r.it1 = min(v.it1, v.it0 + g + 64);
-                        q0 = r.it0;
-                    } else {
-                        if (x0 >= x1) break;
-                        bm_locate<CL>(a, v, l, x0, q0, off0);
-                        q0 = (int64_t)uniform64((uint64_t)q0);
-                        off0 = uniform(off0);
-                    }
-                    int64_t rem = x1 - x0;
-                    while (q0 < r.it1 && rem > 0) {
-                        const int E = (int)min<int64_t>(
-                            load_round_win<false, CL>(a, r, q0, off0, items, sbits, w0, w1, clip), rem);
-                        rem -= E;
-                        const int npass = (E + 63) >> 6;
-                        int cum = 0;
-                        for (int p = 0; p < npass; p += kR) {
-                            Pass<false, false> d[kR];
-#pragma unroll
-                            for (int rr = 0; rr < kR; ++rr) {
-                                if (p + rr < npass) {
-                                    const uint64_t w = uniform64(sbits[p + rr]);
-                                    d[rr] = fetch_pass<false, false>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
-                                    cum += __popcll(w);
-                                } else {
-                                    d[rr].j = kDummyKey;
-                                }
-                            }
-#pragma unroll
-                            for (int rr = 0; rr < kR; ++rr) {
-                                if (d[rr].j != kDummyKey) {
-                                    const uint32_t x = (uint32_t)(d[rr].j - w0);
-                                    atomicOr(&bm[x >> 5], 1u << (x & 31u));
-                                }
-                            }
-                        }
-                    }
-                    if (!clip) break;
-                }
-                __syncthreads();
+                bm_fill<CL>(a, v, l, np, w0, w1, g0 > lo || w1 <= hi, bm, next, items, sbits);
                 // count the bits per chunk: a wavefront's 64 words usually lie in one chunk
                 for (int x0 = wave * 64; x0 < nw; x0 += NT) {
                     const int wd = x0 + lane;
@@ -1687,6 +1714,272 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
             if (!room) atomicOr(a.err, kErrWindows);
             a.ucount[u] = INT32_MAX;
             a.sym_base[u] = first;
+        }
+    }
+}
+
+// Numeric phase of the units too long for shared-memory tables: one
+// workgroup of kBmWaves wavefronts per (member row, column chunk) of the
+// symbolic phase (the chunk's entries follow those of the chunks before it;
+// a row the shared-memory symbolic phase counted whole is one task).  The
+// task's columns are taken in segments of 2^kNbLog2Bits columns; for
+// each, the row's output columns are first set in a bitmap (as in the
+// symbolic phase), whose keys are then shared out between the wavefronts in
+// equal parts of whole words.  A wavefront takes its words in windows of at
+// most kNbK keys and kNbSpan words: a key's slot in the window's values is its
+// rank, the keys before it in the window (a per-word prefix plus a popcount),
+// so there is no probing, no table that can fill and no sort -- the values
+// come out in column order, and the columns are read off the bitmap.  The
+// window's products are walked as on the window path (items in ascending k,
+// 64-product passes, each item's entries applied in turn, positions in B
+// carried from one window to the next), so every output entry still receives
+// its products in ascending k, one fma each from +0.0.
+constexpr int kNbLog2Bits = 19;  // columns per segment: a 64 KiB bitmap
+constexpr int kNbWords = 1 << (kNbLog2Bits - 5);
+constexpr int kNbK = 1024;       // keys per window at most (a value each)
+constexpr int kNbSpan = 512;     // words per window at most
+constexpr int kNbValBytes = (8 * (kNbK + 1) + 15) & ~15;
+constexpr int kNbPreBytes = (2 * (kNbSpan + 1) + 15) & ~15;
+constexpr int kNbWaveBytes = kNbValBytes + kNbPreBytes + 16 * 64 + 8 * kRoundPasses;
+
+struct NbLayout {
+    int bm, tpre, red, psum, next, waves, bytes;
+    __host__ __device__ NbLayout()
+    {
+        bm = 0;
+        tpre = 4 * kNbWords;                // per-thread key prefix [64 * kBmWaves]
+        red = tpre + 4 * 64 * kBmWaves;     // per-wavefront partial lo/hi, then key sums
+        psum = red + 8 * kBmWaves;          // per-wavefront partial product counts
+        next = psum + 8 * kBmWaves;         // the next item group to take
+        waves = align16(next + 4);
+        bytes = waves + kBmWaves * kNbWaveBytes;
+    }
+};
+
+int64_t num_bm_bytes() { return NbLayout().bytes; }
+
+// The smallest word W in [0, nw] whose key prefix P(W) (keys of the segment
+// before word W) is at least x, and P(W).  tpre[t]: keys before thread t's
+// words [t*wpt, (t+1)*wpt); total: keys of the segment.  Whole wavefront.
+__device__ __forceinline__ void nb_split(const uint32_t *bm, const int *tpre, int wpt, int nw, int total, int x,
+                                         int &W, int &PW)
+{
+    constexpr int NT = 64 * kBmWaves;
+    const int lane = (int)__lane_id();
+    int below = 0;  // threads whose words start below the prefix x
+    for (int t = lane; t < NT; t += 64) below += tpre[t] < x;
+    for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
+    below = uniform(below);
+    if (below == 0) {
+        W = 0;
+        PW = 0;
+        return;
+    }
+    const int T = below - 1;
+    const int wd = T * wpt + lane;
+    const bool valid = lane < wpt && wd < nw;
+    const int pc = valid ? __popc(bm[wd]) : 0;
+    const int P = tpre[T] + wave_incl_scan(pc) - pc;
+    const uint64_t q = __ballot(valid && P >= x);
+    if (q) {
+        const int L = __ffsll((unsigned long long)q) - 1;
+        W = T * wpt + L;
+        PW = uniform(__shfl(P, L));
+    } else {
+        W = min(nw, (T + 1) * wpt);
+        PW = T + 1 < NT ? tpre[T + 1] : total;
+    }
+}
+
+template <bool CL>
+__global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NT = 64 * kBmWaves, kR = 4;
+    const NbLayout L;
+    uint32_t *bm = (uint32_t *)(smem + L.bm);
+    int *tpre = (int *)(smem + L.tpre);
+    int *red = (int *)(smem + L.red);
+    int64_t *psum = (int64_t *)(smem + L.psum);
+    int *next = (int *)(smem + L.next);
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)__lane_id();
+    unsigned char *wb = smem + L.waves + wave * kNbWaveBytes;
+    double *vals = (double *)wb;
+    uint16_t *lpre = (uint16_t *)(wb + kNbValBytes);
+    ItemRec *items = (ItemRec *)(wb + kNbValBytes + kNbPreBytes);
+    uint64_t *sbits = (uint64_t *)(wb + kNbValBytes + kNbPreBytes + 16 * 64);
+    const uint64_t le = lanemask_le(lane);
+    int32_t *const cur0 = a.win_cur ? a.win_cur + ((size_t)blockIdx.x * kBmWaves + wave) * (2 * kWinCurMax) : nullptr;
+    int32_t *const cur1 = cur0 ? cur0 + kWinCurMax : nullptr;
+    const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
+    for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
+        const WinPair w = win_pair<CL>(a, i);
+        if (w.u < a.unit_lo || w.u >= a.unit_hi) continue;
+        const int u = w.u, l = w.r.l;
+        const UnitView v = unit_view<CL>(a, u);
+        {
+            const int64_t row = w.row;
+            // this task's columns [clo, chi), its first entry in C and its entries
+            int64_t off = (int64_t)uniform64((uint64_t)a.c_rp[row]) - a.out_base, cnt;
+            int clo, chi;
+            if (uniform(a.ucount[u]) == INT32_MAX) {
+                win_chunk(a.ncols, w.nch, w.c, &clo, &chi);
+                const int64_t cb = (int64_t)uniform64((uint64_t)a.sym_base[u]) + (int64_t)l * w.nch;
+                if (cb < 0 || cb + w.nch > a.win_cap) {
+                    if (threadIdx.x == 0) atomicOr(a.err, kErrWindows);
+                    continue;
+                }
+                const int32_t *cc = a.chunk_cnt + cb;
+                int64_t before = 0;
+                for (int x = lane; x < w.c; x += 64) before += cc[x];
+                for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o);
+                off += (int64_t)uniform64((uint64_t)before);
+                cnt = uniform(cc[w.c]);
+            } else {
+                clo = 0;
+                chi = (int)a.ncols;
+                cnt = (int64_t)uniform64((uint64_t)a.c_rp[row + 1]) - (off + a.out_base);
+            }
+            if (cnt <= 0) continue;
+            if (off < 0 || off + cnt > a.cap) {
+                if (threadIdx.x == 0) atomicOr(a.err, kErrCapacity);
+                continue;
+            }
+            int rlo, rhi;
+            int64_t np;
+            bm_range<CL>(a, v, l, red, psum, rlo, rhi, np);
+            // the row's columns inside the task's; one segment over all of the
+            // row's products needs no clipping
+            const int lo = max(rlo, clo), hi = min(rhi, chi - 1);
+            int64_t done = 0;  // keys of the segments before
+            for (int64_t g0 = lo; g0 <= (int64_t)hi; g0 += (int64_t)1 << kNbLog2Bits) {
+                const int w0 = (int)g0;
+                const int w1 = (int)min<int64_t>((int64_t)hi + 1, g0 + ((int64_t)1 << kNbLog2Bits));
+                const int nw = (w1 - w0 + 31) >> 5;
+                bm_fill<CL>(a, v, l, np, w0, w1, w0 > rlo || w1 <= rhi, bm, next, items, sbits);
+                // keys per thread's words, and their exclusive prefix over the workgroup
+                const int wpt = (nw + NT - 1) / NT;
+                int mine = 0;
+                for (int x = (int)threadIdx.x * wpt; x < min(nw, ((int)threadIdx.x + 1) * wpt); ++x) mine += __popc(bm[x]);
+                const int incl = wave_incl_scan(mine);
+                if (lane == 63) red[wave] = incl;
+                __syncthreads();
+                int before = 0, total = 0;
+#pragma unroll
+                for (int w = 0; w < kBmWaves; ++w) {
+                    const int rw = red[w];
+                    before += w < wave ? rw : 0;
+                    total += rw;
+                }
+                total = uniform(total);
+                tpre[threadIdx.x] = before + incl - mine;
+                __syncthreads();
+                if (done + total > cnt) {  // more keys than the symbolic phase counted
+                    if (threadIdx.x == 0) atomicOr(a.err, kErrCount);
+                    done = cnt + 1;
+                    break;
+                }
+                // this wavefront's words [wa, we) and the keys before wa
+                int wa, pa, we, pe;
+                nb_split(bm, tpre, wpt, nw, total, (int)((int64_t)total * wave / kBmWaves), wa, pa);
+                if (wave + 1 < kBmWaves) {
+                    nb_split(bm, tpre, wpt, nw, total, (int)((int64_t)total * (wave + 1) / kBmWaves), we, pe);
+                } else {
+                    we = nw;
+                    pe = total;
+                }
+                const WinRow r{v.it0, v.it1, v.vbase, l, v.s};
+                const int32_t *cin = nullptr;
+                int32_t *cout = cur0;
+                int pos = pa;
+                for (int a0 = wa; a0 < we;) {
+                    // the window: words [a0, b0) holding nk <= kNbK keys, their prefix in lpre
+                    int nk = 0, b0 = a0;
+                    for (;;) {
+                        const int wd = b0 + lane;
+                        const bool valid = wd < we && wd - a0 < kNbSpan;
+                        const int pc = valid ? __popc(bm[wd]) : 0;
+                        const int inc = wave_incl_scan(pc);
+                        const bool fits = valid && nk + inc <= kNbK;
+                        if (fits) lpre[wd - a0] = (uint16_t)(nk + inc - pc);
+                        const int nf = __popcll(__ballot(fits));
+                        if (nf == 0) break;
+                        nk += __shfl(inc, nf - 1);
+                        b0 += nf;
+                        if (nf < 64) break;
+                    }
+                    nk = uniform(nk);
+                    b0 = uniform(b0);
+                    if (lane == 0) lpre[b0 - a0] = (uint16_t)nk;
+                    for (int x = lane; x < nk; x += 64) vals[x] = 0.0;
+                    if (lane == 0) vals[kNbK] = 0.0;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    const int c0 = w0 + 32 * a0, c1 = min(w1, w0 + 32 * b0);
+                    auto apply = [&](const Pass<false, true> &d, int h, int tf, int tl) {
+                        for (int tt = tf; tt <= tl; ++tt) {
+                            if (d.t != tt) continue;
+                            const double av = *(const double *)&items[tt].x;
+                            vals[h] = __fma_rn(av, d.b, vals[h]);
+                        }
+                    };
+                    int64_t q0 = v.it0;
+                    int off0 = 0;
+                    while (q0 < v.it1) {
+                        const int E = load_round_win<true, CL>(a, r, q0, off0, items, sbits, c0, c1, true, cin, cout);
+                        const int npass = (E + 63) >> 6;
+                        int cum = 0;
+                        for (int p = 0; p < npass; p += kR) {
+                            Pass<false, true> d[kR];
+                            int tf[kR], tl[kR], h[kR];
+#pragma unroll
+                            for (int rr = 0; rr < kR; ++rr) {
+                                if (p + rr < npass) {
+                                    const uint64_t w = uniform64(sbits[p + rr]);
+                                    const int last = min(63, E - 1 - ((p + rr) << 6));
+                                    tf[rr] = cum + (int)(w & 1ull) - 1;
+                                    tl[rr] = cum + __popcll(w & lanemask_le(last)) - 1;
+                                    d[rr] = fetch_pass<false, true>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
+                                    cum += __popcll(w);
+                                }
+                            }
+#pragma unroll
+                            for (int rr = 0; rr < kR; ++rr) {
+                                if (p + rr < npass) {
+                                    h[rr] = kNbK;
+                                    if (d[rr].j != kDummyKey) {
+                                        const uint32_t x = (uint32_t)(d[rr].j - c0);
+                                        const int wd = (int)(x >> 5);
+                                        h[rr] = (int)lpre[wd] + __popc(bm[a0 + wd] & ((1u << (x & 31u)) - 1u));
+                                    }
+                                    apply(d[rr], h[rr], tf[rr], tl[rr]);
+                                }
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    // the window's entries: values in rank order, columns off the bitmap
+                    const int64_t base = off + done + pos;
+                    for (int x = lane; x < nk; x += 64) a.c_val[base + x] = vals[x];
+                    for (int t = lane; t < b0 - a0; t += 64) {
+                        uint32_t bits = bm[a0 + t];
+                        int pr = lpre[t];
+                        while (bits) {
+                            a.c_col[base + pr] = c0 + 32 * t + (__ffs((int)bits) - 1);
+                            ++pr;
+                            bits &= bits - 1u;
+                        }
+                    }
+                    cin = cout;
+                    cout = cout == cur0 ? cur1 : cur0;
+                    pos += nk;
+                    a0 = b0;
+                }
+                (void)pe;
+                __syncthreads();
+                done += total;
+            }
+            if (threadIdx.x == 0 && done != cnt) atomicOr(a.err, kErrCount);
+            __syncthreads();
         }
     }
 }
@@ -1776,6 +2069,14 @@ hipError_t launch_sym_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t 
     const dim3 g(blocks), t(64 * kBmWaves);
     if (cluster) hipLaunchKernelGGL(k_sym_bm<true>, g, t, (size_t)sym_bm_bytes(), s, a);
     else hipLaunchKernelGGL(k_sym_bm<false>, g, t, (size_t)sym_bm_bytes(), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_num_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
+{
+    const dim3 g(blocks), t(64 * kBmWaves);
+    if (cluster) hipLaunchKernelGGL(k_num_bm<true>, g, t, (size_t)num_bm_bytes(), s, a);
+    else hipLaunchKernelGGL(k_num_bm<false>, g, t, (size_t)num_bm_bytes(), s, a);
     return hipGetLastError();
 }
 

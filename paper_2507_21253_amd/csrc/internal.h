@@ -237,6 +237,8 @@ constexpr int kWinChunksMax = 256;
 // items of a window row whose positions in B are carried from one window to
 // the next (later items are found by binary search in every window)
 constexpr int kWinCurMax = 1024;
+// wavefronts of a workgroup of the bitmap kernels (one unit per workgroup)
+constexpr int kBmWaves = 8;
 constexpr int kWinLog2Default = 16;
 __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
 {
@@ -245,8 +247,10 @@ __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
 }
 hipError_t launch_win_prep(bool sym, bool cluster, const SpArgs &a, hipStream_t s);
 int64_t sym_bm_bytes();
+int64_t num_bm_bytes();
 int64_t win_num_wave_bytes();
 hipError_t launch_sym_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
+hipError_t launch_num_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
 hipError_t launch_num_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
 
 // launchers (util.hip)
