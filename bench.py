@@ -82,6 +82,9 @@ def parse():
     p.add_argument("--rmat-cluster-scale", type=int, default=18,
                    help="rmat: scale of the plain vs clustered comparison (C held whole)")
     p.add_argument("--panel-gb", type=float, default=32.0, help="rmat: C panel buffer size")
+    p.add_argument("--win-chunk-log2", type=int, default=0,
+                   help="rmat: log2 of the products per column chunk of rows too long for shared memory "
+                        "(0: the library default)")
     p.add_argument("--load-pct", type=int, default=0, help="numeric table fill target (0: autotuned)")
     p.add_argument("--sym-load-pct", type=int, default=0, help="symbolic table fill bound (0: autotuned)")
     p.add_argument("--untuned", action="store_true", help="ignore the autotuner's table")
@@ -216,13 +219,14 @@ def tallskinny_mode(args):
            "per_iteration": rows}
     print(json.dumps(out), flush=True)
 
-def rmat_panels(D, hc, torch, panel_entries, steps, warmup):
+def rmat_panels(D, hc, torch, panel_entries, steps, warmup, wlog2=0):
     """C = A*A for an A too large to hold C: symbolic over all rows, C's row offsets read back, then the
     numeric phase in row panels of at most panel_entries entries written one after another into one
     reused buffer.  Returns (ms per product, symbolic ms, numeric ms, nnz(C), panels)."""
-    ws = torch.empty(hc.spgemm_workspace(D, D), dtype=torch.uint8, device="cuda")
+    o = hc.opts(win_chunk_log2=wlog2)
+    ws = torch.empty(hc.spgemm_workspace(D, D, o), dtype=torch.uint8, device="cuda")
     crp = torch.empty(D.nrows + 1, dtype=torch.int64, device="cuda")
-    info = hc.spgemm_symbolic(D, D, crp, ws)
+    info = hc.spgemm_symbolic(D, D, crp, ws, o)
     nnz = int(info.nnz)
     cap = int(min(panel_entries, max(nnz, 1)))
     col = torch.empty(cap, dtype=torch.int32, device="cuda")
@@ -230,7 +234,7 @@ def rmat_panels(D, hc, torch, panel_entries, steps, warmup):
 
     def one():
         t0 = time.perf_counter()
-        inf = hc.spgemm_symbolic(D, D, crp, ws)
+        inf = hc.spgemm_symbolic(D, D, crp, ws, o)
         rp = crp.cpu().numpy()
         t1 = time.perf_counter()
         lo, np_ = 0, 0
@@ -239,7 +243,8 @@ def rmat_panels(D, hc, torch, panel_entries, steps, warmup):
             hi = max(hi, lo + 1)
             if rp[hi] - rp[lo] > cap:
                 raise RuntimeError("row %d alone exceeds the panel buffer" % lo)
-            hc.spgemm_numeric(D, D, inf, crp, col, val, ws, hc.opts(unit_lo=lo, unit_hi=hi, out_base=int(rp[lo])),
+            hc.spgemm_numeric(D, D, inf, crp, col, val, ws,
+                              hc.opts(unit_lo=lo, unit_hi=hi, out_base=int(rp[lo]), win_chunk_log2=wlog2),
                               capacity=cap)
             lo, np_ = hi, np_ + 1
         torch.cuda.synchronize()
@@ -271,7 +276,7 @@ def rmat_mode(args):
     D = hc.DeviceCSR.from_host(R)
     panel_entries = int(args.panel_gb * 1e9 / 12)
     ms, sym, num, nnz, npan = rmat_panels(D, hc, torch, panel_entries, max(1, min(args.steps, 3)),
-                                          min(args.warmup, 1))
+                                          min(args.warmup, 1), args.win_chunk_log2)
     log("rmat%d: %d rows, nnz %d, products %d, nnz(C) %d: %.1f ms (symbolic %.1f, numeric %.1f in %d panels)"
         % (args.rmat_scale, R.nrows, R.nnz, products, nnz, ms, sym, num, npan))
     out.update({"metric": "SpGEMM GFLOP/s, R-MAT C = A*A (numeric in row panels)",
@@ -280,7 +285,8 @@ def rmat_mode(args):
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
                 "data": "synthetic",
                 "config": {"workload": "rmat%d_ef16_A2" % args.rmat_scale, "nrows": R.nrows, "nnz_A": R.nnz,
-                           "products": products, "nnz_C": nnz, "panels": npan, "panel_gb": args.panel_gb},
+                           "products": products, "nnz_C": nnz, "panels": npan, "panel_gb": args.panel_gb,
+                           "win_chunk_log2": args.win_chunk_log2 or None},
                 "phases_ms": {"symbolic_incl_readback": round(sym, 2), "numeric_all_panels": round(num, 2)}})
     del D
     torch.cuda.empty_cache()
@@ -290,7 +296,8 @@ def rmat_mode(args):
     rl = np.diff(R.rp)
     products = int(rl[R.col].sum())
     D = hc.DeviceCSR.from_host(R)
-    P = hc.Product(D, D)
+    ow = hc.opts(win_chunk_log2=args.win_chunk_log2)
+    P = hc.Product(D, D, ow)
     w_pl, s_pl, n_pl = time_product(P, max(1, min(args.steps, 3)), 1, torch)
     nnz = P.info.nnz
     ref_rp, ref_col = P.C_row_ptr.clone(), P.C_col[:nnz].clone()
@@ -303,7 +310,7 @@ def rmat_mode(args):
     plan = hc.plan_hierarchical_gpu(R, D, (3, 10), mc, hc.SIM_ROOT, perm_in=perm)
     t_prep = time.perf_counter() - t
     Dc = hc.cluster_build(D, plan)
-    Pc = hc.Product(Dc, D)
+    Pc = hc.Product(Dc, D, ow)
     w_cl, s_cl, n_cl = time_product(Pc, max(1, min(args.steps, 3)), 1, torch)
     same = bool(Pc.info.nnz == nnz and torch.equal(Pc.C_row_ptr, ref_rp) and torch.equal(Pc.C_col[:nnz], ref_col)
                 and torch.equal(Pc.C_val[:nnz].view(torch.int64), ref_val))

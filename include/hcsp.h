@@ -139,8 +139,9 @@ typedef struct hcsp_opts {
     int32_t sym_load_pct;   /* symbolic tables get >= products*100/sym_load_pct slots (products: the
                                unit's upper bound on distinct columns), 10..100: 0 = default (70) */
     int32_t win_chunk_log2; /* rows of units too long for shared memory (single products) are cut into
-                               about products / 2^this column chunks (1..256), one wavefront each:
-                               0 = default (16), else 4..30; the numeric call must use the symbolic
+                               about products / 2^this column chunks (1..256), counted per chunk by the
+                               symbolic phase and computed one workgroup per chunk by the numeric phase:
+                               0 = default (18), else 4..30; the numeric call must use the symbolic
                                call's value */
 } hcsp_opts;
 

@@ -24,7 +24,7 @@ int fail(int code, const std::string &msg)
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-static int64_t win_num_blocks();
+static int64_t num_bm_blocks();
 
 size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, bool windows, char *base,
                         Workspace *ws)
@@ -60,7 +60,7 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->chunk_cnt = (int32_t *)take(4 * (size_t)ws->win_cap);
     ws->sym_base = (int64_t *)take(windows ? 8 * nu : 0);
     ws->win_base = (int64_t *)take(windows ? 8 * (nu + 1) : 0);
-    ws->win_cur_slots = windows ? win_num_blocks() : 0;
+    ws->win_cur_slots = windows ? num_bm_blocks() * kBmWaves : 0;
     ws->win_cur = (int32_t *)take(4 * 2 * (size_t)kWinCurMax * (size_t)ws->win_cur_slots);
     ws->bytes = align_up(off, 256);
     return ws->bytes;
@@ -361,16 +361,12 @@ static void geometry(int64_t wave_bytes, int64_t count, int *blocks, int *thread
     *blocks = (int)((count + wpb - 1) / wpb);
 }
 
-// Blocks (one wavefront each) of a column-window launch: as many as the
-// compute units hold at once (the (row, chunk) pairs are counted on the GPU).
-static int win_blocks(int64_t wave_bytes)
+// Workgroups of a numeric launch over rows too long for shared memory (as
+// many as fit on the device).
+static int64_t num_bm_blocks()
 {
-    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(32, (160 * 1024) / std::max<int64_t>(wave_bytes, 1)));
-    return (int)(per_cu * cu_count());
+    return std::max<int64_t>(1, (160 * 1024) / num_bm_bytes()) * cu_count();
 }
-
-// Wavefronts (one-wavefront blocks) of a numeric window launch.
-static int64_t win_num_blocks() { return win_blocks(win_num_wave_bytes()); }
 
 static int ensure_lds(size_t lds, int64_t budget)
 {
@@ -729,8 +725,7 @@ static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, cons
             if (e) return e;
             // workgroups: as many as fit on the device, each wavefront with a
             // slot of carried positions in the workspace
-            const int64_t per_cu = std::max<int64_t>(1, (160 * 1024) / num_bm_bytes());
-            const int64_t blocks = std::min<int64_t>(per_cu * cu_count(), ws.win_cur_slots / kBmWaves);
+            const int64_t blocks = std::min<int64_t>(num_bm_blocks(), ws.win_cur_slots / kBmWaves);
             if (blocks < 1) return fail(HCSP_E_CAPACITY, "workspace has no room for the long rows' positions");
             HCSP_HIP(launch_num_bm(cluster, a, (int)blocks, st));
             return HCSP_OK;

@@ -1148,19 +1148,17 @@ hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int block
 
 // ================================================================ column windows
 // Units of a single product whose tables do not fit in shared memory: their
-// rows (a CSR row, or each member row of a cluster) are taken one by one.  A
-// row's output columns are cut into chunks of equal column range (more for
-// units with more products, win_nchunks), and each chunk into windows
-// [w0, w1) that one wavefront takes one after another with a shared-memory
-// table.  A window's products are the entries of the rows of
-// B that fall inside it (found by binary search, the rows of B being sorted),
-// walked in ascending k as everywhere else, so every output entry still
-// receives its products in ascending k, one fma each from +0.0.  Window widths
-// follow the density of output columns seen so far; a window whose keys do
-// not fit is redone at half the width (a window of one column always fits).
-// The chunks of a row run on different wavefronts (neighbouring blocks, one
-// XCD): the symbolic phase counts each chunk's columns, and the numeric phase
-// writes a chunk's entries after those of the chunks before it.
+// rows (a CSR row, or each member row of a cluster) are taken one by one, a
+// workgroup each, and their output columns are held in a bitmap in shared
+// memory.  The symbolic phase counts a row's columns per column chunk (equal
+// column ranges, more for units with more products, win_nchunks); the
+// numeric phase takes one chunk per workgroup and writes its entries after
+// those of the chunks before it, in windows of the chunk's columns.  A
+// window's products are the entries of the rows of B that fall inside it
+// (found by binary search or carried over from the window before, the rows
+// of B being sorted), walked in ascending k as everywhere else, so every
+// output entry still receives its products in ascending k, one fma each
+// from +0.0.
 
 // First position in [lo, hi) of B's columns whose column is >= x (hi if none).
 __device__ __forceinline__ uint32_t lower_bound_col(const int32_t *col, uint32_t lo, uint32_t hi, int x)
@@ -1230,146 +1228,6 @@ __device__ __forceinline__ int load_round_win(const SpArgs &a, const WinRow &r, 
     return flatten_round(r.it1, q0, off0, items, sbits, lo, (int)(hi - lo), (uint32_t)ab, (uint32_t)(ab >> 32));
 }
 
-// Numeric window table size (slots, a power of two, keys and values); a
-// window aims at 5/8 of a table of keys.
-constexpr int kWinNumLog2T = 10;
-constexpr int kWinBuckets = 1 << (kWinNumLog2T - 1);  // rank buckets of a numeric window
-
-// Numeric window layout: the table (keys, values, a dummy slot each), the
-// rank buckets (bucket ends, then starts) and the keys in bucket order.
-struct WinNumLayout {
-    int keys, vals, bend, arr, items, sbits, bytes;
-    __host__ __device__ WinNumLayout()
-    {
-        constexpr int T = 1 << kWinNumLog2T;
-        keys = 0;
-        vals = align16(4 * (T + 1));
-        bend = align16(vals + 8 * (T + 1));
-        arr = align16(bend + 4 * (kWinBuckets + 1));
-        items = align16(arr + 4 * T);
-        sbits = items + 16 * 64;
-        bytes = align16(sbits + 8 * kRoundPasses);
-    }
-};
-
-int64_t win_num_wave_bytes() { return WinNumLayout().bytes; }
-
-// Entries of window row r of C inside [w0, w1), written in column order to
-// ccol/cval; returns their number, -1 when the table got too full
-// for another batch of passes (window too wide, nothing written) or -2 when
-// there are more than room of them (nothing written).  Keys are placed by a
-// multiplicative hash; their ranks come from a counting sort over
-// kWinBuckets buckets of equal column range (a bucket's keys are compared
-// with each other only).
-template <bool CL>
-__device__ __forceinline__ int num_window(const SpArgs &a, const WinRow &r, int w0, int w1, unsigned char *base,
-                                          int32_t *ccol, double *cval, int64_t room, const int32_t *cin,
-                                          int32_t *cout)
-{
-    constexpr int T = 1 << kWinNumLog2T, kR = 4, NB = kWinBuckets;
-    const int lane = (int)__lane_id();
-    const WinNumLayout L;
-    int *keys = (int *)(base + L.keys);
-    double *vals = (double *)(base + L.vals);
-    int *bend = (int *)(base + L.bend);
-    int *arr = (int *)(base + L.arr);
-    ItemRec *items = (ItemRec *)(base + L.items);
-    uint64_t *sbits = (uint64_t *)(base + L.sbits);
-    lds_fill(keys, 4 * T, (uint32_t)kEmpty);
-    lds_fill(vals, 8 * T, 0u);
-    if (lane == 0) {
-        keys[T] = kDummyKey;
-        vals[T] = 0.0;
-    }
-    const uint64_t le = lanemask_le(lane);
-    int total = 0;  // keys in the table (wave-uniform)
-    // every probe finds a free slot while at most T - 1 keys are in
-    // (idle lanes confirm the dummy key in the dummy slot)
-    auto probe = [&](int j) -> int {
-        uint32_t h = j == kDummyKey ? (uint32_t)T : ((uint32_t)j * 2654435761u) >> (32 - kWinNumLog2T);
-        int old = atomicCAS(&keys[h], kEmpty, j);
-        while (old != kEmpty && old != j) {
-            h = (h + 1u) & (uint32_t)(T - 1);
-            old = atomicCAS(&keys[h], kEmpty, j);
-        }
-        total += __popcll(__ballot(old == kEmpty && h != (uint32_t)T));
-        return (int)h;
-    };
-    auto apply = [&](const Pass<false, true> &d, int h, int tf, int tl) {
-        for (int tt = tf; tt <= tl; ++tt) {
-            if (d.t != tt) continue;
-            const double av = *(const double *)&items[tt].x;
-            vals[h] = __fma_rn(av, d.b, vals[h]);
-        }
-    };
-    int64_t q0 = r.it0;
-    int off0 = 0;
-    while (q0 < r.it1) {
-        const int E = load_round_win<true, CL>(a, r, q0, off0, items, sbits, w0, w1, true, cin, cout);
-        const int npass = (E + 63) >> 6;
-        int cum = 0;
-        for (int p = 0; p < npass; p += kR) {
-            if (total > T - 1 - 64 * kR) return -1;
-            Pass<false, true> d[kR];
-            int tf[kR], tl[kR];
-#pragma unroll
-            for (int rr = 0; rr < kR; ++rr) {
-                if (p + rr < npass) {
-                    const uint64_t w = uniform64(sbits[p + rr]);
-                    const int last = min(63, E - 1 - ((p + rr) << 6));
-                    tf[rr] = cum + (int)(w & 1ull) - 1;
-                    tl[rr] = cum + __popcll(w & lanemask_le(last)) - 1;
-                    d[rr] = fetch_pass<false, true>(a, items, w, cum, ((p + rr) << 6) + lane, E, le);
-                    cum += __popcll(w);
-                }
-            }
-#pragma unroll
-            for (int rr = 0; rr < kR; ++rr)
-                if (p + rr < npass) apply(d[rr], probe(d[rr].j), tf[rr], tl[rr]);
-        }
-    }
-    if (total > room) return -2;
-    // counting sort by bucket: counts, inclusive prefix (bucket ends), keys
-    // placed from each bucket's end down (the ends become the starts)
-    const float bscale = __fdividef((float)NB, (float)(uint32_t)(w1 - w0));
-    auto bucket = [&](int j) -> int {
-        const int b = (int)((float)(uint32_t)(j - w0) * bscale);
-        return b < NB ? b : NB - 1;
-    };
-    lds_fill(bend, 4 * NB, 0u);
-    if (lane == 0) bend[NB] = total;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (int c0 = 0; c0 < T; c0 += 64) {
-        const int key = keys[c0 + lane];
-        if (key != kEmpty) atomicAdd(&bend[bucket(key)], 1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    int run = 0;
-    for (int c0 = 0; c0 < NB; c0 += 64) {
-        const int cnt = bend[c0 + lane];
-        const int incl = wave_incl_scan(cnt);
-        bend[c0 + lane] = run + incl;
-        run += __shfl(incl, 63);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (int c0 = 0; c0 < T; c0 += 64) {
-        const int key = keys[c0 + lane];
-        if (key != kEmpty) arr[atomicSub(&bend[bucket(key)], 1) - 1] = key;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (int c0 = 0; c0 < T; c0 += 64) {
-        const int sidx = c0 + lane;
-        const int key = keys[sidx];
-        if (key == kEmpty) continue;
-        const int b = bucket(key);
-        const int s0 = bend[b], s1 = bend[b + 1];
-        int rank = s0;
-        for (int t = s0; t < s1; ++t) rank += arr[t] < key;
-        ccol[rank] = key;
-        cval[rank] = vals[sidx];
-    }
-    return total;
-}
 
 // Column range of chunk c of nch equal chunks of the output columns [0, ncols).
 __device__ __forceinline__ void win_chunk(int64_t ncols, int nch, int c, int *lo, int *hi)
@@ -1377,14 +1235,6 @@ __device__ __forceinline__ void win_chunk(int64_t ncols, int nch, int c, int *lo
     const int64_t cw = (ncols + nch - 1) / nch;
     *lo = (int)min<int64_t>(ncols, c * cw);
     *hi = (int)min<int64_t>(ncols, (c + 1) * cw);
-}
-
-// Next window width after a window of width w that held n keys, aiming at
-// tk keys (growing at most 2-fold), within [1, cap].
-__device__ __forceinline__ int64_t win_next(int64_t w, int64_t n, int64_t tk, int64_t cap)
-{
-    const int64_t x = w * tk / max<int64_t>(n, tk / 2);
-    return max<int64_t>(1, min<int64_t>(x, cap));
 }
 
 // (row, chunk) pairs of a window launch per unit of the bin: a CSR row, or
@@ -1730,10 +1580,9 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
 // rank, the keys before it in the window (a per-word prefix plus a popcount),
 // so there is no probing, no table that can fill and no sort -- the values
 // come out in column order, and the columns are read off the bitmap.  The
-// window's products are walked as on the window path (items in ascending k,
-// 64-product passes, each item's entries applied in turn, positions in B
-// carried from one window to the next), so every output entry still receives
-// its products in ascending k, one fma each from +0.0.
+// window's products are walked in the usual way (items in ascending k,
+// 64-product passes, each item's entries applied in turn), with the items'
+// positions in B carried from one window to the next.
 constexpr int kNbLog2Bits = 19;  // columns per segment: a 64 KiB bitmap
 constexpr int kNbWords = 1 << (kNbLog2Bits - 5);
 constexpr int kNbK = 1024;       // keys per window at most (a value each)
@@ -1984,76 +1833,6 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
     }
 }
 
-// Numeric: one wavefront per (row, chunk) for units counted by chunks (count
-// INT32_MAX); a row the shared-memory symbolic phase counted whole is one
-// chunk over its unit's column range [keylo, keyhi].
-template <bool CL>
-__global__ void __launch_bounds__(64) k_num_win(SpArgs a)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int64_t tk = (1 << kWinNumLog2T) * 5 / 8;
-    const int lane = (int)__lane_id();
-    const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
-    int32_t *const cur0 = a.win_cur ? a.win_cur + (size_t)blockIdx.x * (2 * kWinCurMax) : nullptr;
-    int32_t *const cur1 = cur0 ? cur0 + kWinCurMax : nullptr;
-    for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
-        const WinPair w = win_pair<CL>(a, i);
-        if (w.u < a.unit_lo || w.u >= a.unit_hi) continue;
-        const bool chunked = uniform(a.ucount[w.u]) == INT32_MAX;
-        int64_t off = (int64_t)uniform64((uint64_t)a.c_rp[w.row]) - a.out_base;
-        int64_t kc;
-        int lo, hi;
-        if (chunked) {
-            win_chunk(a.ncols, w.nch, w.c, &lo, &hi);
-            // this chunk's entries follow those of the chunks before it; the
-            // symbolic launch numbered the same (member, chunk) pairs from
-            // the unit's first pair
-            const int64_t cb = (int64_t)uniform64((uint64_t)a.sym_base[w.u]) + (int64_t)w.r.l * w.nch;
-            if (cb < 0 || cb + w.nch > a.win_cap) {
-                if (lane == 0) atomicOr(a.err, kErrWindows);
-                continue;
-            }
-            const int32_t *cc = a.chunk_cnt + cb;
-            int64_t before = 0;
-            for (int x = lane; x < w.c; x += 64) before += cc[x];
-            for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o);
-            off += (int64_t)uniform64((uint64_t)before);
-            kc = uniform(cc[w.c]);
-        } else {
-            lo = uniform(a.keylo[w.u]);
-            hi = uniform(a.keyhi[w.u]) + 1;
-            kc = (int64_t)uniform64((uint64_t)(a.c_rp[w.row + 1] - a.c_rp[w.row]));
-        }
-        if (kc <= 0) continue;
-        if (off < 0 || off + kc > a.cap || lo < 0 || hi > a.ncols || lo >= hi) {
-            if (lane == 0) atomicOr(a.err, kErrCapacity);
-            continue;
-        }
-        int64_t width = max<int64_t>(1, min<int64_t>(hi - lo, (hi - lo) * tk / kc));
-        int64_t done = 0;
-        // the items' positions in B at the window start (none before the first
-        // window), and where they reach the window's end; swapped after each
-        // window that completes (a window redone narrower starts from the same)
-        int32_t *cin = nullptr, *cout = cur0;
-        for (int w0 = lo; w0 < hi;) {
-            const int w1 = (int)min<int64_t>(hi, w0 + width);
-            const int k = num_window<CL>(a, w.r, w0, w1, smem, a.c_col + off + done, a.c_val + off + done, kc - done,
-                                         cin, cout);
-            if (k == -1) {
-                width = max<int64_t>(1, (w1 - w0) / 2);
-                continue;
-            }
-            if (k < 0) break;
-            cin = cout;
-            cout = cout == cur0 ? cur1 : cur0;
-            done += k;
-            width = win_next(w1 - w0, k, tk, hi - lo);
-            w0 = w1;
-        }
-        if (lane == 0 && done != kc) atomicOr(a.err, kErrCount);
-    }
-}
-
 hipError_t launch_win_prep(bool sym, bool cluster, const SpArgs &a, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((a.count + 1 + 255) / 256);
@@ -2077,13 +1856,6 @@ hipError_t launch_num_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t 
     const dim3 g(blocks), t(64 * kBmWaves);
     if (cluster) hipLaunchKernelGGL(k_num_bm<true>, g, t, (size_t)num_bm_bytes(), s, a);
     else hipLaunchKernelGGL(k_num_bm<false>, g, t, (size_t)num_bm_bytes(), s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_num_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
-{
-    if (cluster) hipLaunchKernelGGL(k_num_win<true>, dim3(blocks), dim3(64), (size_t)win_num_wave_bytes(), s, a);
-    else hipLaunchKernelGGL(k_num_win<false>, dim3(blocks), dim3(64), (size_t)win_num_wave_bytes(), s, a);
     return hipGetLastError();
 }
 

@@ -229,17 +229,19 @@ hipError_t launch_sym_dense(bool cluster, bool batch, const SpArgs &a, int block
 // numeric with predicted sizes (CSR rows): bounded probing, padded output
 hipError_t launch_num_pred(const SpArgs &a, int blocks, int threads, size_t lds, hipStream_t s);
 hipError_t launch_num_dense(bool cluster, bool batch, const SpArgs &a, int blocks, hipStream_t s);
-// column-window path for units too long for shared memory: one wavefront per
-// (row, chunk) of the output columns (a cluster's member rows one by one),
+// column-window path for units too long for shared memory: bitmaps of each
+// row's output columns (a cluster's member rows one by one), one workgroup
+// per unit (symbolic) or per (row, chunk) of the output columns (numeric),
 // persistent over the bin; a unit of ub products gets about ub / 2^win_log2
 // chunks per row
 constexpr int kWinChunksMax = 256;
 // items of a window row whose positions in B are carried from one window to
 // the next (later items are found by binary search in every window)
 constexpr int kWinCurMax = 1024;
-// wavefronts of a workgroup of the bitmap kernels (one unit per workgroup)
+// wavefronts of a workgroup of the bitmap kernels (one unit, or one column
+// chunk of a row, per workgroup)
 constexpr int kBmWaves = 8;
-constexpr int kWinLog2Default = 16;
+constexpr int kWinLog2Default = 18;
 __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
 {
     const int64_t n = (ub + ((int64_t)1 << log2) - 1) >> log2;
@@ -248,10 +250,8 @@ __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
 hipError_t launch_win_prep(bool sym, bool cluster, const SpArgs &a, hipStream_t s);
 int64_t sym_bm_bytes();
 int64_t num_bm_bytes();
-int64_t win_num_wave_bytes();
 hipError_t launch_sym_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
 hipError_t launch_num_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
-hipError_t launch_num_win(bool cluster, const SpArgs &a, int blocks, hipStream_t s);
 
 // launchers (util.hip)
 struct BinArgs {
