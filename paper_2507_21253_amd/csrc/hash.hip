@@ -219,7 +219,8 @@ int64_t num_wave_bytes(bool cl, int sclass, int T, int load_pct)
 // off0 products of the item at q0 were taken by earlier rounds).  Returns the
 // number of products in the round.
 __device__ __forceinline__ int flatten_round(int64_t it1, int64_t &q0, int &off0, ItemRec *items, uint64_t *sbits,
-                                             int64_t bs, int bl, uint32_t rx, uint32_t ry, int *nitems = nullptr)
+                                             int64_t bs, int bl, uint32_t rx, uint32_t ry, int *nitems = nullptr,
+                                             bool *fin = nullptr)
 {
     const int lane = (int)__lane_id();
     if (lane == 0) {
@@ -242,6 +243,8 @@ __device__ __forceinline__ int flatten_round(int64_t it1, int64_t &q0, int &off0
         items[__popcll(inb & lanemask_lt(lane))] = r;
         atomicOr((unsigned long long *)&sbits[P >> 6], 1ull << (P & 63));
     }
+    // fin: this lane's item needs nothing from later rounds
+    if (fin) *fin = blc == 0 || (in && (int64_t)P + bl <= kRoundW);
     const uint64_t cutb = __ballot(in && (int64_t)P + bl > kRoundW);
     if (cutb) {
         const int cl = __ffsll((unsigned long long)cutb) - 1;
@@ -1195,39 +1198,57 @@ struct WinRow {
 // Loads the next round of a window row's items for the window [w0, w1):
 // lane i takes item q0+i and the part of row k of B inside the window
 // (clip false: the caller knows every row of B reached lies inside).  With
-// cursors, item t < kWinCurMax of the row starts at cin[t] (where its row of
-// B reached w0, left there by the window before) and its end goes to
-// cout[t] for the window after; without, both ends are searched.
+// cursors (cvalid: left by the window before, which ended at w0), item
+// t < kWinCurMax of the row starts at cpos[t], the first position of its row
+// of B at or after w0, whose column cnext[t] tells without any load whether
+// the item reaches this window at all; once an item is done with the window
+// both move on to w1.
 template <bool NUM, bool CL>
 __device__ __forceinline__ int load_round_win(const SpArgs &a, const WinRow &r, int64_t &q0, int &off0,
                                               ItemRec *items, uint64_t *sbits, int w0, int w1, bool clip = true,
-                                              const int32_t *cin = nullptr, int32_t *cout = nullptr)
+                                              int32_t *cpos = nullptr, int32_t *cnext = nullptr, bool cvalid = false)
 {
     const int lane = (int)__lane_id();
     sbits[lane] = 0ull;
     const int64_t q = q0 + lane;
     uint32_t lo = 0, hi = 0;
     double a1 = 0.0;
+    bool upd = false;
+    int32_t npos = 0, nnext = 0;
     if (q < r.it1 && (!CL || ((a.cl_mask[q] >> r.l) & 1u))) {
         const int64_t t = q - r.it0;
-        const bool cur = cout && t < kWinCurMax;
-        const int k = CL ? a.cl_col[q] : a.a_col[q];
-        lo = (uint32_t)a.b_rp[k];
-        hi = (uint32_t)a.b_rp[k + 1];
-        if (cur && cin) {
-            lo = (uint32_t)cin[t];
-            hi = gallop_col(a.b_col, lo, hi, w1);
-        } else {
-            if (clip && lo < hi && ld_col(a.b_col, lo) < w0) lo = lower_bound_col(a.b_col, lo + 1, hi, w0);
-            if (clip && lo < hi && ld_col(a.b_col, hi - 1) >= w1) hi = lower_bound_col(a.b_col, lo, hi - 1, w1);
+        const bool cur = cpos && t < kWinCurMax;
+        if (!(cur && cvalid && cnext[t] >= w1)) {
+            const int k = CL ? a.cl_col[q] : a.a_col[q];
+            lo = (uint32_t)a.b_rp[k];
+            const uint32_t end = (uint32_t)a.b_rp[k + 1];
+            hi = end;
+            if (cur && cvalid) {
+                lo = (uint32_t)cpos[t];
+                hi = gallop_col(a.b_col, lo, end, w1);
+            } else {
+                if (clip && lo < hi && ld_col(a.b_col, lo) < w0) lo = lower_bound_col(a.b_col, lo + 1, hi, w0);
+                if (clip && lo < hi && ld_col(a.b_col, hi - 1) >= w1) hi = lower_bound_col(a.b_col, lo, hi - 1, w1);
+            }
+            if (cur) {
+                upd = true;
+                npos = (int32_t)hi;
+                nnext = hi < end ? ld_col(a.b_col, hi) : INT_MAX;
+            }
+            if (NUM) a1 = CL ? a.cl_val[r.vbase + (q - r.it0) * r.s + r.l] : a.a_val[q];
         }
-        if (cur) cout[t] = (int32_t)hi;
-        if (NUM) a1 = CL ? a.cl_val[r.vbase + (q - r.it0) * r.s + r.l] : a.a_val[q];
     }
     const uint64_t ab = (uint64_t)__double_as_longlong(a1);
-    return flatten_round(r.it1, q0, off0, items, sbits, lo, (int)(hi - lo), (uint32_t)ab, (uint32_t)(ab >> 32));
+    bool fin;
+    const int E = flatten_round(r.it1, q0, off0, items, sbits, lo, (int)(hi - lo), (uint32_t)ab, (uint32_t)(ab >> 32),
+                                nullptr, &fin);
+    if (upd && fin) {
+        const int64_t t = q - r.it0;
+        cpos[t] = npos;
+        cnext[t] = nnext;
+    }
+    return E;
 }
-
 
 // Column range of chunk c of nch equal chunks of the output columns [0, ncols).
 __device__ __forceinline__ void win_chunk(int64_t ncols, int nch, int c, int *lo, int *hi)
@@ -1658,8 +1679,9 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
     ItemRec *items = (ItemRec *)(wb + kNbValBytes + kNbPreBytes);
     uint64_t *sbits = (uint64_t *)(wb + kNbValBytes + kNbPreBytes + 16 * 64);
     const uint64_t le = lanemask_le(lane);
-    int32_t *const cur0 = a.win_cur ? a.win_cur + ((size_t)blockIdx.x * kBmWaves + wave) * (2 * kWinCurMax) : nullptr;
-    int32_t *const cur1 = cur0 ? cur0 + kWinCurMax : nullptr;
+    // this wavefront's carried positions in B and the columns there
+    int32_t *const cpos = a.win_cur ? a.win_cur + ((size_t)blockIdx.x * kBmWaves + wave) * (2 * kWinCurMax) : nullptr;
+    int32_t *const cnext = cpos ? cpos + kWinCurMax : nullptr;
     const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
     for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
         const WinPair w = win_pair<CL>(a, i);
@@ -1738,8 +1760,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
                     pe = total;
                 }
                 const WinRow r{v.it0, v.it1, v.vbase, l, v.s};
-                const int32_t *cin = nullptr;
-                int32_t *cout = cur0;
+                bool cvalid = false;  // the first window searches
                 int pos = pa;
                 for (int a0 = wa; a0 < we;) {
                     // the window: words [a0, b0) holding nk <= kNbK keys, their prefix in lpre
@@ -1774,7 +1795,8 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
                     int64_t q0 = v.it0;
                     int off0 = 0;
                     while (q0 < v.it1) {
-                        const int E = load_round_win<true, CL>(a, r, q0, off0, items, sbits, c0, c1, true, cin, cout);
+                        const int E =
+                            load_round_win<true, CL>(a, r, q0, off0, items, sbits, c0, c1, true, cpos, cnext, cvalid);
                         const int npass = (E + 63) >> 6;
                         int cum = 0;
                         for (int p = 0; p < npass; p += kR) {
@@ -1818,8 +1840,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
                             bits &= bits - 1u;
                         }
                     }
-                    cin = cout;
-                    cout = cout == cur0 ? cur1 : cur0;
+                    cvalid = true;
                     pos += nk;
                     a0 = b0;
                 }
