@@ -1260,8 +1260,10 @@ __device__ __forceinline__ void win_chunk(int64_t ncols, int nch, int c, int *lo
 
 // (row, chunk) pairs of a window launch per unit of the bin: a CSR row, or
 // each member row of a cluster, gets win_nchunks(the unit's products)
-// chunks when the symbolic phase counted it by chunks, one chunk (numeric
-// only) when the shared-memory symbolic phase counted it whole.
+// chunks in the symbolic launch; in the numeric launch only rows of more
+// than kWinCurMax items are split so (the chunks of a row share its work out
+// between workgroups, but each walks all of the row's items), the others
+// are one task each.
 // base[i] = pairs of the bin's i-th unit, base[count] = 0; an exclusive scan
 // then gives each unit's first pair.
 template <bool SYM, bool CL>
@@ -1275,7 +1277,9 @@ __global__ void __launch_bounds__(256) k_win_prep(SpArgs a)
     }
     const int u = a.order[a.bin_begin + i];
     const int s = CL ? (int)(a.cl_row_ptr[u + 1] - a.cl_row_ptr[u]) : 1;
-    a.win_base[i] = (int64_t)s * (SYM || a.ucount[u] == INT32_MAX ? win_nchunks(a.probes[u], a.win_log2) : 1);
+    const int64_t m = CL ? a.cl_col_ptr[u + 1] - a.cl_col_ptr[u] : a.a_rp[u + 1] - a.a_rp[u];
+    const bool split = SYM || (a.ucount[u] == INT32_MAX && m > kWinCurMax);
+    a.win_base[i] = (int64_t)s * (split ? win_nchunks(a.probes[u], a.win_log2) : 1);
 }
 
 // The (row, chunk) pair i of a window launch: p = the largest position with
@@ -1441,9 +1445,11 @@ __device__ __forceinline__ void bm_range(const SpArgs &a, const UnitView &v, int
 
 // Sets the bits of member row l's output columns inside the segment [w0, w1)
 // (bit x of bm: column w0 + x), clearing the segment's words first.  clip
-// false: the segment holds the row's whole range, and the row's np products
-// are cut into kBmWaves equal parts, one per wavefront; else the wavefronts
-// take the items 64 at a time from *next.  Starts and ends with a barrier.
+// false: the row's np products are cut into kBmWaves equal parts, one per
+// wavefront, and those outside the segment are passed over (none when the
+// segment holds the row's whole range); clip: the wavefronts take the items
+// 64 at a time from *next and find each item's part inside the segment by
+// binary search.  Starts and ends with a barrier.
 template <bool CL>
 __device__ __forceinline__ void bm_fill(const SpArgs &a, const UnitView &v, int l, int64_t np, int w0, int w1,
                                         bool clip, uint32_t *bm, int *next, ItemRec *items, uint64_t *sbits)
@@ -1500,10 +1506,8 @@ __device__ __forceinline__ void bm_fill(const SpArgs &a, const UnitView &v, int 
                 }
 #pragma unroll
                 for (int rr = 0; rr < kR; ++rr) {
-                    if (d[rr].j != kDummyKey) {
-                        const uint32_t x = (uint32_t)(d[rr].j - w0);
-                        atomicOr(&bm[x >> 5], 1u << (x & 31u));
-                    }
+                    const uint32_t x = (uint32_t)(d[rr].j - w0);
+                    if (d[rr].j != kDummyKey && x < (uint32_t)(w1 - w0)) atomicOr(&bm[x >> 5], 1u << (x & 31u));
                 }
             }
         }
@@ -1590,9 +1594,9 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
 }
 
 // Numeric phase of the units too long for shared-memory tables: one
-// workgroup of kBmWaves wavefronts per (member row, column chunk) of the
-// symbolic phase (the chunk's entries follow those of the chunks before it;
-// a row the shared-memory symbolic phase counted whole is one task).  The
+// workgroup of kBmWaves wavefronts per member row, or, for rows of many items,
+// per (member row, column chunk) of the symbolic phase (the chunk's entries
+// follow those of the chunks before it).  The
 // task's columns are taken in segments of 2^kNbLog2Bits columns; for
 // each, the row's output columns are first set in a bitmap (as in the
 // symbolic phase), whose keys are then shared out between the wavefronts in
@@ -1693,7 +1697,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
             // this task's columns [clo, chi), its first entry in C and its entries
             int64_t off = (int64_t)uniform64((uint64_t)a.c_rp[row]) - a.out_base, cnt;
             int clo, chi;
-            if (uniform(a.ucount[u]) == INT32_MAX) {
+            if (w.nch > 1) {
                 win_chunk(a.ncols, w.nch, w.c, &clo, &chi);
                 const int64_t cb = (int64_t)uniform64((uint64_t)a.sym_base[u]) + (int64_t)l * w.nch;
                 if (cb < 0 || cb + w.nch > a.win_cap) {
@@ -1727,7 +1731,9 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
                 const int w0 = (int)g0;
                 const int w1 = (int)min<int64_t>((int64_t)hi + 1, g0 + ((int64_t)1 << kNbLog2Bits));
                 const int nw = (w1 - w0 + 31) >> 5;
-                bm_fill<CL>(a, v, l, np, w0, w1, w0 > rlo || w1 <= rhi, bm, next, items, sbits);
+                // a chunk of a row searches its items' parts; a whole row walks
+                // all of its products once per segment
+                bm_fill<CL>(a, v, l, np, w0, w1, w.nch > 1 && (w0 > rlo || w1 <= rhi), bm, next, items, sbits);
                 // keys per thread's words, and their exclusive prefix over the workgroup
                 const int wpt = (nw + NT - 1) / NT;
                 int mine = 0;
