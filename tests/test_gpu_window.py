@@ -9,8 +9,8 @@ largest symbolic table; a bitmap per row, the counts split at the numeric
 chunks), with one chunk or up to 256 (win_chunk_log2 sets the products per
 chunk); rows whose column range is wider than one bitmap segment; rows counted whole in shared memory but too large
 for the numeric tables (one chunk over the row's column range); output
-columns packed densely into part of a chunk, so that first windows overflow
-and are redone narrower in both phases; row panels; R-MAT rows; clustered
+columns packed densely into part of a chunk; row panels; R-MAT rows (the
+whole R-MAT 16 product among them); clustered
 operands (fixed and hierarchical plans); a numeric call whose chunking
 differs from its symbolic call's is refused."""
 import numpy as np
@@ -99,6 +99,15 @@ def test_rmat_window_path_bitwise(scale):
     assert_same(product(R, R), ref, "default")
     assert_same(product(R, R, hc.opts(sym_tmax_log2=8, num_tmax=128)), ref, "small tables")
     assert_same(product(R, R, hc.opts(sym_tmax_log2=8, num_tmax=128, win_chunk_log2=6)), ref, "many chunks")
+
+
+def test_rmat16_whole_product_bitwise():
+    # 65,536 rows, 1.24e9 products, 3.5e8 entries: most products on the
+    # long-row path (bitmaps, whole-row tasks and column-chunk tasks)
+    import os
+    R = synth.workload_rmat(16, 4)
+    ref = oracle.spgemm_mt(R, R, min(16, len(os.sched_getaffinity(0))))
+    assert_same(product(R, R), ref, "rmat16")
 
 
 def test_window_rows_in_panels():
