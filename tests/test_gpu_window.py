@@ -1,13 +1,16 @@
-"""GPU parity of the column-window path: rows whose output is too large for
-one shared-memory table (CSR rows, or the member rows of clusters) are cut
-into column chunks (one wavefront each) and every chunk into windows that fit
-a table; C must still equal the
-oracle bit for bit, since every output entry gets its products in ascending k.
+"""GPU parity of the long-row path: rows whose output is too large for one
+shared-memory table (CSR rows, or the member rows of clusters) hold their
+output columns in bitmaps, counted per column chunk in the symbolic phase;
+the numeric phase takes a whole row, or for rows of many items one column
+chunk, per workgroup, in windows whose slots are the keys' ranks; C must
+still equal the oracle bit for bit, since every output entry gets its
+products in ascending k.
 
 Cases: rows counted by chunks in the symbolic phase (products beyond the
 largest symbolic table; a bitmap per row, the counts split at the numeric
 chunks), with one chunk or up to 256 (win_chunk_log2 sets the products per
-chunk); rows whose column range is wider than one bitmap segment; rows counted whole in shared memory but too large
+chunk); rows whose column range is wider than one bitmap segment; rows
+counted whole in shared memory but too large
 for the numeric tables (one chunk over the row's column range); output
 columns packed densely into part of a chunk; row panels; R-MAT rows (the
 whole R-MAT 16 product among them); clustered
