@@ -124,7 +124,13 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
     for (int64_t u = cb + (threadIdx.x >> 4); u < ce; u += blockDim.x >> 4) {
         const WorkView w = work_view<CL, BATCH>(a, u);
         int64_t probes = 0;
-        for (int64_t q = w.it0 + g.gl; q < w.it1; q += 16) {
+        // two items per lane and step, so that both items' loads are in flight together
+        int64_t q = w.it0 + g.gl;
+        for (; q + 16 < w.it1; q += 32) {
+            const int k0 = w.col[q], k1 = w.col[q + 16];
+            probes += (w.b_rp[k0 + 1] - w.b_rp[k0]) + (w.b_rp[k1 + 1] - w.b_rp[k1]);
+        }
+        if (q < w.it1) {
             const int k = w.col[q];
             probes += w.b_rp[k + 1] - w.b_rp[k];
         }

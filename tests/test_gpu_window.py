@@ -86,6 +86,28 @@ def test_rows_wider_than_one_bitmap_segment():
         assert_same(product(A, B, o), ref, str(o))
 
 
+@pytest.mark.parametrize("log2", [30, 7])
+def test_rows_at_the_item_limit_of_whole_row_tasks(log2):
+    # rows of 1,023, 1,024 and 1,025 items (whole-row tasks up to 1,024 items,
+    # column-chunk tasks beyond when the symbolic phase cut the row), plain and
+    # as hierarchical clusters of up to 4 rows
+    rng = np.random.default_rng(31)
+    nb, ncols = 1100, 300_000
+    brows = [rng.choice(ncols, int(rng.integers(5, 60)), replace=False) for _ in range(nb)]
+    B = csr_from_rows(brows, ncols, rng)
+    arows = [rng.choice(nb, m, replace=False) for m in (1023, 1024, 1025, 3, 1025, 1024, 700)]
+    A = csr_from_rows(arows, nb, rng)
+    ref = oracle.spgemm(A, B)
+    o = hc.opts(sym_tmax_log2=8, num_tmax=128, win_chunk_log2=log2)
+    assert_same(product(A, B, o), ref, "csr")
+    Ad, Bd = hc.DeviceCSR.from_host(A), hc.DeviceCSR.from_host(B)
+    Dc = hc.cluster_build(Ad, hc.plan_hierarchical(A, (1, 10), 4))
+    torch.cuda.synchronize()
+    C = hc.spgemm(Dc, Bd, o)
+    torch.cuda.synchronize()
+    assert_same(C.to_host(), ref, "clusters")
+
+
 def test_rows_counted_whole_then_windowed():
     # symbolic tables large enough for every row, numeric tables too small:
     # the numeric phase takes each row as one chunk over its column range
