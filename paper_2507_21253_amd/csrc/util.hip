@@ -109,7 +109,7 @@ __device__ __forceinline__ WorkView work_view(const BinArgs &a, int64_t g)
     return w;
 }
 
-// One group of 16 lanes per unit: probes = sum of |B_k| over the unit's
+// One group of 8 lanes per unit: probes = sum of |B_k| over the unit's
 // columns k (an upper bound on its distinct output columns) and its
 // symbolic bin.  Units with no products get their zero row counts here.
 template <bool CL, bool BATCH>
@@ -118,16 +118,17 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
     __shared__ int hist[kSymBins];
     for (int i = threadIdx.x; i < kSymBins; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    const Group g = make_group(16);
+    constexpr int G = 8;
+    const Group g = make_group(G);
     int64_t cb, ce;
     chunk_of(a.nunits, &cb, &ce);
-    for (int64_t u = cb + (threadIdx.x >> 4); u < ce; u += blockDim.x >> 4) {
+    for (int64_t u = cb + (threadIdx.x / G); u < ce; u += blockDim.x / G) {
         const WorkView w = work_view<CL, BATCH>(a, u);
         int64_t probes = 0;
         // two items per lane and step, so that both items' loads are in flight together
         int64_t q = w.it0 + g.gl;
-        for (; q + 16 < w.it1; q += 32) {
-            const int k0 = w.col[q], k1 = w.col[q + 16];
+        for (; q + G < w.it1; q += 2 * G) {
+            const int k0 = w.col[q], k1 = w.col[q + G];
             probes += (w.b_rp[k0 + 1] - w.b_rp[k0]) + (w.b_rp[k1 + 1] - w.b_rp[k1]);
         }
         if (q < w.it1) {
