@@ -1850,7 +1850,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
                     pos += nk;
                     a0 = b0;
                 }
-                (void)pe;
+                if (lane == 0 && pos != pe) atomicOr(a.err, kErrCount);  // windows did not tile the share
                 __syncthreads();
                 done += total;
             }
