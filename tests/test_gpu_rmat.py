@@ -5,7 +5,8 @@ the symbolic phase runs over all rows and the numeric phase in row panels.
 Checked: every row count against the oracle's structure count and the
 product bound; the 1,000 rows with the most products, and sampled rows, bit
 for bit, each computed as its own one-row panel; one large panel's sampled
-rows."""
+rows.  At scale 18 the whole product is checked row by row against the
+oracle's streaming per-row statistics (count, column hash, value sum)."""
 import os
 from concurrent.futures import ThreadPoolExecutor
 
@@ -108,3 +109,43 @@ def test_rmat20_large_panel(rmat20):
         np.testing.assert_array_equal(col[b:e].cpu().numpy(), ref.col, err_msg="row %d" % r)
         np.testing.assert_array_equal(val[b:e].cpu().numpy(), ref.val, err_msg="row %d" % r)
     del col, val
+
+
+def test_rmat18_every_row_checksum():
+    # R-MAT scale 18 (262,144 rows, 9.5e9 products, 3.0e9 entries, 35 GB): the
+    # whole C computed in row panels, and every row's count, hash of its sorted
+    # columns and value sum (exact: the values are integers) against the
+    # oracle's streaming per-row statistics (C never stored on the host side)
+    import os
+    R = synth.workload_rmat(18, 4)
+    D = hc.DeviceCSR.from_host(R)
+    P = hc.Product(D, D)
+    P.info = hc.spgemm_symbolic(D, D, P.C_row_ptr, P.ws, P.o)
+    rp = P.C_row_ptr.cpu().numpy()
+    nthreads = min(16, len(os.sched_getaffinity(0)))
+    ref_n, ref_h, ref_s = oracle.rowstats(R, R, (0, R.nrows), nthreads)
+    np.testing.assert_array_equal(np.diff(rp), ref_n)
+    cap = 700_000_000  # entries per panel (8.4 GB)
+    col = torch.empty(cap, dtype=torch.int32, device="cuda")
+    val = torch.empty(cap, dtype=torch.float64, device="cuda")
+    lo = 0
+    while lo < R.nrows:
+        hi = max(int(np.searchsorted(rp, rp[lo] + cap, side="right")) - 1, lo + 1)
+        b0 = int(rp[lo])
+        o = hc.opts(unit_lo=lo, unit_hi=hi, out_base=b0, flags=hc.F_SYNC_CHECK)
+        hc.spgemm_numeric(D, D, P.info, P.C_row_ptr, col, val, P.ws, o, capacity=cap)
+        n = int(rp[hi]) - b0
+        c = col[:n].cpu().numpy()
+        v = val[:n].cpu().numpy()
+        for r in range(lo, hi):
+            b, e = int(rp[r]) - b0, int(rp[r + 1]) - b0
+            assert oracle.hash_cols(c[b:e]) == int(ref_h[r]), "row %d columns" % r
+        starts = (rp[lo:hi] - b0).astype(np.int64)
+        nonempty = rp[lo + 1:hi + 1] > rp[lo:hi]
+        sums = np.zeros(hi - lo)
+        if n:
+            sums[nonempty] = np.add.reduceat(v, starts[nonempty])
+        np.testing.assert_array_equal(sums, ref_s[lo:hi], err_msg="value sums of rows %d..%d" % (lo, hi))
+        lo = hi
+    del col, val, P, D
+    torch.cuda.empty_cache()
