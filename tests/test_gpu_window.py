@@ -9,8 +9,8 @@ products in ascending k.
 Cases: rows counted by chunks in the symbolic phase (products beyond the
 largest symbolic table; a bitmap per row, the counts split at the numeric
 chunks), with one chunk or up to 256 (win_chunk_log2 sets the products per
-chunk); rows whose column range is wider than one bitmap segment; rows
-counted whole in shared memory but too large
+chunk); rows whose column range is wider than one bitmap segment (CSR
+rows and the member rows of clusters); rows counted whole in shared memory but too large
 for the numeric tables (one chunk over the row's column range); output
 columns packed densely into part of a chunk; row panels; R-MAT rows (the
 whole R-MAT 16 product among them); clustered
@@ -84,6 +84,30 @@ def test_rows_wider_than_one_bitmap_segment():
     ref = oracle.spgemm(A, B)
     for o in (None, hc.opts(sym_tmax_log2=8, num_tmax=128), hc.opts(sym_tmax_log2=8, num_tmax=128, win_chunk_log2=9)):
         assert_same(product(A, B, o), ref, str(o))
+
+
+def test_cluster_rows_wider_than_one_bitmap_segment():
+    # member rows of clusters whose output spans 1.3M columns (three bitmap
+    # segments), with few items (whole-row tasks, every segment filled by a
+    # walk over all of the row's products) and with more than 1,024 items
+    # (column-chunk tasks), an empty member among them
+    rng = np.random.default_rng(23)
+    ncols, nb = 1_300_000, 1_200
+    brows = [rng.choice(ncols, int(rng.integers(20, 200)), replace=False) for _ in range(nb)]
+    arows = [rng.choice(nb, m, replace=False) for m in (5, 40, 1030, 12, 1100, 300, 0, 64, 1025, 2)]
+    A, B = csr_from_rows(arows, nb, rng), csr_from_rows(brows, ncols, rng)
+    ref = oracle.spgemm(A, B)
+    Ad, Bd = hc.DeviceCSR.from_host(A), hc.DeviceCSR.from_host(B)
+    opts = (None, hc.opts(sym_tmax_log2=8, num_tmax=128), hc.opts(sym_tmax_log2=8, num_tmax=128, win_chunk_log2=9))
+    for o in opts:
+        assert_same(product(A, B, o), ref, "csr %s" % o)
+    for K in (2, 4):
+        Dc = hc.cluster_build(Ad, hc.plan_fixed(A.nrows, K))
+        for o in opts:
+            torch.cuda.synchronize()
+            C = hc.spgemm(Dc, Bd, o)
+            torch.cuda.synchronize()
+            assert_same(C.to_host(), ref, "clusters of %d %s" % (K, o))
 
 
 @pytest.mark.parametrize("log2", [30, 7])
