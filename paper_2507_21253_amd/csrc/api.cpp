@@ -60,7 +60,7 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->chunk_cnt = (int32_t *)take(4 * (size_t)ws->win_cap);
     ws->sym_base = (int64_t *)take(windows ? 8 * nu : 0);
     ws->win_base = (int64_t *)take(windows ? 8 * (nu + 1) : 0);
-    ws->win_cur_slots = windows ? num_bm_blocks() * kBmWaves : 0;
+    ws->win_cur_slots = windows ? num_bm_blocks() * kNumBmWaves : 0;
     ws->win_cur = (int32_t *)take(4 * 2 * (size_t)kWinCurMax * (size_t)ws->win_cur_slots);
     ws->bytes = align_up(off, 256);
     return ws->bytes;
@@ -725,7 +725,7 @@ static int numeric_bins(SpArgs &a, const hcsp_sym_info *info, bool cluster, cons
             if (e) return e;
             // workgroups: as many as fit on the device, each wavefront with a
             // slot of carried positions in the workspace
-            const int64_t blocks = std::min<int64_t>(num_bm_blocks(), ws.win_cur_slots / kBmWaves);
+            const int64_t blocks = std::min<int64_t>(num_bm_blocks(), ws.win_cur_slots / kNumBmWaves);
             if (blocks < 1) return fail(HCSP_E_CAPACITY, "workspace has no room for the long rows' positions");
             HCSP_HIP(launch_num_bm(cluster, a, (int)blocks, st));
             return HCSP_OK;

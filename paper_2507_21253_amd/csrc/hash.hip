@@ -1333,21 +1333,21 @@ __device__ __forceinline__ WinPair win_pair(const SpArgs &a, int64_t i)
     return w;
 }
 
-// Symbolic phase of the units too long for shared-memory tables: their member
-// rows' output columns are counted in a bitmap instead of a table, one
-// workgroup of kBmWaves wavefronts per unit (persistent over the bin), member
-// rows one after another.  A row's column range [lo, hi] (the first and last
-// columns of the rows of B its items reach) is taken in segments of
+// Symbolic phase of the units too long for shared-memory tables: their
+// member rows' output columns are counted in a bitmap instead of a table,
+// one workgroup of kSymBmWaves wavefronts per unit (persistent over the bin),
+// member rows one after another.  A row's column range [lo, hi] (the first
+// and last columns of the rows of B its items reach) is taken in segments of
 // 2^kBmLog2Bits columns.  When the range fits one segment (no row of B needs
-// clipping) the row's flattened product list is cut into kBmWaves equal
+// clipping) the row's flattened product list is cut into kSymBmWaves equal
 // parts, one per wavefront (a few items carry most of the products of a
 // power-law row, so items alone would share the work out badly); otherwise
 // the wavefronts take the items 64 at a time from a shared counter.  Each
 // product sets one bit by an atomic OR that returns nothing (ORs commute, so
-// how the work is shared out does not change the bitmap).  The bits are then counted per column chunk of the numeric phase
-// -- chunk_cnt[first + l*nch + c] for member l, chunk c, first the unit's
-// first pair -- and the row's total is added to its count (zeroed by the
-// binning kernel).
+// how the work is shared out does not change the bitmap).  The bits are then
+// counted per column chunk of the numeric phase -- chunk_cnt[first + l*nch +
+// c] for member l, chunk c, first the unit's first pair -- and the row's
+// total is added to its count (zeroed by the binning kernel).
 constexpr int kBmLog2Bits = 20;  // columns per segment: a 128 KiB bitmap
 constexpr int kBmWords = 1 << (kBmLog2Bits - 5);
 constexpr int kBmWaveBytes = 16 * 64 + 8 * kRoundPasses;  // a wavefront's item records and start bits
@@ -1359,10 +1359,10 @@ struct BmLayout {
         bm = 0;
         ccnt = 4 * kBmWords;             // kWinChunksMax chunk counters
         red = ccnt + 4 * kWinChunksMax;  // per-wavefront partial lo/hi
-        psum = red + 8 * kBmWaves;       // per-wavefront partial product counts
-        next = psum + 8 * kBmWaves;      // the next item group to take
+        psum = red + 8 * kSymBmWaves;    // per-wavefront partial product counts
+        next = psum + 8 * kSymBmWaves;   // the next item group to take
         waves = align16(next + 4);
-        bytes = waves + kBmWaves * kBmWaveBytes;
+        bytes = waves + kSymBmWaves * kBmWaveBytes;
     }
 };
 
@@ -1400,12 +1400,13 @@ __device__ __forceinline__ void bm_locate(const SpArgs &a, const UnitView &v, in
 
 // A member row's column range [lo, hi] (the first and last columns of the
 // rows of B its items reach) and product count, reduced over the workgroup
-// (lo > hi for a row without products).  Contains a barrier.
-template <bool CL>
+// (lo > hi for a row without products), over a workgroup of W wavefronts.
+// Contains a barrier.
+template <bool CL, int W>
 __device__ __forceinline__ void bm_range(const SpArgs &a, const UnitView &v, int l, int *red, int64_t *psum, int &lo,
                                          int &hi, int64_t &np)
 {
-    constexpr int NT = 64 * kBmWaves;
+    constexpr int NT = 64 * W;
     const int wave = (int)(threadIdx.x >> 6), lane = (int)__lane_id();
     lo = INT_MAX;
     hi = -1;
@@ -1427,15 +1428,15 @@ __device__ __forceinline__ void bm_range(const SpArgs &a, const UnitView &v, int
     }
     if (lane == 0) {
         red[wave] = lo;
-        red[kBmWaves + wave] = hi;
+        red[W + wave] = hi;
         psum[wave] = np;
     }
     __syncthreads();
     np = 0;
 #pragma unroll
-    for (int w = 0; w < kBmWaves; ++w) {
+    for (int w = 0; w < W; ++w) {
         lo = min(lo, red[w]);
-        hi = max(hi, red[kBmWaves + w]);
+        hi = max(hi, red[W + w]);
         np += psum[w];
     }
     lo = uniform(lo);
@@ -1445,16 +1446,16 @@ __device__ __forceinline__ void bm_range(const SpArgs &a, const UnitView &v, int
 
 // Sets the bits of member row l's output columns inside the segment [w0, w1)
 // (bit x of bm: column w0 + x), clearing the segment's words first.  clip
-// false: the row's np products are cut into kBmWaves equal parts, one per
+// false: the row's np products are cut into W equal parts, one per
 // wavefront, and those outside the segment are passed over (none when the
 // segment holds the row's whole range); clip: the wavefronts take the items
 // 64 at a time from *next and find each item's part inside the segment by
-// binary search.  Starts and ends with a barrier.
-template <bool CL>
+// binary search.  A workgroup of W wavefronts; starts and ends with a barrier.
+template <bool CL, int W>
 __device__ __forceinline__ void bm_fill(const SpArgs &a, const UnitView &v, int l, int64_t np, int w0, int w1,
                                         bool clip, uint32_t *bm, int *next, ItemRec *items, uint64_t *sbits)
 {
-    constexpr int kR = 8, NT = 64 * kBmWaves;
+    constexpr int kR = 8, NT = 64 * W;
     const int wave = (int)(threadIdx.x >> 6), lane = (int)__lane_id();
     const uint64_t le = lanemask_le(lane);
     const int nw = (w1 - w0 + 31) >> 5;
@@ -1464,8 +1465,8 @@ __device__ __forceinline__ void bm_fill(const SpArgs &a, const UnitView &v, int 
     __syncthreads();
     int64_t x0 = 0, x1 = INT64_MAX;
     if (!clip) {
-        x0 = np * wave / kBmWaves;
-        x1 = np * (wave + 1) / kBmWaves;
+        x0 = np * wave / W;
+        x1 = np * (wave + 1) / W;
     }
     for (;;) {
         int64_t q0;
@@ -1517,10 +1518,10 @@ __device__ __forceinline__ void bm_fill(const SpArgs &a, const UnitView &v, int 
 }
 
 template <bool CL>
-__global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
+__global__ void __launch_bounds__(64 * kSymBmWaves) k_sym_bm(SpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NT = 64 * kBmWaves;
+    constexpr int NT = 64 * kSymBmWaves;
     const BmLayout L;
     uint32_t *bm = (uint32_t *)(smem + L.bm);
     int *ccnt = (int *)(smem + L.ccnt);
@@ -1541,12 +1542,12 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
             for (int c = (int)threadIdx.x; c < nch; c += NT) ccnt[c] = 0;
             int lo, hi;
             int64_t np;
-            bm_range<CL>(a, v, l, red, psum, lo, hi, np);
+            bm_range<CL, kSymBmWaves>(a, v, l, red, psum, lo, hi, np);
             for (int64_t g0 = lo; g0 <= (int64_t)hi; g0 += (int64_t)1 << kBmLog2Bits) {
                 const int w0 = (int)g0;
                 const int w1 = (int)min<int64_t>((int64_t)hi + 1, g0 + ((int64_t)1 << kBmLog2Bits));
                 const int nw = (w1 - w0 + 31) >> 5;
-                bm_fill<CL>(a, v, l, np, w0, w1, g0 > lo || w1 <= hi, bm, next, items, sbits);
+                bm_fill<CL, kSymBmWaves>(a, v, l, np, w0, w1, g0 > lo || w1 <= hi, bm, next, items, sbits);
                 // count the bits per chunk: a wavefront's 64 words usually lie in one chunk
                 for (int x0 = wave * 64; x0 < nw; x0 += NT) {
                     const int wd = x0 + lane;
@@ -1594,9 +1595,9 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_sym_bm(SpArgs a)
 }
 
 // Numeric phase of the units too long for shared-memory tables: one
-// workgroup of kBmWaves wavefronts per member row, or, for rows of many items,
-// per (member row, column chunk) of the symbolic phase (the chunk's entries
-// follow those of the chunks before it).  The
+// workgroup of kNumBmWaves wavefronts per member row, or, for rows of many
+// items, per (member row, column chunk) of the symbolic phase (the chunk's
+// entries follow those of the chunks before it).  The
 // task's columns are taken in segments of 2^kNbLog2Bits columns; for
 // each, the row's output columns are first set in a bitmap (as in the
 // symbolic phase), whose keys are then shared out between the wavefronts in
@@ -1621,12 +1622,12 @@ struct NbLayout {
     __host__ __device__ NbLayout()
     {
         bm = 0;
-        tpre = 4 * kNbWords;                // per-thread key prefix [64 * kBmWaves]
-        red = tpre + 4 * 64 * kBmWaves;     // per-wavefront partial lo/hi, then key sums
-        psum = red + 8 * kBmWaves;          // per-wavefront partial product counts
-        next = psum + 8 * kBmWaves;         // the next item group to take
+        tpre = 4 * kNbWords;                   // per-thread key prefix [64 * kNumBmWaves]
+        red = tpre + 4 * 64 * kNumBmWaves;     // per-wavefront partial lo/hi, then key sums
+        psum = red + 8 * kNumBmWaves;          // per-wavefront partial product counts
+        next = psum + 8 * kNumBmWaves;         // the next item group to take
         waves = align16(next + 4);
-        bytes = waves + kBmWaves * kNbWaveBytes;
+        bytes = waves + kNumBmWaves * kNbWaveBytes;
     }
 };
 
@@ -1638,7 +1639,7 @@ int64_t num_bm_bytes() { return NbLayout().bytes; }
 __device__ __forceinline__ void nb_split(const uint32_t *bm, const int *tpre, int wpt, int nw, int total, int x,
                                          int &W, int &PW)
 {
-    constexpr int NT = 64 * kBmWaves;
+    constexpr int NT = 64 * kNumBmWaves;
     const int lane = (int)__lane_id();
     int below = 0;  // threads whose words start below the prefix x
     for (int t = lane; t < NT; t += 64) below += tpre[t] < x;
@@ -1666,10 +1667,10 @@ __device__ __forceinline__ void nb_split(const uint32_t *bm, const int *tpre, in
 }
 
 template <bool CL>
-__global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
+__global__ void __launch_bounds__(64 * kNumBmWaves) k_num_bm(SpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NT = 64 * kBmWaves, kR = 4;
+    constexpr int NT = 64 * kNumBmWaves, kR = 4;
     const NbLayout L;
     uint32_t *bm = (uint32_t *)(smem + L.bm);
     int *tpre = (int *)(smem + L.tpre);
@@ -1684,7 +1685,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
     uint64_t *sbits = (uint64_t *)(wb + kNbValBytes + kNbPreBytes + 16 * 64);
     const uint64_t le = lanemask_le(lane);
     // this wavefront's carried positions in B and the columns there
-    int32_t *const cpos = a.win_cur ? a.win_cur + ((size_t)blockIdx.x * kBmWaves + wave) * (2 * kWinCurMax) : nullptr;
+    int32_t *const cpos = a.win_cur ? a.win_cur + ((size_t)blockIdx.x * kNumBmWaves + wave) * (2 * kWinCurMax) : nullptr;
     int32_t *const cnext = cpos ? cpos + kWinCurMax : nullptr;
     const int64_t pairs = (int64_t)uniform64((uint64_t)a.win_base[a.count]);
     for (int64_t i = xcd_block(); i < pairs; i += gridDim.x) {
@@ -1722,7 +1723,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
             }
             int rlo, rhi;
             int64_t np;
-            bm_range<CL>(a, v, l, red, psum, rlo, rhi, np);
+            bm_range<CL, kNumBmWaves>(a, v, l, red, psum, rlo, rhi, np);
             // the row's columns inside the task's; one segment over all of the
             // row's products needs no clipping
             const int lo = max(rlo, clo), hi = min(rhi, chi - 1);
@@ -1733,7 +1734,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
                 const int nw = (w1 - w0 + 31) >> 5;
                 // a chunk of a row searches its items' parts; a whole row walks
                 // all of its products once per segment
-                bm_fill<CL>(a, v, l, np, w0, w1, w.nch > 1 && (w0 > rlo || w1 <= rhi), bm, next, items, sbits);
+                bm_fill<CL, kNumBmWaves>(a, v, l, np, w0, w1, w.nch > 1 && (w0 > rlo || w1 <= rhi), bm, next, items, sbits);
                 // keys per thread's words, and their exclusive prefix over the workgroup
                 const int wpt = (nw + NT - 1) / NT;
                 int mine = 0;
@@ -1743,7 +1744,7 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
                 __syncthreads();
                 int before = 0, total = 0;
 #pragma unroll
-                for (int w = 0; w < kBmWaves; ++w) {
+                for (int w = 0; w < kNumBmWaves; ++w) {
                     const int rw = red[w];
                     before += w < wave ? rw : 0;
                     total += rw;
@@ -1758,9 +1759,9 @@ __global__ void __launch_bounds__(64 * kBmWaves) k_num_bm(SpArgs a)
                 }
                 // this wavefront's words [wa, we) and the keys before wa
                 int wa, pa, we, pe;
-                nb_split(bm, tpre, wpt, nw, total, (int)((int64_t)total * wave / kBmWaves), wa, pa);
-                if (wave + 1 < kBmWaves) {
-                    nb_split(bm, tpre, wpt, nw, total, (int)((int64_t)total * (wave + 1) / kBmWaves), we, pe);
+                nb_split(bm, tpre, wpt, nw, total, (int)((int64_t)total * wave / kNumBmWaves), wa, pa);
+                if (wave + 1 < kNumBmWaves) {
+                    nb_split(bm, tpre, wpt, nw, total, (int)((int64_t)total * (wave + 1) / kNumBmWaves), we, pe);
                 } else {
                     we = nw;
                     pe = total;
@@ -1872,7 +1873,7 @@ hipError_t launch_win_prep(bool sym, bool cluster, const SpArgs &a, hipStream_t 
 
 hipError_t launch_sym_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
 {
-    const dim3 g(blocks), t(64 * kBmWaves);
+    const dim3 g(blocks), t(64 * kSymBmWaves);
     if (cluster) hipLaunchKernelGGL(k_sym_bm<true>, g, t, (size_t)sym_bm_bytes(), s, a);
     else hipLaunchKernelGGL(k_sym_bm<false>, g, t, (size_t)sym_bm_bytes(), s, a);
     return hipGetLastError();
@@ -1880,7 +1881,7 @@ hipError_t launch_sym_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t 
 
 hipError_t launch_num_bm(bool cluster, const SpArgs &a, int blocks, hipStream_t s)
 {
-    const dim3 g(blocks), t(64 * kBmWaves);
+    const dim3 g(blocks), t(64 * kNumBmWaves);
     if (cluster) hipLaunchKernelGGL(k_num_bm<true>, g, t, (size_t)num_bm_bytes(), s, a);
     else hipLaunchKernelGGL(k_num_bm<false>, g, t, (size_t)num_bm_bytes(), s, a);
     return hipGetLastError();

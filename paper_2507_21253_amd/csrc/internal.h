@@ -238,9 +238,13 @@ constexpr int kWinChunksMax = 256;
 // items of a window row whose positions in B are carried from one window to
 // the next (later items are found by binary search in every window)
 constexpr int kWinCurMax = 1024;
-// wavefronts of a workgroup of the bitmap kernels (one unit, or one column
-// chunk of a row, per workgroup)
-constexpr int kBmWaves = 8;
+// wavefronts of a workgroup of the bitmap kernels: symbolic (one unit per
+// workgroup; its bitmap takes most of a compute unit's shared memory, so more
+// wavefronts hide more of the latency of walking the products) and numeric
+// (a row, or a column chunk of one, per workgroup; each wavefront also holds
+// a window of values, so fewer of them fit beside the bitmap)
+constexpr int kSymBmWaves = 16;
+constexpr int kNumBmWaves = 8;
 constexpr int kWinLog2Default = 18;
 __host__ __device__ inline int win_nchunks(int64_t ub, int log2)
 {
