@@ -543,6 +543,14 @@ def test_rcm_hand_example():
     assert oracle.order_rcm(H).tolist() == g["perm"]
 
 
+def test_rcm_hand_example_pseudo_peripheral_start_and_degree_order():
+    # the least-degree vertex is a leaf in the middle: the start moves to an end of the longest path, and
+    # the hub's neighbours are visited by (degree, id), not by id
+    g = json.load(open(os.path.join(GOLDEN, "rcm_hand_example_2.json")))
+    H = _graph(g["n"], g["edges"])
+    assert oracle.order_rcm(H).tolist() == g["perm"]
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_rcm_recovers_a_shuffled_path(seed):
     # a path 0-1-...-(n-1) under a random labelling: RCM lays it out again, bandwidth 1
