@@ -82,6 +82,13 @@ MUTANTS = [
     ("RCM: neighbours visited in id order",
      "for (int64_t i = 0; i < n; ++i) qsort(ga + gp[i], (size_t)deg[i], sizeof(int32_t), cmp_deg_id);",
      ";", 0),
+    ("row counts: repeated columns counted again",
+     "if (!(seen[c >> 6] & bit)) { seen[c >> 6] |= bit; ++cnt; }", "{ seen[c >> 6] |= bit; ++cnt; }", 0),
+    ("row counts: marks not cleared between rows",
+     "for (int64_t r = j->Brp[k]; r < j->Brp[k + 1]; ++r) seen[(uint32_t)j->Bcol[r] >> 6] = 0;", ";", 0),
+    ("row statistics: value sum skips the last entry",
+     "for (int64_t t = 0; t < cnt; ++t) s += w.acc[w.list[t]];",
+     "for (int64_t t = 0; t + 1 < cnt; ++t) s += w.acc[w.list[t]];", 0),
     ("degree order: equal lengths by descending id",
      "for (int64_t i = 0; i < n; ++i) perm[start[maxl - (rp[i + 1] - rp[i])]++] = (int32_t)i;",
      "for (int64_t i = n - 1; i >= 0; --i) perm[start[maxl - (rp[i + 1] - rp[i])]++] = (int32_t)i;", 0),
