@@ -4,9 +4,11 @@ Each case plants one plausible mistake in a copy of ``oracle/oracle.c`` (a
 dropped term, a wrong sign, index or tie order, a transposed layout, the
 algorithm listing's own slip), builds it with gcc into a temporary
 directory, and runs the oracle's pin tests (``tests/test_oracle.py``)
-against that build in a child process.  Every mistake must make some pin
-fail; the unmodified source must pass.  Nothing here touches the GPU
-library.
+against that build in a child process; or in the float64 MLP oracle
+(``oracle/mlp.py``), whose mutated source replaces the module's functions in
+a child process that then runs ``tests/test_oracle_mlp.py``.  Every mistake
+must make some pin fail; the unmodified sources must pass.  Nothing here
+touches the GPU library.
 """
 import os
 import subprocess
@@ -126,4 +128,42 @@ def test_unmodified_oracle_passes_its_pins(tmp_path):
 def test_planted_mistake_fails_a_pin(tmp_path, name, old, new, k):
     rc, out = run_pins(tmp_path, mutate(open(SRC).read(), old, new, k), "mutant")
     # 1: some test failed (a crash of the child counts too: negative status)
+    assert rc == 1 or rc < 0, "%s: no pin failed (status %d)\n%s" % (name, rc, out)
+
+
+MLP_SRC = os.path.join(ROOT, "oracle", "mlp.py")
+
+MLP_MUTANTS = [
+    ("forward: first-layer ReLU missing", "h1 = np.maximum(a1, 0.0)", "h1 = a1"),
+    ("forward: inputs multiplied by the spread", "xn = (np.asarray(X, np.float64) - mu) / sd",
+     "xn = (np.asarray(X, np.float64) - mu) * sd"),
+    ("loss: regression term not weighted", "ce.mean() + lam * np.mean(", "ce.mean() + np.mean("),
+    ("gradient: label not subtracted from the softmax", "dz[np.arange(B), y] -= 1.0", "dz[np.arange(B), y] -= 0.0"),
+    ("gradient: regression factor 2 missing", "dz[:, NCLS] = 2.0 * lam *", "dz[:, NCLS] = lam *"),
+    ("gradient: second layer masked by the first layer's signs", "da2 = dh2 * (a2 > 0)", "da2 = dh2 * (a1 > 0)"),
+    ("gradient: first-layer bias before the ReLU mask", 'g["b1"] = da1.sum(axis=0)', 'g["b1"] = dh1.sum(axis=0)'),
+    ("Adam: no bias correction", "mh = m / (1 - b1 ** step)", "mh = m"),
+    ("Adam: second moment of |g| instead of g squared", "v = b2 * v + (1 - b2) * g * g",
+     "v = b2 * v + (1 - b2) * np.abs(g)"),
+]
+
+
+def run_mlp_pins(source):
+    prog = ("import sys; sys.path.insert(0, %r); import oracle.mlp as m; "
+            "exec(compile(sys.stdin.read(), 'mlp.py', 'exec'), m.__dict__); import pytest; "
+            "sys.exit(pytest.main([%r, '-x', '-q', '-p', 'no:cacheprovider']))"
+            % (ROOT, os.path.join(ROOT, "tests", "test_oracle_mlp.py")))
+    r = subprocess.run([sys.executable, "-c", prog], cwd=ROOT, input=source, capture_output=True, text=True,
+                       timeout=300)
+    return r.returncode, r.stdout[-2000:] + r.stderr[-2000:]
+
+
+def test_unmodified_mlp_oracle_passes_its_pins():
+    rc, out = run_mlp_pins(open(MLP_SRC).read())
+    assert rc == 0, out
+
+
+@pytest.mark.parametrize("name,old,new", MLP_MUTANTS, ids=[m[0] for m in MLP_MUTANTS])
+def test_planted_mlp_mistake_fails_a_pin(name, old, new):
+    rc, out = run_mlp_pins(mutate(open(MLP_SRC).read(), old, new, 0))
     assert rc == 1 or rc < 0, "%s: no pin failed (status %d)\n%s" % (name, rc, out)
