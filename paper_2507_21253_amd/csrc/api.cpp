@@ -623,13 +623,14 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     HCSP_HIP(launch_scan_exclusive(C_row_ptr_d, v.nrows + 1, ws.scan_tmp, s));
     HCSP_HIP(launch_numbin(v.cluster, ba, s));
     HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.bin_hist, kNumBins, ws.num_count, ws.order_num, s));
+    // the numeric bin counts, nnz(C) and the error word in one read-back
+    static_assert(kNumBins + 2 <= HCSP_MAX_BINS, "room for nnz and the error word after the bin counts");
     int64_t ncnt[HCSP_MAX_BINS];
-    int64_t nnz = 0;
-    uint32_t e = 0;
-    HCSP_HIP(hipMemcpyAsync(ncnt, ws.num_count, 8 * kNumBins, hipMemcpyDeviceToHost, s));
-    HCSP_HIP(hipMemcpyAsync(&nnz, C_row_ptr_d + v.nrows, 8, hipMemcpyDeviceToHost, s));
-    HCSP_HIP(hipMemcpyAsync(&e, ws.err, 4, hipMemcpyDeviceToHost, s));
+    HCSP_HIP(launch_gather_words(ws.num_count + kNumBins, GatherWords{{C_row_ptr_d + v.nrows, ws.err}, {8, 4}, 2}, s));
+    HCSP_HIP(hipMemcpyAsync(ncnt, ws.num_count, 8 * (kNumBins + 2), hipMemcpyDeviceToHost, s));
     HCSP_HIP(hipStreamSynchronize(s));
+    const int64_t nnz = ncnt[kNumBins];
+    const uint32_t e = (uint32_t)ncnt[kNumBins + 1];
     if (e & kErrWindows)
         return fail(HCSP_E_CAPACITY, "more (row, chunk) pairs of long rows than the workspace holds (raise "
                                      "opts.win_chunk_log2 for fewer chunks)");
@@ -839,12 +840,16 @@ int hcsp_cluster_output_layout(const hcsp_operand *A, const hcsp_csr *B, const h
     HCSP_HIP(launch_cl_out_counts(ws.ucount, A->cl.cl_row_ptr, v.nunits, cl_col_ptr_d, cl_val_ptr_d, ws.err, s));
     HCSP_HIP(launch_scan_exclusive(cl_col_ptr_d, v.nunits + 1, ws.scan_tmp, s));
     HCSP_HIP(launch_scan_exclusive(cl_val_ptr_d, v.nunits + 1, ws.scan_tmp, s));
-    uint32_t e = 0;
-    HCSP_HIP(hipMemcpyAsync(ncc_h, cl_col_ptr_d + v.nunits, 8, hipMemcpyDeviceToHost, s));
-    HCSP_HIP(hipMemcpyAsync(nslots_h, cl_val_ptr_d + v.nunits, 8, hipMemcpyDeviceToHost, s));
-    HCSP_HIP(hipMemcpyAsync(&e, ws.err, 4, hipMemcpyDeviceToHost, s));
+    // both totals and the error word in one read-back, through spare bin-count slots
+    static_assert(kNumBins + 3 <= HCSP_MAX_BINS, "room for three words after the bin counts");
+    int64_t w[3];
+    HCSP_HIP(launch_gather_words(ws.num_count + kNumBins,
+                                 GatherWords{{cl_col_ptr_d + v.nunits, cl_val_ptr_d + v.nunits, ws.err}, {8, 8, 4}, 3}, s));
+    HCSP_HIP(hipMemcpyAsync(w, ws.num_count + kNumBins, sizeof w, hipMemcpyDeviceToHost, s));
     HCSP_HIP(hipStreamSynchronize(s));
-    if (e) return fail(HCSP_E_UNSUPPORTED, "a cluster's union exceeds shared memory (no CSR_Cluster output)");
+    *ncc_h = w[0];
+    *nslots_h = w[1];
+    if ((uint32_t)w[2]) return fail(HCSP_E_UNSUPPORTED, "a cluster's union exceeds shared memory (no CSR_Cluster output)");
     return HCSP_OK;
 }
 
@@ -1025,10 +1030,12 @@ static int predicted_impl(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     HCSP_HIP(launch_work_pred(ba, s));
     HCSP_HIP(launch_scatter(ws.bin, n, ws.bin_hist, kNumBins, ws.num_count, ws.order_num, s));
     HCSP_HIP(launch_scan_exclusive(pw.pad_off, n + 1, ws.scan_tmp, s));
-    int64_t cnt[HCSP_MAX_BINS], padded = 0;
-    HCSP_HIP(hipMemcpyAsync(cnt, ws.num_count, 8 * kNumBins, hipMemcpyDeviceToHost, s));
-    HCSP_HIP(hipMemcpyAsync(&padded, pw.pad_off + n, 8, hipMemcpyDeviceToHost, s));
+    // the bin counts and the padded total in one read-back
+    int64_t cnt[HCSP_MAX_BINS];
+    HCSP_HIP(launch_gather_words(ws.num_count + kNumBins, GatherWords{{pw.pad_off + n}, {8}, 1}, s));
+    HCSP_HIP(hipMemcpyAsync(cnt, ws.num_count, 8 * (kNumBins + 1), hipMemcpyDeviceToHost, s));
     HCSP_HIP(hipStreamSynchronize(s));
+    const int64_t padded = cnt[kNumBins];
     if (padded > pw.entries)  // per-row capacities summing past what the caller declared
         return fail(HCSP_E_INVALID, "row capacities need " + std::to_string(padded) + " scratch entries, " +
                                         std::to_string(pw.entries) + " declared");

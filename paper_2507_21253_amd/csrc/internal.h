@@ -290,6 +290,15 @@ struct BinArgs {
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+// Up to four device scalars (8- or 4-byte words, the latter zero-extended)
+// gathered into dst[0..n), so that the host reads them back with the bin
+// counts in one copy.
+struct GatherWords {
+    const void *src[4];
+    int32_t bytes[4];
+    int32_t n;
+};
+hipError_t launch_gather_words(int64_t *dst, const GatherWords &g, hipStream_t s);
 hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s);
 hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
 // batches

@@ -32,6 +32,20 @@ hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s) { re
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) { return fill(p, n, v, s); }
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) { return fill(p, n, v, s); }
 
+__global__ void k_gather_words(int64_t *dst, GatherWords g)
+{
+    const int i = (int)threadIdx.x;
+    if (i < g.n)
+        dst[i] = g.bytes[i] == 8 ? *(const int64_t *)g.src[i] : (int64_t) * (const uint32_t *)g.src[i];
+}
+
+hipError_t launch_gather_words(int64_t *dst, const GatherWords &g, hipStream_t s)
+{
+    if (g.n < 1 || g.n > 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather_words, dim3(1), dim3(64), 0, s, dst, g);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ binning
 __device__ __forceinline__ int ceil_log2(int64_t x)
 {
