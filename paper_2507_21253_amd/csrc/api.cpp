@@ -26,8 +26,8 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 static int64_t num_bm_blocks();
 
-size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, bool windows, char *base,
-                        Workspace *ws)
+size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int64_t brows, int dense_slots, bool windows,
+                        char *base, Workspace *ws)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> void * {
@@ -62,6 +62,7 @@ size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_
     ws->win_base = (int64_t *)take(windows ? 8 * (nu + 1) : 0);
     ws->win_cur_slots = windows ? num_bm_blocks() * kNumBmWaves : 0;
     ws->win_cur = (int32_t *)take(4 * 2 * (size_t)kWinCurMax * (size_t)ws->win_cur_slots);
+    ws->b_len = (uint16_t *)take(windows ? 2 * (size_t)std::max<int64_t>(brows, 1) : 0);
     ws->bytes = align_up(off, 256);
     return ws->bytes;
 }
@@ -407,7 +408,7 @@ static size_t layout_batch(int32_t count, int64_t units, int64_t row_ptr_len, in
     b->sym_begin = (int64_t *)take(8 * HCSP_MAX_BINS);
     b->num_begin = (int64_t *)take(8 * HCSP_MAX_BINS);
     off = align_up(off, 256);
-    const size_t rest = layout_workspace(units, row_ptr_len, max_ncols, dense_slots, false, base ? base + off : nullptr, &b->w);
+    const size_t rest = layout_workspace(units, row_ptr_len, max_ncols, 0, dense_slots, false, base ? base + off : nullptr, &b->w);
     return off + rest;
 }
 
@@ -542,7 +543,7 @@ int hcsp_spgemm_workspace(const hcsp_operand *A, const hcsp_csr *B, const hcsp_o
     rc = make_tune(opts, B, false, &tu);
     if (rc) return rc;
     Workspace ws;
-    *bytes = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, nullptr, &ws);
+    *bytes = layout_workspace(v.nunits, v.nrows, B->ncols, B->nrows, tu.dense_slots, true, nullptr, &ws);
     return HCSP_OK;
 }
 
@@ -562,7 +563,7 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, (char *)ws_d, &ws);
+    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, B->nrows, tu.dense_slots, true, (char *)ws_d, &ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     hipStream_t s = (hipStream_t)stream;
     std::memset(info, 0, sizeof *info);
@@ -574,6 +575,8 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
 
     BinArgs ba = bin_args(A, B, ws, tu, v.nunits, C_row_ptr_d);
     ba.active = active;
+    HCSP_HIP(launch_row_len16(B->row_ptr, B->nrows, ws.b_len, s));
+    ba.b_len = ws.b_len;
     HCSP_HIP(launch_work(v.cluster, ba, s));
     HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.bin_hist, kSymBins, ws.sym_count, ws.order_sym, s));
     int64_t cnt[HCSP_MAX_BINS];
@@ -670,7 +673,7 @@ int hcsp_spgemm_numeric(const hcsp_operand *A, const hcsp_csr *B, const hcsp_opt
     if (tu.G != info->lanes || tu.load_pct != info->load_pct || tu.win_log2 != info->win_chunk_log2)
         return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
     Workspace ws;
-    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, (char *)ws_d, &ws);
+    const size_t need = layout_workspace(v.nunits, v.nrows, B->ncols, B->nrows, tu.dense_slots, true, (char *)ws_d, &ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     hipStream_t s = (hipStream_t)stream;
     hcsp_opts z;
@@ -760,7 +763,7 @@ static int numeric_setup(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     if (rc) return rc;
     if (tu->G != info->lanes || tu->load_pct != info->load_pct || tu->win_log2 != info->win_chunk_log2)
         return fail(HCSP_E_INVALID, "opts differ from the symbolic call");
-    const size_t need = layout_workspace(v->nunits, v->nrows, B->ncols, tu->dense_slots, true, (char *)ws_d, ws);
+    const size_t need = layout_workspace(v->nunits, v->nrows, B->ncols, B->nrows, tu->dense_slots, true, (char *)ws_d, ws);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "SpGEMM workspace too small");
     return HCSP_OK;
 }
@@ -962,7 +965,7 @@ static int pred_workspace(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     rc = make_tune(opts, B, false, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, nullptr, &ws);
+    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, B->nrows, tu.dense_slots, true, nullptr, &ws);
     PredWs p;
     *bytes = layout_pred(base, v.nrows, B->nrows, entries, nullptr, &p);
     return HCSP_OK;
@@ -1008,7 +1011,7 @@ static int predicted_impl(const hcsp_csr *A, const hcsp_csr *B, const hcsp_opts 
     rc = make_tune(opts, B, true, &tu);
     if (rc) return rc;
     Workspace ws;
-    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, tu.dense_slots, true, (char *)ws_d, &ws);
+    const size_t base = layout_workspace(v.nunits, v.nrows, B->ncols, B->nrows, tu.dense_slots, true, (char *)ws_d, &ws);
     PredWs pw;
     const size_t need = layout_pred(base, v.nrows, B->nrows, entries, (char *)ws_d, &pw);
     if (!ws_d || ws_bytes < need) return fail(HCSP_E_CAPACITY, "predicted-size workspace too small");

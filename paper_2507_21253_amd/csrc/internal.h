@@ -110,14 +110,18 @@ struct Workspace {
     // the next window)
     int32_t *win_cur;
     int64_t win_cur_slots;
+    // single products: the length of each row of B, saturated at 65535 (a
+    // 2-byte array that the work estimate gathers from instead of pairs of
+    // 8-byte row offsets; it stays in L2)
+    uint16_t *b_len;
     size_t bytes;
 };
 
 // windows: single products, whose units too long for shared memory take the
 // column-window path (chunk counts, no dense accumulators); otherwise
 // (batches) dense_slots dense accumulators
-size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int dense_slots, bool windows, char *base,
-                        Workspace *ws);
+size_t layout_workspace(int64_t nunits, int64_t nrows, int64_t ncols, int64_t brows, int dense_slots, bool windows,
+                        char *base, Workspace *ws);
 
 // ------------------------------------------------------------ batches
 // One product of a batch as the kernels see it (device copy).  Units of all
@@ -267,6 +271,7 @@ struct BinArgs {
     const int32_t *cl_col;
     const int64_t *b_rp;
     const int32_t *b_col;
+    const uint16_t *b_len;  // nullable: B's row lengths, saturated at 65535
     int64_t nunits;
     Workspace ws;
     int64_t *c_rp;
@@ -299,6 +304,8 @@ struct GatherWords {
     int32_t n;
 };
 hipError_t launch_gather_words(int64_t *dst, const GatherWords &g, hipStream_t s);
+// out[k] = min(rp[k+1] - rp[k], 65535) for k < n
+hipError_t launch_row_len16(const int64_t *rp, int64_t n, uint16_t *out, hipStream_t s);
 hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s);
 hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
 // batches

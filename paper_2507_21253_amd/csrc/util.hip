@@ -46,6 +46,20 @@ hipError_t launch_gather_words(int64_t *dst, const GatherWords &g, hipStream_t s
     return hipGetLastError();
 }
 
+__global__ void k_row_len16(const int64_t *rp, int64_t n, uint16_t *out)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = (uint16_t)min<int64_t>(rp[k + 1] - rp[k], 65535);
+}
+
+hipError_t launch_row_len16(const int64_t *rp, int64_t n, uint16_t *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_row_len16, dim3((unsigned)blocks), dim3(256), 0, s, rp, n, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ binning
 __device__ __forceinline__ int ceil_log2(int64_t x)
 {
@@ -80,7 +94,8 @@ __device__ __forceinline__ void chunk_of(int64_t n, int64_t *b, int64_t *e)
 // batch the product holding batch-wide unit g.
 struct WorkView {
     const int64_t *b_rp;
-    const int32_t *col;  // A's columns, or the cluster's union columns
+    const uint16_t *b_len;  // B's row lengths saturated at 65535 (nullable)
+    const int32_t *col;     // A's columns, or the cluster's union columns
     const int32_t *perm;
     int64_t *c_rp;
     int64_t it0, it1, pos0, u;
@@ -93,6 +108,7 @@ __device__ __forceinline__ WorkView work_view(const BinArgs &a, int64_t g)
     WorkView w;
     const int64_t *a_rp = a.a_rp, *cl_row_ptr = a.cl_row_ptr, *cl_col_ptr = a.cl_col_ptr;
     w.b_rp = a.b_rp;
+    w.b_len = BATCH ? nullptr : a.b_len;
     w.col = CL ? a.cl_col : a.a_col;
     w.perm = a.perm;
     w.c_rp = a.c_rp;
@@ -139,16 +155,22 @@ __global__ void __launch_bounds__(256) k_work(BinArgs a)
     for (int64_t u = cb + (threadIdx.x / G); u < ce; u += blockDim.x / G) {
         const WorkView w = work_view<CL, BATCH>(a, u);
         int64_t probes = 0;
+        // a row of B's length, from the 2-byte lengths where they are given and
+        // below the saturation value
+        auto blen = [&](int k) -> int64_t {
+            if (w.b_len) {
+                const int l = w.b_len[k];
+                if (l < 65535) return l;
+            }
+            return w.b_rp[k + 1] - w.b_rp[k];
+        };
         // two items per lane and step, so that both items' loads are in flight together
         int64_t q = w.it0 + g.gl;
         for (; q + G < w.it1; q += 2 * G) {
             const int k0 = w.col[q], k1 = w.col[q + G];
-            probes += (w.b_rp[k0 + 1] - w.b_rp[k0]) + (w.b_rp[k1 + 1] - w.b_rp[k1]);
+            probes += blen(k0) + blen(k1);
         }
-        if (q < w.it1) {
-            const int k = w.col[q];
-            probes += w.b_rp[k + 1] - w.b_rp[k];
-        }
+        if (q < w.it1) probes += blen(w.col[q]);
         probes = gsum64(g, probes);
         const bool on = !a.active || a.active[u];
         if (!on) probes = 0;
