@@ -288,7 +288,9 @@ int hcsp_spgemm_status(const void *ws_d, size_t ws_bytes, void *stream);
  *                             phase did not run
  * Errors: HCSP_E_CAPACITY when the product's workspace
  * (hcsp_spgemm_workspace) exceeds the static array (nothing runs; about
- * 7.5e5 rows for a square CSR A times a B of the same size) or when nnz(C) >
+ * 5.1e5 rows for a square CSR A times a B of the same size on a device of
+ * 256 compute units: 32 MiB of it are the long-row path's chunk counts and
+ * carried positions) or when nnz(C) >
  * capacity (then only C_row_ptr_d and *nnz_h are written); the numeric
  * phase's own errors as hcsp_spgemm_status reports them.  Synchronizes.
  * Every call on one device shares that device's array, which keeps the last
