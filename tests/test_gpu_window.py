@@ -132,6 +132,21 @@ def test_rows_at_the_item_limit_of_whole_row_tasks(log2):
     assert_same(C.to_host(), ref, "clusters")
 
 
+def test_rows_of_b_longer_than_the_two_byte_lengths():
+    # rows of B with 65,535 entries and more: the work estimate's 2-byte row lengths saturate there and it
+    # reads those rows' offsets instead; products over them, with default and with small chunks
+    rng = np.random.default_rng(41)
+    ncols = 300_000
+    brows = [rng.choice(ncols, m, replace=False) for m in (65_534, 65_535, 65_536, 90_000)]
+    brows += [rng.choice(ncols, int(rng.integers(1, 50)), replace=False) for _ in range(20)]
+    B = csr_from_rows(brows, ncols, rng)
+    arows = [[0], [1], [2], [3], [0, 1, 2, 3], [3, 7, 9], [5, 6], [], [1, 23]]
+    A = csr_from_rows([np.array(r, np.int64) for r in arows], len(brows), rng)
+    ref = oracle.spgemm(A, B)
+    for o in (None, hc.opts(win_chunk_log2=12)):
+        assert_same(product(A, B, o), ref, str(o))
+
+
 def test_rows_counted_whole_then_windowed():
     # symbolic tables large enough for every row, numeric tables too small:
     # the numeric phase takes each row as one chunk over its column range
