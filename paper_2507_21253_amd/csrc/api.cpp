@@ -101,9 +101,11 @@ static int64_t lds_limit()
 }
 
 // Side streams for the bins of a phase.  The bin with the most work runs on
-// the caller's stream, the others on side streams forked from it and joined
-// back before the phase's next step, so that the few long units of a small
-// bin overlap the large bin instead of running alone after it.  Created once
+// the caller's stream, launched first (its start is the phase's critical
+// path; queueing the other launches first delayed it by their host time),
+// the others on side streams forked from it and joined back before the
+// phase's next step, so that the few long units of a small bin overlap the
+// large bin instead of running alone after it.  Created once
 // per device (default priority, non-blocking); where they cannot be created
 // every bin runs on the caller's stream.  The lock keeps one call's fork and
 // join events from being re-recorded by another host thread in between.
@@ -134,7 +136,7 @@ static SideStreams *side_streams()
 }
 
 // Runs launch(b, stream) for every bin b with work[b] > 0: the largest on s
-// (last), the others on the side streams (first).  The side streams are
+// (first), the others on the side streams.  The side streams are
 // joined back into s also when a launch fails; returns the first error.
 template <class F>
 static int run_bins(hipStream_t s, const std::vector<int64_t> &work, bool one_stream, F launch)
@@ -150,6 +152,7 @@ static int run_bins(hipStream_t s, const std::vector<int64_t> &work, bool one_st
     if (x && hipEventRecord(x->fork, s) != hipSuccess) x = nullptr;
     bool used[kSide] = {false, false, false};
     int k = 0, rc = HCSP_OK;
+    if (big >= 0) rc = launch(big, s);
     for (int b = 0; b < (int)work.size() && rc == HCSP_OK; ++b) {
         if (work[b] <= 0 || b == big) continue;
         hipStream_t t = s;
@@ -166,7 +169,6 @@ static int run_bins(hipStream_t s, const std::vector<int64_t> &work, bool one_st
         }
         rc = launch(b, t);
     }
-    if (rc == HCSP_OK && big >= 0) rc = launch(big, s);
     for (int i = 0; i < kSide; ++i) {
         if (!used[i]) continue;
         if ((hipEventRecord(x->join[i], x->st[i]) != hipSuccess || hipStreamWaitEvent(s, x->join[i], 0) != hipSuccess) &&
