@@ -570,14 +570,13 @@ static int symbolic_impl(const hcsp_operand *A, const hcsp_csr *B, const hcsp_op
     hipStream_t s = (hipStream_t)stream;
     std::memset(info, 0, sizeof *info);
 
-    HCSP_HIP(launch_fill_i64(ws.sym_count, HCSP_MAX_BINS, 0, s));
-    HCSP_HIP(launch_fill_i64(ws.num_count, HCSP_MAX_BINS, 0, s));
-    HCSP_HIP(launch_fill_u32(ws.err, 1, 0u, s));
-    HCSP_HIP(launch_fill_i64(C_row_ptr_d + v.nrows, 1, 0, s));
+    // one launch: the bin counters, the error word and C's last row offset
+    // cleared, and B's 2-byte row lengths for the work estimate
+    HCSP_HIP(launch_sym_start(B->row_ptr, B->nrows, ws.b_len, ws.sym_count, ws.num_count, HCSP_MAX_BINS, ws.err,
+                              C_row_ptr_d + v.nrows, s));
 
     BinArgs ba = bin_args(A, B, ws, tu, v.nunits, C_row_ptr_d);
     ba.active = active;
-    HCSP_HIP(launch_row_len16(B->row_ptr, B->nrows, ws.b_len, s));
     ba.b_len = ws.b_len;
     HCSP_HIP(launch_work(v.cluster, ba, s));
     HCSP_HIP(launch_scatter(ws.bin, v.nunits, ws.bin_hist, kSymBins, ws.sym_count, ws.order_sym, s));

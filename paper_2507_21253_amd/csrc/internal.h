@@ -304,8 +304,11 @@ struct GatherWords {
     int32_t n;
 };
 hipError_t launch_gather_words(int64_t *dst, const GatherWords &g, hipStream_t s);
-// out[k] = min(rp[k+1] - rp[k], 65535) for k < n
-hipError_t launch_row_len16(const int64_t *rp, int64_t n, uint16_t *out, hipStream_t s);
+// The symbolic phase's first launch: out[k] = min(rp[k+1] - rp[k], 65535)
+// for k < n (B's row lengths), and zeros into the first nz words of z0 and
+// of z1, into *err and into *z2.
+hipError_t launch_sym_start(const int64_t *rp, int64_t n, uint16_t *out, int64_t *z0, int64_t *z1, int nz,
+                            uint32_t *err, int64_t *z2, hipStream_t s);
 hipError_t launch_work(bool cluster, const BinArgs &a, hipStream_t s);
 hipError_t launch_numbin(bool cluster, const BinArgs &a, hipStream_t s);
 // batches

@@ -46,17 +46,29 @@ hipError_t launch_gather_words(int64_t *dst, const GatherWords &g, hipStream_t s
     return hipGetLastError();
 }
 
-__global__ void k_row_len16(const int64_t *rp, int64_t n, uint16_t *out)
+__global__ void k_sym_start(const int64_t *rp, int64_t n, uint16_t *out, int64_t *z0, int64_t *z1, int nz,
+                            uint32_t *err, int64_t *z2)
 {
+    if (blockIdx.x == 0) {
+        for (int i = (int)threadIdx.x; i < nz; i += blockDim.x) {
+            z0[i] = 0;
+            z1[i] = 0;
+        }
+        if (threadIdx.x == 0) {
+            *err = 0u;
+            *z2 = 0;
+        }
+    }
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
         out[k] = (uint16_t)min<int64_t>(rp[k + 1] - rp[k], 65535);
 }
 
-hipError_t launch_row_len16(const int64_t *rp, int64_t n, uint16_t *out, hipStream_t s)
+hipError_t launch_sym_start(const int64_t *rp, int64_t n, uint16_t *out, int64_t *z0, int64_t *z1, int nz,
+                            uint32_t *err, int64_t *z2, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_row_len16, dim3((unsigned)blocks), dim3(256), 0, s, rp, n, out);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_sym_start, dim3((unsigned)blocks), dim3(256), 0, s, rp, std::max<int64_t>(n, 0), out, z0,
+                       z1, nz, err, z2);
     return hipGetLastError();
 }
 
