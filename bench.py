@@ -705,6 +705,9 @@ def main():
                           "plan_gpu_candidates_s": None if t_plan_gpu is None else round(t_plan_gpu, 3),
                           "cluster_build_s": round(t_build, 4),
                           "in_spgemms": round((t_reorder + t_plan + t_build) / (wall_cl * 1e-3), 1),
+                          # the same plan (asserted equal) with the candidate search on the GPU
+                          "in_spgemms_gpu_candidates": None if t_plan_gpu is None else
+                          round((t_reorder + t_plan_gpu + t_build) / (wall_cl * 1e-3), 1),
                           "nclusters": plan.nclusters, "ncc": Dc.ncc, "nslots": Dc.nslots,
                           "csr_cluster_over_csr_bytes": round(bytes_Acl / bytes_A, 3)},
         "roofline": {"bound": "hbm", "kernel": "k_num (numeric phase launches of one product)",
