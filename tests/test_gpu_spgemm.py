@@ -178,6 +178,11 @@ def test_empty_and_degenerate():
     one = synth.from_dense(np.array([[2.0]]))
     C = gpu_product(to_dev(one), to_dev(one))
     assert C.col.tolist() == [0] and C.val.tolist() == [4.0]
+    # inner dimension zero: A has no columns, B no rows
+    A0 = synth.HostCSR(np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0), 5, 0)
+    B0 = synth.HostCSR(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0), 0, 9)
+    C = gpu_product(to_dev(A0), to_dev(B0))
+    assert C.rp.tolist() == [0] * 6 and len(C.col) == 0
 
 
 def test_panels_with_out_base():
