@@ -971,8 +971,6 @@ __device__ __forceinline__ void num_unit(const SpArgs &a, const int u, unsigned 
 constexpr int kGmSym = 16 * 64 + 8 * kRoundPasses;     // items + start bits
 constexpr int kGmNumCl = kGmSym + 8 * 16 * 64;         // + staged cluster values
 
-int64_t gm_wave_bytes(bool cl, bool num) { return num && cl ? kGmNumCl : kGmSym; }
-
 template <bool BATCH>
 __device__ __forceinline__ int gm_unit(SpArgs &a, const SpArgs &a0, int64_t i)
 {
